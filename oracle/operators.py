@@ -1,0 +1,55 @@
+"""Gated operators A_i = A D_i and A_i^* = D_i^* A^* (Section II-A; Algorithm 1)."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import projector, warp
+
+
+class GatedOperators:
+    """The N gate operators of one problem.
+
+    motion: "identity", ("rigid", params [N][3]) or ("field", fields [N][2][n][n]).
+    """
+
+    def __init__(self, n: int, n_angles: int, n_det: int, kind: str, params=None, n_gates: int | None = None):
+        self.n, self.n_angles, self.n_det = n, n_angles, n_det
+        self.kind = kind
+        if kind == "identity":
+            self.n_gates = int(n_gates)
+            self.params = None
+            self.pos = [None] * self.n_gates
+        elif kind == "rigid":
+            self.params = np.asarray(params, dtype=np.float64)
+            self.n_gates = self.params.shape[0]
+            self.pos = [warp.rigid_positions(n, *self.params[i]) for i in range(self.n_gates)]
+        elif kind == "field":
+            self.params = np.asarray(params, dtype=np.float64)
+            self.n_gates = self.params.shape[0]
+            self.pos = [warp.field_positions(self.params[i]) for i in range(self.n_gates)]
+        else:
+            raise ValueError(kind)
+
+    def D(self, i, x):
+        if self.pos[i] is None:
+            return np.asarray(x, dtype=np.float64).copy()
+        return warp.warp(x, *self.pos[i])
+
+    def Dt(self, i, b):
+        if self.pos[i] is None:
+            return np.asarray(b, dtype=np.float64).copy()
+        return warp.warp_adjoint(b, *self.pos[i])
+
+    def project(self, x):
+        return projector.forward(x, self.n_angles, self.n_det)
+
+    def backproject(self, y):
+        return projector.adjoint(y, self.n)
+
+    def A(self, i, x):
+        """A_i x = A D_i x."""
+        return self.project(self.D(i, x))
+
+    def At(self, i, y):
+        """A_i^* y = D_i^T A^T y."""
+        return self.Dt(i, self.backproject(y))
