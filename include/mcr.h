@@ -1,0 +1,211 @@
+/*
+ * mcr.h - motion-compensated SPDHG / PDHG reconstruction on AMD Instinct
+ * MI355X (gfx950). C ABI of libmcr.so.
+ *
+ * Problem (Section II-A of Delplancke, Thielemans, Ehrhardt, "Accelerated
+ * Convergent Motion Compensated Image Reconstruction"): gated data
+ * d_i = A_i x + noise with A_i = A D_i, where D_i: X -> X is the displacement
+ * operator of gate i and A: X -> Y the ray transform; the reconstruction
+ * minimises alpha |x|^2 + sum_i |A_i x - d_i|^2 / N with Algorithm 1 (SPDHG,
+ * and PDHG as its special case p_i = 1, every gate every iteration).
+ *
+ * Discretisation used by every entry point (the paper names the operators,
+ * not their discretisation):
+ *   image   x: [n][n] row-major, pixel (r, c) centred at
+ *              (c - (n-1)/2, r - (n-1)/2) in unit pixels;
+ *   sinogram : [n_angles][n_det] row-major (angle-major, detector fastest),
+ *              angle k at k*pi/n_angles, bin j centred at j - (n_det-1)/2;
+ *   A        : Joseph ray transform - each ray steps along image rows when
+ *              4k <= n_angles or 4k >= 3*n_angles, along columns otherwise,
+ *              interpolating linearly between the two nearest pixels of each
+ *              line (zero outside the image) and weighting the line sum by
+ *              1/|cos| (rows) or 1/|sin| (columns);
+ *   D_i      : bilinear pull-back (D x)(p) = x~(phi_i(p)), zero outside the
+ *              image; rigid phi(p) = R(phi)(p - c) + c + t about the image
+ *              centre c, or phi(p) = p + u(p) for a displacement field u;
+ *   A^T, D^T : the exact transposes of the same weights (gather kernels, no
+ *              atomics, deterministic).
+ *
+ * Conventions common to every call:
+ *   - Array arguments typed void* / const void* are DEVICE pointers to
+ *     contiguous arrays of the handle's dtype (float for MCR_F32, double for
+ *     MCR_F64) unless stated otherwise. They stay owned by the caller; the
+ *     library never frees them and never keeps them after the call returns.
+ *   - Arrays of pointers (mcr_state.y, d) and arrays of per-gate scalars
+ *     (sigma, p, gate_seq) are HOST arrays.
+ *   - All work is queued on the handle's HIP stream and is asynchronous,
+ *     except the calls that return a host scalar (norms, objective, gap),
+ *     which synchronise the stream before returning.
+ *   - Every argument is validated before any device work is queued; a call
+ *     that returns a status other than MCR_OK has queued nothing (except
+ *     MCR_ERR_HIP, which reports a failure of the HIP runtime itself).
+ *     mcr_last_error() then returns a message for the calling thread.
+ *   - A handle must not be used from two host threads at once.
+ */
+#ifndef MCR_H
+#define MCR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MCR_OK = 0,
+  MCR_ERR_ARG = 1,        /* invalid argument (size, index, null pointer, step size, ...) */
+  MCR_ERR_HIP = 2,        /* the HIP runtime reported an error                            */
+  MCR_ERR_NOMEM = 3,      /* a device or pinned host allocation failed                    */
+  MCR_ERR_NONFINITE = 4,  /* a scalar result is NaN or infinite                           */
+  MCR_ERR_STATE = 5       /* the handle cannot do this (e.g. motion too irregular)        */
+} mcr_status;
+
+typedef enum { MCR_F32 = 0, MCR_F64 = 1 } mcr_dtype;
+
+typedef enum {
+  MCR_MOTION_IDENTITY = 0,  /* D_i = I                                                     */
+  MCR_MOTION_RIGID = 1,     /* rigid[0] = rotation phi [rad], rigid[1..2] = (t_x, t_y) [px] */
+  MCR_MOTION_FIELD = 2      /* field: device float [2][n][n], plane 0 = u_x (along columns),
+                               plane 1 = u_y (along rows), in pixels                         */
+} mcr_motion_kind;
+
+typedef struct {
+  int32_t n;         /* image is n x n, 1 <= n <= 4096                         */
+  int32_t n_angles;  /* angles k*pi/n_angles, k = 0..n_angles-1, 1..16384     */
+  int32_t n_det;     /* unit-spaced centred detector bins, 1..16384           */
+} mcr_geometry;
+
+typedef struct {
+  int32_t kind;        /* mcr_motion_kind                                        */
+  double rigid[3];     /* MCR_MOTION_RIGID: (phi, t_x, t_y); ignored otherwise    */
+  const float* field;  /* MCR_MOTION_FIELD: device [2][n][n] float32; the handle
+                          copies it, so it may be freed after the call            */
+} mcr_motion;
+
+typedef struct mcr_handle mcr_handle;
+
+/* State of Algorithm 1 (its initialisation is x = z = z-bar = 0, y = 0). All
+ * device arrays of the handle's dtype: x, z, zbar [n][n]; y is a HOST array
+ * of N device pointers, y[i] of shape [n_angles][n_det]. Updated in place.   */
+typedef struct {
+  void* x;
+  void* z;
+  void* zbar;
+  void* const* y;
+} mcr_state;
+
+/* ---------------------------------------------------------------------------
+ * Handle: geometry, the N gates' motion, device workspaces, a HIP stream.
+ * `stream` is a hipStream_t (NULL = the null stream). The handle copies the
+ * motion (fields included). dtype selects the precision of the operators and
+ * of the state; the scalar diagnostics (norms, objective, gap) are always
+ * computed in FP64 on the device. Fails with MCR_ERR_STATE if a displacement
+ * field folds so strongly that the transposed warp's gather window (at most
+ * 7 x 7 pixels around the inverse image of each pixel) cannot cover it.
+ * ------------------------------------------------------------------------- */
+mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motion* motion,
+                      mcr_dtype dtype, void* stream, mcr_handle** out);
+mcr_status mcr_destroy(mcr_handle* h);
+mcr_status mcr_set_stream(mcr_handle* h, void* stream);
+/* Replace the motion of one gate (synchronises the handle's stream first). */
+mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion);
+/* Sizes and settings of a handle (any pointer may be NULL). */
+mcr_status mcr_get_info(const mcr_handle* h, mcr_geometry* geom, int32_t* n_gates,
+                        mcr_dtype* dtype, int32_t* window_radius);
+
+/* ---------------------------------------------------------------------------
+ * Operators (Section II-A; A_i^* as used in Algorithm 1 step (iii)).
+ * x, img: [n][n]; sino: [n_angles][n_det]; gate in [0, N).
+ * ------------------------------------------------------------------------- */
+mcr_status mcr_warp(mcr_handle* h, int32_t gate, const void* x, void* img);              /* D_i x     */
+mcr_status mcr_warp_adjoint(mcr_handle* h, int32_t gate, const void* b, void* img);      /* D_i^T b   */
+mcr_status mcr_project(mcr_handle* h, const void* x, void* sino);                        /* A x       */
+mcr_status mcr_backproject(mcr_handle* h, const void* sino, void* img);                  /* A^T y     */
+mcr_status mcr_apply_Ai(mcr_handle* h, int32_t gate, const void* x, void* sino);         /* A D_i x   */
+mcr_status mcr_apply_Ai_adjoint(mcr_handle* h, int32_t gate, const void* sino, void* img); /* D_i^T A^T y */
+
+/* ---------------------------------------------------------------------------
+ * Algorithm 1. Each iteration with drawn gate set S:
+ *   (i)   x <- (x - tau z-bar) / (1 + 2 tau alpha)                 (prox of tau g)
+ *   (ii)  y_i <- (y_i + sigma_i (A_i x - d_i)) / (1 + sigma_i N/2), i in S (prox of sigma_i f_i^*)
+ *   (iii) z <- z + sum_{i in S} A_i^*(y_i' - y_i);
+ *         z-bar <- z + sum_{i in S} (theta / p_i) A_i^*(y_i' - y_i)   (z after the update)
+ * with g(x) = alpha |x|^2 and f_i(u) = |u - d_i|^2 / N.
+ * d: host array of N device pointers to the gated data d_i [n_angles][n_det].
+ * sigma, p: host arrays of N doubles, sigma_i > 0, p_i in (0, 1]; tau > 0;
+ * alpha > 0; theta >= 0; all finite.
+ * ------------------------------------------------------------------------- */
+/* SPDHG with serial sampling: n_iter iterations, iteration k updating the one
+ * gate gate_seq[k] (host int32 array, entries in [0, N)).                    */
+mcr_status mcr_spdhg_iterate(mcr_handle* h, const mcr_state* st, const void* const* d,
+                             double alpha, const double* sigma, double tau, double theta,
+                             const double* p, const int32_t* gate_seq, int32_t n_iter);
+/* One SPDHG epoch: N iterations (the paper's epoch, Section II-A).            */
+mcr_status mcr_spdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const* d,
+                           double alpha, const double* sigma, double tau, double theta,
+                           const double* p, const int32_t* gate_seq);
+/* One PDHG epoch = one iteration with S = all gates and p_i = 1. It runs the
+ * same kernels as SPDHG, so PDHG with N = 1 equals SPDHG with N = 1 bit for bit. */
+mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const* d,
+                          double alpha, const double* sigma, double tau, double theta);
+
+/* ---------------------------------------------------------------------------
+ * FP64 diagnostics (Theorem 1 and the model of Section II-A), computed on the
+ * device in double precision whatever the handle's dtype; they synchronise.
+ * ------------------------------------------------------------------------- */
+/* |A_i|^2 (gate >= 0) or |(A_1; ...; A_N)|^2 = lambda_max(sum_i A_i^* A_i)
+ * (gate = -1) by power iteration from the device FP64 image v0 [n][n] (not
+ * modified), stopping when the Rayleigh quotient changes by at most rtol
+ * relative, or after max_iter iterations. *iters (may be NULL) receives the
+ * iteration count.                                                            */
+mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int32_t max_iter,
+                             double rtol, double* out, int32_t* iters);
+/* O(x) = alpha |x|^2 + sum_i |A_i x - d_i|^2 / N.                              */
+mcr_status mcr_objective(mcr_handle* h, const void* x, const void* const* d, double alpha,
+                         double* out);
+/* O(x) + |z|^2 / (4 alpha) + sum_i (<y_i, d_i> + (N/4) |y_i|^2) with
+ * z = sum_i A_i^* y_i recomputed from y (>= 0; zero exactly at the saddle point). */
+mcr_status mcr_duality_gap(mcr_handle* h, const mcr_state* st, const void* const* d,
+                           double alpha, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Step sizes (host only, no device work). Theorem 1 quotes the rates of
+ * "well-chosen" step sizes; these attain them:
+ *   algo 0 (SPDHG, p_i = 1/N): norms_sq = |A_i|^2 for i = 0..N-1;
+ *     s_i = sqrt(1 + |A_i|^2 / (alpha N)), s = max s_i, rho = 1 - 2/(N (1 + s)),
+ *     sigma_i = 2 / (N (s_i - 1)), tau = 1 / (2 N alpha rho (1 + s)), theta = rho,
+ *     per-epoch rate rho^N = l(kappa^SPDHG, N).
+ *   algo 1 (PDHG): norms_sq[0] = |(A_1; ...; A_N)|^2; s = sqrt(1 + norms_sq[0] / (alpha N)),
+ *     sigma_i = 2 / (N (s - 1)), tau = 1 / (2 alpha (s - 1)), theta = (s - 1)/(s + 1),
+ *     per-epoch rate theta = l(kappa^PDHG, 1).
+ * sigma: host array of N doubles (out). Any of tau, theta, rate may be NULL.  */
+mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq, double alpha,
+                          double* sigma, double* tau, double* theta, double* rate_per_epoch);
+
+/* ---------------------------------------------------------------------------
+ * Kernel timing (diagnostic). While enabled, every kernel launch of the handle
+ * is bracketed by HIP events on the handle's stream. mcr_profile_read waits
+ * for the stream, then returns per kernel class the summed duration [ms] and
+ * the launch count, and clears the records. total_ms and launches are host
+ * arrays of MCR_KERNEL_CLASSES entries (either may be NULL).
+ * ------------------------------------------------------------------------- */
+typedef enum {
+  MCR_KERNEL_WARP = 0,         /* D_i (a1)                                   */
+  MCR_KERNEL_PROJECT = 1,      /* A, fused with the dual step (a2, a3)       */
+  MCR_KERNEL_BACKPROJECT = 2,  /* A^T (a4)                                   */
+  MCR_KERNEL_TWARP = 3,        /* D_i^T, fused with the z / z-bar / x update (a5, a6) */
+  MCR_KERNEL_XSTEP = 4,        /* step (i) alone                             */
+  MCR_KERNEL_OTHER = 5,        /* reductions, copies                         */
+  MCR_KERNEL_CLASSES = 6
+} mcr_kernel_class;
+mcr_status mcr_profile_enable(mcr_handle* h, int32_t enable);
+mcr_status mcr_profile_read(mcr_handle* h, double* total_ms, int64_t* launches);
+
+/* Message describing the last non-OK status returned on the calling thread. */
+const char* mcr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCR_H */

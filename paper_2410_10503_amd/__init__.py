@@ -1,0 +1,274 @@
+"""Motion-compensated SPDHG / PDHG reconstruction on AMD Instinct MI355X.
+
+Python binding of libmcr (include/mcr.h). Every step of the reconstruction
+runs in the library's HIP kernels; this module only checks and marshals
+arguments (torch tensors on the HIP device provide memory and the stream).
+
+    h = Handle(n, n_angles, n_det, motion=[("rigid", (phi, tx, ty)), ...])
+    s = h.apply_Ai(gate, x)             # A D_i x
+    b = h.apply_Ai_adjoint(gate, s)     # D_i^T A^T s
+    st = h.zero_state()
+    h.spdhg_epoch(st, d, alpha, sigma, tau, theta, p, gate_seq)   # Algorithm 1
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Sequence
+
+import torch
+
+from . import _lib
+from ._lib import McrError  # noqa: F401
+
+__all__ = ["Handle", "ReconState", "McrError", "step_sizes"]
+
+_DTYPES = {torch.float32: _lib.MCR_F32, torch.float64: _lib.MCR_F64}
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dbl_array(vals):
+    vals = [float(v) for v in vals]
+    return (ctypes.c_double * len(vals))(*vals)
+
+
+def step_sizes(algo: str, norms_sq: Sequence[float], alpha: float, n_gates: int):
+    """Step sizes attaining Theorem 1's rates (host arithmetic in the library).
+
+    algo "spdhg": norms_sq = |A_i|^2 per gate; "pdhg": norms_sq = [|(A_1; ...; A_N)|^2].
+    Returns (sigma list, tau, theta, rate per epoch)."""
+    lib = _lib.load()
+    a = {"spdhg": 0, "pdhg": 1}[algo]
+    sig = (ctypes.c_double * n_gates)()
+    tau, theta, rate = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _lib.check(lib.mcr_step_sizes(a, n_gates, _dbl_array(norms_sq), float(alpha), sig,
+                                  ctypes.byref(tau), ctypes.byref(theta), ctypes.byref(rate)))
+    return list(sig), tau.value, theta.value, rate.value
+
+
+class ReconState:
+    """(x, y_1..y_N, z, z-bar) of Algorithm 1 as device tensors."""
+
+    def __init__(self, x, y, z, zbar):
+        self.x, self.y, self.z, self.zbar = x, list(y), z, zbar
+
+    def clone(self):
+        return ReconState(self.x.clone(), [v.clone() for v in self.y], self.z.clone(), self.zbar.clone())
+
+    def _c(self):
+        ys = (ctypes.c_void_p * len(self.y))(*[v.data_ptr() for v in self.y])
+        st = _lib.State(self.x.data_ptr(), self.z.data_ptr(), self.zbar.data_ptr(), ys)
+        st._keep = ys
+        return st
+
+
+class Handle:
+    """One reconstruction problem: geometry, the gates' motion, workspaces.
+
+    motion: sequence of "identity", ("rigid", (phi_rad, t_x, t_y)) or
+    ("field", tensor [2][n][n] float32 on the device).
+    """
+
+    def __init__(self, n: int, n_angles: int, n_det: int, motion, dtype=torch.float32, device="cuda"):
+        self._lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the library runs on the HIP device only")
+        if dtype not in _DTYPES:
+            raise ValueError(f"dtype must be float32 or float64, not {dtype}")
+        self.n, self.n_angles, self.n_det = int(n), int(n_angles), int(n_det)
+        self.dtype = dtype
+        self.n_gates = len(motion)
+        self._h = ctypes.c_void_p()
+        arr = (_lib.Motion * self.n_gates)()
+        keep = []
+        for i, m in enumerate(motion):
+            arr[i] = self._motion(m, keep)
+        geo = _lib.Geometry(self.n, self.n_angles, self.n_det)
+        self._stream = _stream_ptr(self.device)
+        _lib.check(self._lib.mcr_create(ctypes.byref(geo), self.n_gates, arr, _DTYPES[dtype],
+                                        ctypes.c_void_p(self._stream), ctypes.byref(self._h)))
+
+    def _motion(self, m, keep):
+        if m == "identity" or m is None:
+            return _lib.Motion(_lib.MOTION_IDENTITY, (ctypes.c_double * 3)(0, 0, 0), None)
+        kind, val = m
+        if kind == "rigid":
+            return _lib.Motion(_lib.MOTION_RIGID, (ctypes.c_double * 3)(*[float(v) for v in val]), None)
+        if kind == "field":
+            f = val
+            if not (isinstance(f, torch.Tensor) and f.dtype == torch.float32 and f.is_cuda
+                    and tuple(f.shape) == (2, self.n, self.n)):
+                raise ValueError("a field must be a float32 device tensor of shape [2][n][n]")
+            f = f.contiguous()
+            keep.append(f)
+            return _lib.Motion(_lib.MOTION_FIELD, (ctypes.c_double * 3)(0, 0, 0), f.data_ptr())
+        raise ValueError(f"unknown motion {kind!r}")
+
+    def close(self):
+        if self._h:
+            self._lib.mcr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- argument marshalling ------------------------------------------------
+    def _sync_stream(self):
+        s = _stream_ptr(self.device)
+        if s != self._stream:
+            _lib.check(self._lib.mcr_set_stream(self._h, ctypes.c_void_p(s)))
+            self._stream = s
+
+    def _check(self, t, shape, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda):
+            raise ValueError(f"{name} must be a tensor on the HIP device")
+        if t.dtype != self.dtype or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape {shape}")
+        return t.data_ptr()
+
+    def _img(self, t, name="image"):
+        return self._check(t, (self.n, self.n), name)
+
+    def _sino(self, t, name="sinogram"):
+        return self._check(t, (self.n_angles, self.n_det), name)
+
+    def new_image(self):
+        return torch.empty((self.n, self.n), dtype=self.dtype, device=self.device)
+
+    def new_sino(self):
+        return torch.empty((self.n_angles, self.n_det), dtype=self.dtype, device=self.device)
+
+    def zero_state(self) -> ReconState:
+        z = lambda shape: torch.zeros(shape, dtype=self.dtype, device=self.device)  # noqa: E731
+        return ReconState(z((self.n, self.n)), [z((self.n_angles, self.n_det)) for _ in range(self.n_gates)],
+                          z((self.n, self.n)), z((self.n, self.n)))
+
+    def _ptrs(self, ts, kind):
+        if len(ts) != self.n_gates:
+            raise ValueError(f"need {self.n_gates} {kind} arrays, got {len(ts)}")
+        vals = [self._sino(t, kind) for t in ts]
+        return (ctypes.c_void_p * len(vals))(*vals)
+
+    # -- operators -----------------------------------------------------------
+    def set_motion(self, gate: int, motion):
+        keep = []
+        m = self._motion(motion, keep)
+        _lib.check(self._lib.mcr_set_motion(self._h, int(gate), ctypes.byref(m)))
+
+    def warp(self, gate, x, out=None):
+        self._sync_stream()
+        out = self.new_image() if out is None else out
+        _lib.check(self._lib.mcr_warp(self._h, int(gate), self._img(x, "x"), self._img(out, "out")))
+        return out
+
+    def warp_adjoint(self, gate, b, out=None):
+        self._sync_stream()
+        out = self.new_image() if out is None else out
+        _lib.check(self._lib.mcr_warp_adjoint(self._h, int(gate), self._img(b, "b"), self._img(out, "out")))
+        return out
+
+    def project(self, x, out=None):
+        self._sync_stream()
+        out = self.new_sino() if out is None else out
+        _lib.check(self._lib.mcr_project(self._h, self._img(x, "x"), self._sino(out, "out")))
+        return out
+
+    def backproject(self, s, out=None):
+        self._sync_stream()
+        out = self.new_image() if out is None else out
+        _lib.check(self._lib.mcr_backproject(self._h, self._sino(s, "s"), self._img(out, "out")))
+        return out
+
+    def apply_Ai(self, gate, x, out=None):
+        self._sync_stream()
+        out = self.new_sino() if out is None else out
+        _lib.check(self._lib.mcr_apply_Ai(self._h, int(gate), self._img(x, "x"), self._sino(out, "out")))
+        return out
+
+    def apply_Ai_adjoint(self, gate, s, out=None):
+        self._sync_stream()
+        out = self.new_image() if out is None else out
+        _lib.check(self._lib.mcr_apply_Ai_adjoint(self._h, int(gate), self._sino(s, "s"), self._img(out, "out")))
+        return out
+
+    # -- Algorithm 1 ---------------------------------------------------------
+    def _state(self, st: ReconState):
+        self._img(st.x, "x")
+        self._img(st.z, "z")
+        self._img(st.zbar, "zbar")
+        self._ptrs(st.y, "y")
+        return st._c()
+
+    def spdhg_iterate(self, st: ReconState, d, alpha, sigma, tau, theta, p, gate_seq):
+        self._sync_stream()
+        seq = [int(g) for g in gate_seq]
+        c_seq = (ctypes.c_int32 * max(1, len(seq)))(*seq)
+        _lib.check(self._lib.mcr_spdhg_iterate(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
+                                               float(alpha), _dbl_array(sigma), float(tau), float(theta),
+                                               _dbl_array(p), c_seq, len(seq)))
+
+    def spdhg_epoch(self, st: ReconState, d, alpha, sigma, tau, theta, p, gate_seq):
+        self._sync_stream()
+        seq = [int(g) for g in gate_seq]
+        if len(seq) != self.n_gates:
+            raise ValueError(f"an epoch has {self.n_gates} iterations, got {len(seq)} gates")
+        c_seq = (ctypes.c_int32 * len(seq))(*seq)
+        _lib.check(self._lib.mcr_spdhg_epoch(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
+                                             float(alpha), _dbl_array(sigma), float(tau), float(theta),
+                                             _dbl_array(p), c_seq))
+
+    def pdhg_epoch(self, st: ReconState, d, alpha, sigma, tau, theta):
+        self._sync_stream()
+        _lib.check(self._lib.mcr_pdhg_epoch(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
+                                            float(alpha), _dbl_array(sigma), float(tau), float(theta)))
+
+    # -- FP64 diagnostics ----------------------------------------------------
+    def power_norm_sq(self, gate: int, v0, max_iter: int = 500, rtol: float = 1e-12):
+        """|A_gate|^2 (gate >= 0) or the stacked |(A_1; ...; A_N)|^2 (gate = -1)."""
+        self._sync_stream()
+        if not (v0.dtype == torch.float64 and v0.is_cuda and tuple(v0.shape) == (self.n, self.n)
+                and v0.is_contiguous()):
+            raise ValueError("v0 must be a contiguous float64 device tensor of shape (n, n)")
+        out, it = ctypes.c_double(), ctypes.c_int32()
+        _lib.check(self._lib.mcr_power_norm_sq(self._h, int(gate), v0.data_ptr(), int(max_iter), float(rtol),
+                                               ctypes.byref(out), ctypes.byref(it)))
+        return out.value, it.value
+
+    def objective(self, x, d, alpha) -> float:
+        self._sync_stream()
+        out = ctypes.c_double()
+        _lib.check(self._lib.mcr_objective(self._h, self._img(x, "x"), self._ptrs(d, "d"), float(alpha),
+                                           ctypes.byref(out)))
+        return out.value
+
+    def duality_gap(self, st: ReconState, d, alpha) -> float:
+        self._sync_stream()
+        out = ctypes.c_double()
+        _lib.check(self._lib.mcr_duality_gap(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
+                                             float(alpha), ctypes.byref(out)))
+        return out.value
+
+    def profile(self, enable: bool = True):
+        """Bracket every kernel launch with HIP events (see profile_read)."""
+        _lib.check(self._lib.mcr_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel class: (total ms, launches)} since the last read; synchronises."""
+        k = len(_lib.KERNEL_CLASSES)
+        ms = (ctypes.c_double * k)()
+        cnt = (ctypes.c_int64 * k)()
+        _lib.check(self._lib.mcr_profile_read(self._h, ms, cnt))
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(_lib.KERNEL_CLASSES)}
+
+    def info(self):
+        geo, ng, dt, rad = _lib.Geometry(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self._lib.mcr_get_info(self._h, ctypes.byref(geo), ctypes.byref(ng), ctypes.byref(dt),
+                                          ctypes.byref(rad)))
+        return {"n": geo.n, "n_angles": geo.n_angles, "n_det": geo.n_det, "n_gates": ng.value,
+                "dtype": dt.value, "window_radius": rad.value}

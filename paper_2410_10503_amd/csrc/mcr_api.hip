@@ -1,0 +1,982 @@
+// Host side of libmcr: handle, workspaces, argument validation, the drivers
+// of Algorithm 1 and the FP64 diagnostics. Implements include/mcr.h.
+#include "mcr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mcr_kernels.h"
+
+using namespace mcr;
+
+namespace {
+
+thread_local std::string g_err;
+
+mcr_status fail(mcr_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_OK(expr)                                                                       \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? MCR_ERR_NOMEM : MCR_ERR_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                       \
+  } while (0)
+
+#define LAUNCH_OK() HIP_OK(hipGetLastError())
+
+#define STATUS_OK(expr)           \
+  do {                            \
+    mcr_status s_ = (expr);       \
+    if (s_ != MCR_OK) return s_;  \
+  } while (0)
+
+inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+
+// Per-precision workspace and tables.
+template <typename T>
+struct Work {
+  bool ready = false;
+  AngleT<T>* ang = nullptr;          // [n_angles]
+  GateMotion<T>* motion = nullptr;   // [N + 1]; entry N is the identity
+  GateScalars<T>* scalars = nullptr; // [N]
+  GatePtrs<T>* ptrs = nullptr;       // [N]
+  T* wP = nullptr;                   // [N][padded]
+  T* wTP = nullptr;                  // [N][padded]
+  T* bP = nullptr;                   // [N][padded]
+  T* dy = nullptr;                   // [N][sino]
+  T* img = nullptr;                  // [n*n] scratch
+  T* img2 = nullptr;                 // [n*n] scratch
+  // host staging for scalars and pointers, uploaded when they change
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
+  hipEvent_t pin_ev = nullptr;
+  bool pin_recorded = false;
+  std::vector<char> last;
+};
+
+}  // namespace
+
+struct mcr_handle {
+  mcr_geometry geo{};
+  int N = 0;
+  mcr_dtype dtype = MCR_F32;
+  hipStream_t stream = nullptr;
+  int pitch = 0;
+  long padded = 0;   // elements of one padded image
+  long sino = 0;     // elements of one sinogram
+  std::vector<mcr_motion> motion;  // host copy (field pointers not kept)
+  std::vector<int> radius;         // per gate
+  float* fieldP = nullptr;         // [N][2][padded]
+  short2* centres = nullptr;       // [N][n][n]
+  bool any_field = false;
+  Work<float> wf;
+  Work<double> wd;
+  double* red_partial = nullptr;   // [kRedBlocks]
+  double* red_out = nullptr;       // [64] result slots
+  double* red_host = nullptr;      // pinned [64]
+  int* need = nullptr;             // window verification
+  std::vector<void*> allocs;
+  // kernel timing
+  bool prof = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> spare;
+};
+
+namespace {
+
+mcr_status dmalloc(mcr_handle* h, void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes < 256 ? 256 : bytes);
+  if (e != hipSuccess) return fail(MCR_ERR_NOMEM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+  h->allocs.push_back(*p);
+  HIP_OK(hipMemsetAsync(*p, 0, bytes < 256 ? 256 : bytes, h->stream));
+  return MCR_OK;
+}
+
+hipEvent_t prof_event(mcr_handle* h) {
+  if (!h->spare.empty()) {
+    hipEvent_t e = h->spare.back();
+    h->spare.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches made while alive with events when timing is enabled.
+struct Timed {
+  mcr_handle* h;
+  int cls;
+  hipEvent_t a = nullptr;
+  Timed(mcr_handle* hh, int c) : h(hh), cls(c) {
+    if (h->prof && h->recs.size() < 200000) {
+      a = prof_event(h);
+      if (a && hipEventRecord(a, h->stream) != hipSuccess) a = nullptr;
+    }
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = prof_event(h);
+    if (b && hipEventRecord(b, h->stream) == hipSuccess) {
+      h->recs.push_back({cls, a, b});
+    } else {
+      h->spare.push_back(a);
+      if (b) h->spare.push_back(b);
+    }
+  }
+};
+
+template <typename T>
+Work<T>& work(mcr_handle* h);
+template <>
+Work<float>& work<float>(mcr_handle* h) { return h->wf; }
+template <>
+Work<double>& work<double>(mcr_handle* h) { return h->wd; }
+
+template <typename T>
+Geo<T> geo_of(const mcr_handle* h) {
+  Geo<T> g;
+  g.n = h->geo.n;
+  g.na = h->geo.n_angles;
+  g.nd = h->geo.n_det;
+  g.pitch = h->pitch;
+  g.hc = T((h->geo.n - 1) / 2.0);
+  g.jc = T((h->geo.n_det - 1) / 2.0);
+  return g;
+}
+
+// Joseph constants per angle in FP64, rounded once to T. The stepping axis is
+// decided by the integer rule on k so that every precision uses the same matrix.
+template <typename T>
+std::vector<AngleT<T>> angle_table(int na) {
+  std::vector<AngleT<T>> v(na);
+  for (int k = 0; k < na; ++k) {
+    const double th = M_PI * k / na;
+    const double cs = std::cos(th), sn = std::sin(th);
+    const bool rows = (4L * k <= na) || (4L * k >= 3L * na);
+    AngleT<T> a{};
+    if (rows) {
+      a.a = T(1.0 / cs);
+      a.beta = T(-sn / cs);
+      a.ia = T(cs);
+      a.ds = T(1.0 / std::fabs(cs));
+    } else {
+      a.a = T(1.0 / sn);
+      a.beta = T(-cs / sn);
+      a.ia = T(sn);
+      a.ds = T(1.0 / std::fabs(sn));
+    }
+    a.rows = rows ? 1 : 0;
+    v[k] = a;
+  }
+  return v;
+}
+
+template <typename T>
+GateMotion<T> gate_motion(const mcr_handle* h, int gate) {
+  GateMotion<T> m{};
+  const double hc = (h->geo.n - 1) / 2.0;
+  if (gate >= h->N) return m;  // the identity entry
+  const mcr_motion& mo = h->motion[gate];
+  m.kind = mo.kind;
+  m.radius = h->radius[gate];
+  if (mo.kind == MCR_MOTION_RIGID) {
+    const double c = std::cos(mo.rigid[0]), s = std::sin(mo.rigid[0]);
+    m.m00 = T(c);
+    m.m01 = T(-s);
+    m.m10 = T(s);
+    m.m11 = T(c);
+    m.bx = T(hc + mo.rigid[1]);
+    m.by = T(hc + mo.rigid[2]);
+    m.i00 = T(c);
+    m.i01 = T(s);
+    m.i10 = T(-s);
+    m.i11 = T(c);
+  }
+  return m;
+}
+
+template <typename T>
+mcr_status upload_motion(mcr_handle* h) {
+  Work<T>& w = work<T>(h);
+  std::vector<GateMotion<T>> gm(h->N + 1);
+  for (int i = 0; i <= h->N; ++i) gm[i] = gate_motion<T>(h, i);
+  HIP_OK(hipMemcpyAsync(w.motion, gm.data(), sizeof(GateMotion<T>) * gm.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status init_work(mcr_handle* h) {
+  Work<T>& w = work<T>(h);
+  if (w.ready) return MCR_OK;
+  const int N = h->N;
+  const long n2 = (long)h->geo.n * h->geo.n;
+  STATUS_OK(dmalloc(h, (void**)&w.ang, sizeof(AngleT<T>) * h->geo.n_angles));
+  STATUS_OK(dmalloc(h, (void**)&w.motion, sizeof(GateMotion<T>) * (N + 1)));
+  STATUS_OK(dmalloc(h, (void**)&w.scalars, sizeof(GateScalars<T>) * N));
+  STATUS_OK(dmalloc(h, (void**)&w.ptrs, sizeof(GatePtrs<T>) * N));
+  STATUS_OK(dmalloc(h, (void**)&w.wP, sizeof(T) * h->padded * N));
+  STATUS_OK(dmalloc(h, (void**)&w.wTP, sizeof(T) * h->padded * N));
+  STATUS_OK(dmalloc(h, (void**)&w.bP, sizeof(T) * h->padded * N));
+  STATUS_OK(dmalloc(h, (void**)&w.dy, sizeof(T) * h->sino * N));
+  STATUS_OK(dmalloc(h, (void**)&w.img, sizeof(T) * n2));
+  STATUS_OK(dmalloc(h, (void**)&w.img2, sizeof(T) * n2));
+  w.pin_bytes = (sizeof(GateScalars<T>) + sizeof(GatePtrs<T>)) * N;
+  HIP_OK(hipHostMalloc(&w.pin, w.pin_bytes, hipHostMallocDefault));
+  HIP_OK(hipEventCreateWithFlags(&w.pin_ev, hipEventDisableTiming));
+  const std::vector<AngleT<T>> at = angle_table<T>(h->geo.n_angles);
+  HIP_OK(hipMemcpyAsync(w.ang, at.data(), sizeof(AngleT<T>) * at.size(), hipMemcpyHostToDevice, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  STATUS_OK(upload_motion<T>(h));
+  w.ready = true;
+  return MCR_OK;
+}
+
+// Uploads per-gate scalars and pointers when they differ from the last upload.
+// The pinned buffer is only rewritten after the previous copy has executed.
+template <typename T>
+mcr_status upload_params(mcr_handle* h, const std::vector<GateScalars<T>>& sc,
+                         const std::vector<GatePtrs<T>>& pt) {
+  Work<T>& w = work<T>(h);
+  const size_t b1 = sizeof(GateScalars<T>) * sc.size(), b2 = sizeof(GatePtrs<T>) * pt.size();
+  std::vector<char> cur(b1 + b2);
+  std::memcpy(cur.data(), sc.data(), b1);
+  std::memcpy(cur.data() + b1, pt.data(), b2);
+  if (cur == w.last) return MCR_OK;
+  if (w.pin_recorded) HIP_OK(hipEventSynchronize(w.pin_ev));
+  std::memcpy(w.pin, cur.data(), cur.size());
+  HIP_OK(hipMemcpyAsync(w.scalars, w.pin, b1, hipMemcpyHostToDevice, h->stream));
+  HIP_OK(hipMemcpyAsync(w.ptrs, (char*)w.pin + b1, b2, hipMemcpyHostToDevice, h->stream));
+  HIP_OK(hipEventRecord(w.pin_ev, h->stream));
+  w.pin_recorded = true;
+  w.last.swap(cur);
+  return MCR_OK;
+}
+
+int max_radius(const mcr_handle* h, int gate0, int G) {
+  int r = 1;
+  for (int i = gate0; i < gate0 + G && i < h->N; ++i) r = std::max(r, h->radius[i]);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  Timed tm(h, MCR_KERNEL_WARP);
+  dim3 grid(cdiv(n, 32), cdiv(n, 32), G), block(32, 8);
+  hipLaunchKernelGGL(k_warp_fwd<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate0,
+                     h->fieldP, 2 * h->padded, h->padded, x, 0L, w.wP, w.wTP, h->padded);
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+template <typename T, int MODE>
+mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stride) {
+  Work<T>& w = work<T>(h);
+  Timed tm(h, MCR_KERNEL_PROJECT);
+  dim3 grid(cdiv(h->geo.n_det, 256), h->geo.n_angles, G), block(256);
+  hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.ang, w.wP,
+                     w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_stride, T* out,
+                              long out_stride, int padded) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  Timed tm(h, MCR_KERNEL_BACKPROJECT);
+  dim3 grid(cdiv(n, 16), cdiv(n, 16), G), block(16, 16);
+  hipLaunchKernelGGL(k_joseph_adj<T>, grid, block, 0, h->stream, geo_of<T>(h), w.ang, sino,
+                     sino_stride, out, out_stride, padded);
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+template <typename T, int MODE>
+mcr_status launch_twarp(mcr_handle* h, int gate0, int G, T* out, UpdateArgs<T> ua) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  Timed tm(h, MCR_KERNEL_TWARP);
+  dim3 grid(cdiv(n, 16), cdiv(n, 16)), block(16, 16);
+  const int R = max_radius(h, gate0, G);
+  const Geo<T> g = geo_of<T>(h);
+#define TW(RR)                                                                                   \
+  hipLaunchKernelGGL((k_twarp<T, MODE, RR>), grid, block, 0, h->stream, g, w.motion, gate0, G,   \
+                     w.scalars, h->fieldP, 2 * h->padded, h->padded, h->centres, w.bP, h->padded, \
+                     out, ua)
+  if (R <= 1)
+    TW(1);
+  else if (R == 2)
+    TW(2);
+  else
+    TW(3);
+#undef TW
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status launch_xstep(mcr_handle* h, T* x, const T* zbar, T tau, T cx) {
+  const long n2 = (long)h->geo.n * h->geo.n;
+  Timed tm(h, MCR_KERNEL_XSTEP);
+  hipLaunchKernelGGL(k_xstep<T>, dim3(cdiv(n2, 256)), dim3(256), 0, h->stream, n2, x, zbar, tau, cx);
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+template <typename T>
+__global__ void k_from_padded(int n, int pitch, const T* __restrict__ src, T* __restrict__ dst) {
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c < n && r < n) dst[(long)r * n + c] = src[(long)(r + kPad) * pitch + c + kPad];
+}
+
+// Reductions into result slot `slot` of red_out (device); read back later.
+template <typename Ta, typename Tb, int OP>
+mcr_status launch_reduce(mcr_handle* h, long count, const Ta* a, const Tb* b, int slot) {
+  Timed tm(h, MCR_KERNEL_OTHER);
+  hipLaunchKernelGGL((k_reduce_partial<Ta, Tb, OP>), dim3(kRedBlocks), dim3(256), 0, h->stream, count,
+                     a, b, h->red_partial);
+  LAUNCH_OK();
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, slot);
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+mcr_status read_results(mcr_handle* h, int count) {
+  HIP_OK(hipMemcpyAsync(h->red_host, h->red_out, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  return MCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Validation
+// ---------------------------------------------------------------------------
+mcr_status check_handle(const mcr_handle* h) {
+  if (!h) return fail(MCR_ERR_ARG, "null handle");
+  return MCR_OK;
+}
+
+mcr_status check_gate(const mcr_handle* h, int gate) {
+  if (gate < 0 || gate >= h->N) return fail(MCR_ERR_ARG, "gate %d out of range [0, %d)", gate, h->N);
+  return MCR_OK;
+}
+
+mcr_status check_ptr(const void* p, const char* what) {
+  if (!p) return fail(MCR_ERR_ARG, "%s is null", what);
+  return MCR_OK;
+}
+
+mcr_status check_motion(const mcr_motion* m, int i) {
+  if (m->kind < MCR_MOTION_IDENTITY || m->kind > MCR_MOTION_FIELD)
+    return fail(MCR_ERR_ARG, "gate %d: unknown motion kind %d", i, m->kind);
+  if (m->kind == MCR_MOTION_RIGID)
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(m->rigid[k])) return fail(MCR_ERR_ARG, "gate %d: rigid parameter %d not finite", i, k);
+  if (m->kind == MCR_MOTION_FIELD && !m->field) return fail(MCR_ERR_ARG, "gate %d: field pointer is null", i);
+  return MCR_OK;
+}
+
+mcr_status check_alg(const mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                     const double* sigma, double tau, double theta, const double* p) {
+  if (!st) return fail(MCR_ERR_ARG, "state is null");
+  STATUS_OK(check_ptr(st->x, "state.x"));
+  STATUS_OK(check_ptr(st->z, "state.z"));
+  STATUS_OK(check_ptr(st->zbar, "state.zbar"));
+  STATUS_OK(check_ptr(st->y, "state.y"));
+  STATUS_OK(check_ptr(d, "d"));
+  STATUS_OK(check_ptr(sigma, "sigma"));
+  for (int i = 0; i < h->N; ++i) {
+    if (!st->y[i]) return fail(MCR_ERR_ARG, "state.y[%d] is null", i);
+    if (!d[i]) return fail(MCR_ERR_ARG, "d[%d] is null", i);
+    if (!(sigma[i] > 0) || !std::isfinite(sigma[i]))
+      return fail(MCR_ERR_ARG, "sigma[%d] = %g must be finite and > 0", i, sigma[i]);
+    if (p && (!(p[i] > 0) || !(p[i] <= 1))) return fail(MCR_ERR_ARG, "p[%d] = %g must be in (0, 1]", i, p[i]);
+  }
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(MCR_ERR_ARG, "alpha = %g must be finite and > 0", alpha);
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(MCR_ERR_ARG, "tau = %g must be finite and > 0", tau);
+  if (!(theta >= 0) || !std::isfinite(theta)) return fail(MCR_ERR_ARG, "theta = %g must be finite and >= 0", theta);
+  return MCR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 driver: one iteration over the gates gate0 .. gate0+G-1.
+// ---------------------------------------------------------------------------
+template <typename T>
+mcr_status iteration(mcr_handle* h, const mcr_state* st, int gate0, int G, bool xstep_first,
+                     bool xstep_after, T tau, T cx) {
+  Work<T>& w = work<T>(h);
+  T* x = (T*)st->x;
+  if (xstep_first) STATUS_OK(launch_xstep<T>(h, x, (const T*)st->zbar, tau, cx));
+  STATUS_OK(launch_warp<T>(h, gate0, G, x));
+  STATUS_OK((launch_project<T, 1>(h, gate0, G, w.dy, h->sino)));
+  STATUS_OK(launch_backproject<T>(h, G, w.dy, h->sino, w.bP, h->padded, 1));
+  UpdateArgs<T> ua{x, (T*)st->z, (T*)st->zbar, tau, cx, xstep_after ? 1 : 0};
+  STATUS_OK((launch_twarp<T, 2>(h, gate0, G, nullptr, ua)));
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status set_params(mcr_handle* h, const mcr_state* st, const void* const* d, const double* sigma,
+                      double theta, const double* p) {
+  const int N = h->N;
+  std::vector<GateScalars<T>> sc(N);
+  std::vector<GatePtrs<T>> pt(N);
+  for (int i = 0; i < N; ++i) {
+    sc[i].sigma = T(sigma[i]);
+    sc[i].cy = T(1.0 / (1.0 + sigma[i] * N / 2.0));
+    sc[i].coef = T(theta / (p ? p[i] : 1.0));
+    sc[i].pad_ = T(0);
+    pt[i].y = (T*)st->y[i];
+    pt[i].d = (const T*)d[i];
+  }
+  return upload_params<T>(h, sc, pt);
+}
+
+template <typename T>
+mcr_status spdhg_impl(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                      const double* sigma, double tau, double theta, const double* p,
+                      const int32_t* seq, int n_iter) {
+  STATUS_OK(set_params<T>(h, st, d, sigma, theta, p));
+  const T t = T(tau), cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
+  for (int k = 0; k < n_iter; ++k)
+    STATUS_OK(iteration<T>(h, st, seq[k], 1, k == 0, k + 1 < n_iter, t, cx));
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status pdhg_impl(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                     const double* sigma, double tau, double theta) {
+  STATUS_OK(set_params<T>(h, st, d, sigma, theta, nullptr));
+  const T t = T(tau), cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
+  return iteration<T>(h, st, 0, h->N, true, false, t, cx);
+}
+
+// ---------------------------------------------------------------------------
+// Operators
+// ---------------------------------------------------------------------------
+template <typename T>
+mcr_status apply_Ai_impl(mcr_handle* h, int gate, const void* x, void* out) {
+  STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)x));
+  return launch_project<T, 0>(h, gate, 1, (T*)out, h->sino);
+}
+
+template <typename T>
+mcr_status apply_Ai_adjoint_impl(mcr_handle* h, int gate, const void* s, void* out) {
+  Work<T>& w = work<T>(h);
+  STATUS_OK(launch_backproject<T>(h, 1, (const T*)s, h->sino, w.bP, h->padded, 1));
+  return launch_twarp<T, 0>(h, gate, 1, (T*)out, UpdateArgs<T>{});
+}
+
+template <typename T>
+mcr_status warp_impl(mcr_handle* h, int gate, const void* x, void* out) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)x));
+  hipLaunchKernelGGL(k_from_padded<T>, dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n,
+                     h->pitch, w.wP, (T*)out);
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status warp_adjoint_impl(mcr_handle* h, int gate, const void* b, void* out) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  hipLaunchKernelGGL((k_to_padded<T, T>), dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n,
+                     h->pitch, (const T*)b, w.bP);
+  LAUNCH_OK();
+  return launch_twarp<T, 0>(h, gate, 1, (T*)out, UpdateArgs<T>{});
+}
+
+// ---------------------------------------------------------------------------
+// FP64 diagnostics (always on the double workspace)
+// ---------------------------------------------------------------------------
+// out = sum over gates in [gate0, gate0+G) of A_g^* A_g v  (v unpadded double)
+mcr_status normal_op64(mcr_handle* h, int gate0, int G, const double* v, double* out) {
+  Work<double>& w = h->wd;
+  STATUS_OK(launch_warp<double>(h, gate0, G, v));
+  STATUS_OK((launch_project<double, 0>(h, gate0, G, w.dy, h->sino)));
+  STATUS_OK(launch_backproject<double>(h, G, w.dy, h->sino, w.bP, h->padded, 1));
+  return launch_twarp<double, 0>(h, gate0, G, out, UpdateArgs<double>{});
+}
+
+template <typename T>
+mcr_status objective_impl(mcr_handle* h, const void* x, const void* const* d, double alpha, double* out) {
+  STATUS_OK(init_work<double>(h));
+  Work<double>& w = h->wd;
+  const long n2 = (long)h->geo.n * h->geo.n;
+  const int N = h->N;
+  double* x64 = w.img;
+  hipLaunchKernelGGL((k_convert<T, double>), dim3(cdiv(n2, 256)), dim3(256), 0, h->stream, n2,
+                     (const T*)x, x64);
+  LAUNCH_OK();
+  STATUS_OK((launch_reduce<double, double, 0>(h, n2, x64, x64, 0)));
+  STATUS_OK(read_results(h, 1));
+  const double xx = h->red_host[0];
+  // chunks of up to 32 gates share one warp and one projection launch;
+  // each gate's residual norm goes to result slot 1 + (gate - g0)
+  double resid = 0.0;
+  for (int g0 = 0; g0 < N; g0 += 32) {
+    const int G = std::min(32, N - g0);
+    STATUS_OK(launch_warp<double>(h, g0, G, x64));
+    STATUS_OK((launch_project<double, 0>(h, g0, G, w.dy, h->sino)));
+    for (int i = 0; i < G; ++i)
+      STATUS_OK((launch_reduce<double, T, 2>(h, h->sino, w.dy + i * h->sino, (const T*)d[g0 + i], 1 + i)));
+    STATUS_OK(read_results(h, 1 + G));
+    for (int i = 0; i < G; ++i) resid += h->red_host[1 + i];
+  }
+  const double val = alpha * xx + resid / N;
+  if (!std::isfinite(val)) return fail(MCR_ERR_NONFINITE, "objective is not finite");
+  *out = val;
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status gap_impl(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha, double* out) {
+  double obj = 0.0;
+  STATUS_OK(objective_impl<T>(h, st->x, d, alpha, &obj));
+  Work<double>& w = h->wd;
+  const int N = h->N;
+  const long n2 = (long)h->geo.n * h->geo.n;
+  // z = sum_i A_i^* y_i in FP64, 32 gates per launch, accumulated into img2
+  double dual = 0.0;
+  for (int g0 = 0; g0 < N; g0 += 32) {
+    const int G = std::min(32, N - g0);
+    for (int i = 0; i < G; ++i) {
+      hipLaunchKernelGGL((k_convert<T, double>), dim3(cdiv(h->sino, 256)), dim3(256), 0, h->stream, h->sino,
+                         (const T*)st->y[g0 + i], w.dy + i * h->sino);
+      LAUNCH_OK();
+    }
+    STATUS_OK(launch_backproject<double>(h, G, w.dy, h->sino, w.bP, h->padded, 1));
+    if (g0 == 0)
+      STATUS_OK((launch_twarp<double, 0>(h, g0, G, w.img2, UpdateArgs<double>{})));
+    else
+      STATUS_OK((launch_twarp<double, 1>(h, g0, G, w.img2, UpdateArgs<double>{})));
+    for (int i = 0; i < G; ++i) {
+      STATUS_OK((launch_reduce<T, T, 1>(h, h->sino, (const T*)st->y[g0 + i], (const T*)d[g0 + i], 2 * i)));
+      STATUS_OK((launch_reduce<T, T, 0>(h, h->sino, (const T*)st->y[g0 + i], (const T*)st->y[g0 + i], 2 * i + 1)));
+    }
+    STATUS_OK(read_results(h, 2 * G));
+    for (int i = 0; i < G; ++i) dual += h->red_host[2 * i] + 0.25 * N * h->red_host[2 * i + 1];
+  }
+  STATUS_OK((launch_reduce<double, double, 0>(h, n2, w.img2, w.img2, 0)));
+  STATUS_OK(read_results(h, 1));
+  const double val = obj + h->red_host[0] / (4.0 * alpha) + dual;
+  if (!std::isfinite(val)) return fail(MCR_ERR_NONFINITE, "duality gap is not finite");
+  *out = val;
+  return MCR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* mcr_last_error(void) { return g_err.c_str(); }
+
+mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motion* motion, mcr_dtype dtype,
+                      void* stream, mcr_handle** out) {
+  if (!out) return fail(MCR_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!geom) return fail(MCR_ERR_ARG, "geometry is null");
+  if (geom->n < 1 || geom->n > 4096) return fail(MCR_ERR_ARG, "n = %d must be in [1, 4096]", geom->n);
+  if (geom->n_angles < 1 || geom->n_angles > 16384)
+    return fail(MCR_ERR_ARG, "n_angles = %d must be in [1, 16384]", geom->n_angles);
+  if (geom->n_det < 1 || geom->n_det > 16384)
+    return fail(MCR_ERR_ARG, "n_det = %d must be in [1, 16384]", geom->n_det);
+  if (n_gates < 1 || n_gates > 4096) return fail(MCR_ERR_ARG, "n_gates = %d must be in [1, 4096]", n_gates);
+  if (!motion) return fail(MCR_ERR_ARG, "motion is null");
+  for (int i = 0; i < n_gates; ++i) STATUS_OK(check_motion(&motion[i], i));
+  if (dtype != MCR_F32 && dtype != MCR_F64) return fail(MCR_ERR_ARG, "unknown dtype %d", (int)dtype);
+
+  mcr_handle* h = new mcr_handle();
+  h->geo = *geom;
+  h->N = n_gates;
+  h->dtype = dtype;
+  h->stream = (hipStream_t)stream;
+  h->pitch = geom->n + 2 * kPad;
+  h->padded = (long)h->pitch * h->pitch;
+  h->sino = (long)geom->n_angles * geom->n_det;
+  h->motion.assign(motion, motion + n_gates);
+  h->radius.assign(n_gates, 1);
+  for (auto& m : h->motion) {
+    if (m.kind == MCR_MOTION_FIELD) h->any_field = true;
+  }
+  auto cleanup = [&](mcr_status s) {
+    mcr_destroy(h);
+    return s;
+  };
+  mcr_status s;
+  const int n = geom->n;
+  if ((s = dmalloc(h, (void**)&h->fieldP, sizeof(float) * 2 * h->padded * (h->any_field ? n_gates : 1))) != MCR_OK)
+    return cleanup(s);
+  if ((s = dmalloc(h, (void**)&h->centres, sizeof(short2) * (long)n * n * (h->any_field ? n_gates : 1))) != MCR_OK)
+    return cleanup(s);
+  if ((s = dmalloc(h, (void**)&h->red_partial, sizeof(double) * kRedBlocks)) != MCR_OK) return cleanup(s);
+  if ((s = dmalloc(h, (void**)&h->red_out, sizeof(double) * 64)) != MCR_OK) return cleanup(s);
+  if ((s = dmalloc(h, (void**)&h->need, sizeof(int) * 4)) != MCR_OK) return cleanup(s);
+  if (hipHostMalloc((void**)&h->red_host, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(MCR_ERR_NOMEM, "pinned allocation failed"));
+  // copy fields into the padded layout and build the window centres
+  for (int i = 0; i < n_gates && h->any_field; ++i) {
+    if (h->motion[i].kind != MCR_MOTION_FIELD) continue;
+    float* dst = h->fieldP + (long)i * 2 * h->padded;
+    for (int pl = 0; pl < 2; ++pl) {
+      hipLaunchKernelGGL((k_to_padded<float, float>), dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0,
+                         h->stream, n, h->pitch, h->motion[i].field + (long)pl * n * n, dst + pl * h->padded);
+    }
+    hipLaunchKernelGGL(k_field_centres, dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n, h->pitch,
+                       dst, h->padded, h->centres + (long)i * n * n);
+    h->motion[i].field = nullptr;
+  }
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+    return cleanup(fail(MCR_ERR_HIP, "field set-up failed"));
+  if ((s = init_work<double>(h)) != MCR_OK) return cleanup(s);
+  if (dtype == MCR_F32 && (s = init_work<float>(h)) != MCR_OK) return cleanup(s);
+  if ((s = mcr_set_motion(h, -1, nullptr)) != MCR_OK) return cleanup(s);
+  *out = h;
+  return MCR_OK;
+}
+
+mcr_status mcr_destroy(mcr_handle* h) {
+  if (!h) return MCR_OK;
+  // release everything even if the runtime reports an earlier error
+  (void)(h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize());
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->red_host) (void)hipHostFree(h->red_host);
+  if (h->wf.pin) (void)hipHostFree(h->wf.pin);
+  if (h->wd.pin) (void)hipHostFree(h->wd.pin);
+  if (h->wf.pin_ev) (void)hipEventDestroy(h->wf.pin_ev);
+  if (h->wd.pin_ev) (void)hipEventDestroy(h->wd.pin_ev);
+  for (auto& r : h->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : h->spare) (void)hipEventDestroy(e);
+  delete h;
+  return MCR_OK;
+}
+
+mcr_status mcr_set_stream(mcr_handle* h, void* stream) {
+  STATUS_OK(check_handle(h));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  h->stream = (hipStream_t)stream;
+  return MCR_OK;
+}
+
+// gate = -1 (internal): re-verify every gate's window with the current motion.
+mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion) {
+  STATUS_OK(check_handle(h));
+  const int n = h->geo.n;
+  if (gate >= 0) {
+    STATUS_OK(check_gate(h, gate));
+    STATUS_OK(check_ptr(motion, "motion"));
+    STATUS_OK(check_motion(motion, gate));
+    if (motion->kind == MCR_MOTION_FIELD && !h->any_field)
+      return fail(MCR_ERR_STATE, "handle was created without displacement fields");
+    HIP_OK(hipStreamSynchronize(h->stream));
+    h->motion[gate] = *motion;
+    if (motion->kind == MCR_MOTION_FIELD) {
+      float* dst = h->fieldP + (long)gate * 2 * h->padded;
+      for (int pl = 0; pl < 2; ++pl) {
+        hipLaunchKernelGGL((k_to_padded<float, float>), dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0,
+                           h->stream, n, h->pitch, motion->field + (long)pl * n * n, dst + pl * h->padded);
+        LAUNCH_OK();
+      }
+      hipLaunchKernelGGL(k_field_centres, dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n, h->pitch,
+                         dst, h->padded, h->centres + (long)gate * n * n);
+      LAUNCH_OK();
+      h->motion[gate].field = nullptr;
+    }
+  }
+  // verify the gather windows with both precisions' arithmetic
+  const int g0 = gate >= 0 ? gate : 0, g1 = gate >= 0 ? gate + 1 : h->N;
+  STATUS_OK(upload_motion<double>(h));
+  if (h->wf.ready) STATUS_OK(upload_motion<float>(h));
+  for (int i = g0; i < g1; ++i) {
+    if (h->motion[i].kind == MCR_MOTION_IDENTITY) {
+      h->radius[i] = 1;
+      continue;
+    }
+    HIP_OK(hipMemsetAsync(h->need, 0, sizeof(int), h->stream));
+    dim3 grid(cdiv(n, 16), cdiv(n, 16)), block(16, 16);
+    hipLaunchKernelGGL(k_window_check<double>, grid, block, 0, h->stream, geo_of<double>(h), h->wd.motion, i,
+                       h->fieldP, 2 * h->padded, h->padded, h->centres, h->need);
+    LAUNCH_OK();
+    if (h->wf.ready) {
+      hipLaunchKernelGGL(k_window_check<float>, grid, block, 0, h->stream, geo_of<float>(h), h->wf.motion, i,
+                         h->fieldP, 2 * h->padded, h->padded, h->centres, h->need);
+      LAUNCH_OK();
+    }
+    int need = 0;
+    HIP_OK(hipMemcpyAsync(&need, h->need, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+    if (need > kMaxRadius)
+      return fail(MCR_ERR_STATE,
+                  "gate %d: the displacement field folds too strongly for a %dx%d transposed-warp window (needs %d)",
+                  i, 2 * kMaxRadius + 1, 2 * kMaxRadius + 1, need);
+    h->radius[i] = std::max(1, need);
+  }
+  STATUS_OK(upload_motion<double>(h));
+  if (h->wf.ready) STATUS_OK(upload_motion<float>(h));
+  return MCR_OK;
+}
+
+mcr_status mcr_get_info(const mcr_handle* h, mcr_geometry* geom, int32_t* n_gates, mcr_dtype* dtype,
+                        int32_t* window_radius) {
+  STATUS_OK(check_handle(h));
+  if (geom) *geom = h->geo;
+  if (n_gates) *n_gates = h->N;
+  if (dtype) *dtype = h->dtype;
+  if (window_radius) {
+    int r = 1;
+    for (int v : h->radius) r = std::max(r, v);
+    *window_radius = r;
+  }
+  return MCR_OK;
+}
+
+#define DISPATCH(fn, ...) \
+  (h->dtype == MCR_F32 ? fn<float>(__VA_ARGS__) : fn<double>(__VA_ARGS__))
+
+mcr_status mcr_warp(mcr_handle* h, int32_t gate, const void* x, void* img) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(x, "x"));
+  STATUS_OK(check_ptr(img, "img"));
+  return DISPATCH(warp_impl, h, gate, x, img);
+}
+
+mcr_status mcr_warp_adjoint(mcr_handle* h, int32_t gate, const void* b, void* img) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(b, "b"));
+  STATUS_OK(check_ptr(img, "img"));
+  return DISPATCH(warp_adjoint_impl, h, gate, b, img);
+}
+
+mcr_status mcr_project(mcr_handle* h, const void* x, void* sino) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_ptr(x, "x"));
+  STATUS_OK(check_ptr(sino, "sino"));
+  return DISPATCH(apply_Ai_impl, h, h->N, x, sino);  // entry N of the motion table is the identity
+}
+
+mcr_status mcr_backproject(mcr_handle* h, const void* sino, void* img) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_ptr(sino, "sino"));
+  STATUS_OK(check_ptr(img, "img"));
+  if (h->dtype == MCR_F32)
+    return launch_backproject<float>(h, 1, (const float*)sino, h->sino, (float*)img, 0, 0);
+  return launch_backproject<double>(h, 1, (const double*)sino, h->sino, (double*)img, 0, 0);
+}
+
+mcr_status mcr_apply_Ai(mcr_handle* h, int32_t gate, const void* x, void* sino) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(x, "x"));
+  STATUS_OK(check_ptr(sino, "sino"));
+  return DISPATCH(apply_Ai_impl, h, gate, x, sino);
+}
+
+mcr_status mcr_apply_Ai_adjoint(mcr_handle* h, int32_t gate, const void* sino, void* img) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(sino, "sino"));
+  STATUS_OK(check_ptr(img, "img"));
+  return DISPATCH(apply_Ai_adjoint_impl, h, gate, sino, img);
+}
+
+mcr_status mcr_spdhg_iterate(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                             const double* sigma, double tau, double theta, const double* p,
+                             const int32_t* gate_seq, int32_t n_iter) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_alg(h, st, d, alpha, sigma, tau, theta, p));
+  STATUS_OK(check_ptr(p, "p"));
+  STATUS_OK(check_ptr(gate_seq, "gate_seq"));
+  if (n_iter < 0) return fail(MCR_ERR_ARG, "n_iter = %d must be >= 0", n_iter);
+  for (int k = 0; k < n_iter; ++k) STATUS_OK(check_gate(h, gate_seq[k]));
+  if (n_iter == 0) return MCR_OK;
+  return DISPATCH(spdhg_impl, h, st, d, alpha, sigma, tau, theta, p, gate_seq, n_iter);
+}
+
+mcr_status mcr_spdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                           const double* sigma, double tau, double theta, const double* p,
+                           const int32_t* gate_seq) {
+  STATUS_OK(check_handle(h));
+  return mcr_spdhg_iterate(h, st, d, alpha, sigma, tau, theta, p, gate_seq, h->N);
+}
+
+mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                          const double* sigma, double tau, double theta) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_alg(h, st, d, alpha, sigma, tau, theta, nullptr));
+  return DISPATCH(pdhg_impl, h, st, d, alpha, sigma, tau, theta);
+}
+
+mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int32_t max_iter, double rtol,
+                             double* out, int32_t* iters) {
+  STATUS_OK(check_handle(h));
+  if (gate != -1) STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(v0, "v0"));
+  STATUS_OK(check_ptr(out, "out"));
+  if (max_iter < 1) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 1", max_iter);
+  if (!(rtol >= 0) || !std::isfinite(rtol)) return fail(MCR_ERR_ARG, "rtol must be finite and >= 0");
+  STATUS_OK(init_work<double>(h));
+  Work<double>& w = h->wd;
+  const long n2 = (long)h->geo.n * h->geo.n;
+  double* v = w.img;
+  double* av = w.img2;
+  HIP_OK(hipMemcpyAsync(v, v0, sizeof(double) * n2, hipMemcpyDeviceToDevice, h->stream));
+  STATUS_OK((launch_reduce<double, double, 0>(h, n2, v, v, 0)));
+  STATUS_OK(read_results(h, 1));
+  if (!(h->red_host[0] > 0)) return fail(MCR_ERR_ARG, "v0 must be nonzero and finite");
+  double scale = 1.0 / std::sqrt(h->red_host[0]);
+  double lam = 0.0;
+  int it = 0;
+  const int gate0 = gate < 0 ? 0 : gate, G = gate < 0 ? h->N : 1;
+  for (it = 1; it <= max_iter; ++it) {
+    hipLaunchKernelGGL(k_scale<double>, dim3(cdiv(n2, 256)), dim3(256), 0, h->stream, n2, v, scale);
+    LAUNCH_OK();
+    STATUS_OK(normal_op64(h, gate0, G, v, av));
+    STATUS_OK((launch_reduce<double, double, 1>(h, n2, v, av, 0)));
+    STATUS_OK((launch_reduce<double, double, 0>(h, n2, av, av, 1)));
+    STATUS_OK(read_results(h, 2));
+    const double lam_new = h->red_host[0], nw2 = h->red_host[1];
+    if (!std::isfinite(lam_new) || !std::isfinite(nw2)) return fail(MCR_ERR_NONFINITE, "power iteration diverged");
+    if (nw2 == 0.0) {
+      lam = 0.0;
+      break;
+    }
+    std::swap(v, av);  // v <- A^*A v, rescaled at the top of the next iteration
+    scale = 1.0 / std::sqrt(nw2);
+    const bool done = it > 1 && std::fabs(lam_new - lam) <= rtol * std::fabs(lam_new);
+    lam = lam_new;
+    if (done) break;
+  }
+  HIP_OK(hipStreamSynchronize(h->stream));
+  *out = lam;
+  if (iters) *iters = std::min(it, max_iter);
+  return MCR_OK;
+}
+
+mcr_status mcr_objective(mcr_handle* h, const void* x, const void* const* d, double alpha, double* out) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_ptr(x, "x"));
+  STATUS_OK(check_ptr(d, "d"));
+  STATUS_OK(check_ptr(out, "out"));
+  for (int i = 0; i < h->N; ++i)
+    if (!d[i]) return fail(MCR_ERR_ARG, "d[%d] is null", i);
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(MCR_ERR_ARG, "alpha must be finite and > 0");
+  return DISPATCH(objective_impl, h, x, d, alpha, out);
+}
+
+mcr_status mcr_duality_gap(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha, double* out) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_ptr(out, "out"));
+  if (!st) return fail(MCR_ERR_ARG, "state is null");
+  STATUS_OK(check_ptr(st->x, "state.x"));
+  STATUS_OK(check_ptr(st->y, "state.y"));
+  STATUS_OK(check_ptr(d, "d"));
+  for (int i = 0; i < h->N; ++i) {
+    if (!st->y[i]) return fail(MCR_ERR_ARG, "state.y[%d] is null", i);
+    if (!d[i]) return fail(MCR_ERR_ARG, "d[%d] is null", i);
+  }
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(MCR_ERR_ARG, "alpha must be finite and > 0");
+  return DISPATCH(gap_impl, h, st, d, alpha, out);
+}
+
+mcr_status mcr_profile_enable(mcr_handle* h, int32_t enable) {
+  STATUS_OK(check_handle(h));
+  h->prof = enable != 0;
+  return MCR_OK;
+}
+
+mcr_status mcr_profile_read(mcr_handle* h, double* total_ms, int64_t* launches) {
+  STATUS_OK(check_handle(h));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  double ms[MCR_KERNEL_CLASSES] = {0};
+  int64_t cnt[MCR_KERNEL_CLASSES] = {0};
+  for (auto& r : h->recs) {
+    float t = 0.0f;
+    HIP_OK(hipEventElapsedTime(&t, r.a, r.b));
+    ms[r.cls] += t;
+    cnt[r.cls] += 1;
+    h->spare.push_back(r.a);
+    h->spare.push_back(r.b);
+  }
+  h->recs.clear();
+  for (int i = 0; i < MCR_KERNEL_CLASSES; ++i) {
+    if (total_ms) total_ms[i] = ms[i];
+    if (launches) launches[i] = cnt[i];
+  }
+  return MCR_OK;
+}
+
+mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq, double alpha, double* sigma,
+                          double* tau, double* theta, double* rate_per_epoch) {
+  if (algo != 0 && algo != 1) return fail(MCR_ERR_ARG, "algo = %d must be 0 (SPDHG) or 1 (PDHG)", algo);
+  if (n_gates < 1) return fail(MCR_ERR_ARG, "n_gates = %d must be >= 1", n_gates);
+  STATUS_OK(check_ptr(norms_sq, "norms_sq"));
+  STATUS_OK(check_ptr(sigma, "sigma"));
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(MCR_ERR_ARG, "alpha must be finite and > 0");
+  const int cnt = algo == 0 ? n_gates : 1;
+  for (int i = 0; i < cnt; ++i)
+    if (!(norms_sq[i] > 0) || !std::isfinite(norms_sq[i]))
+      return fail(MCR_ERR_ARG, "norms_sq[%d] = %g must be finite and > 0", i, norms_sq[i]);
+  const double N = n_gates;
+  if (algo == 0) {
+    const double pr = 1.0 / N;
+    double s = 0.0;
+    for (int i = 0; i < n_gates; ++i) {
+      const double si = std::sqrt(1.0 + norms_sq[i] / (alpha * N));
+      s = std::max(s, si);
+      sigma[i] = 2.0 / (N * (si - 1.0));
+    }
+    const double rho = 1.0 - 2.0 * pr / (1.0 + s);
+    if (tau) *tau = pr / (2.0 * alpha * rho * (1.0 + s));
+    if (theta) *theta = rho;
+    if (rate_per_epoch) *rate_per_epoch = std::pow(rho, N);
+  } else {
+    const double s = std::sqrt(1.0 + norms_sq[0] / (alpha * N));
+    for (int i = 0; i < n_gates; ++i) sigma[i] = 2.0 / (N * (s - 1.0));
+    if (tau) *tau = 1.0 / (2.0 * alpha * (s - 1.0));
+    if (theta) *theta = (s - 1.0) / (s + 1.0);
+    if (rate_per_epoch) *rate_per_epoch = (s - 1.0) / (s + 1.0);
+  }
+  return MCR_OK;
+}
+
+}  // extern "C"

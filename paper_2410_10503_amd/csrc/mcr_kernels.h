@@ -1,0 +1,547 @@
+// Device code of libmcr: the hot path of motion-compensated SPDHG/PDHG on
+// gfx950. Every kernel is templated on the scalar type T (float for the bulk
+// path, double for the FP64 diagnostics); all are gathers, so every output
+// element is written by exactly one thread (no atomics on the hot path, bitwise
+// reproducible).
+//
+// Layouts in HBM
+//   image         [n][n] row-major (caller arrays)
+//   padded image  [n+2P][n+2P] with a zero border of P = 4 pixels (handle
+//                 workspaces): lets the projector and the transposed warp read
+//                 neighbours of edge pixels without bounds checks
+//   sinogram      [n_angles][n_det] row-major, detector fastest
+//   field         padded [2][n+2P][n+2P] float (u_x plane, u_y plane)
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mcr {
+
+constexpr int kPad = 4;          // zero border of padded images and fields
+constexpr int kMaxRadius = 3;    // largest gather window radius of D^T
+
+// Per-angle constants of the Joseph projector, built in FP64 on the host.
+// Along the stepping line at offset u from the centre, ray t crosses the
+// interpolation axis at  cf = t * a + (u * beta + hc)  (index coordinates).
+template <typename T>
+struct AngleT {
+  T a;      // 1/cos (row stepping) or 1/sin (column stepping)
+  T beta;   // -sin/cos or -cos/sin
+  T ia;     // 1/a
+  T ds;     // |a|: length of the ray per line
+  int rows; // 1: lines are image rows, interpolation along columns
+  int pad_;
+};
+
+// Motion of one gate. Rigid forward map in index coordinates, with
+// xc = c - hc, yc = r - hc:  px = m00 xc + m01 yc + bx,  py = m10 xc + m11 yc + by.
+template <typename T>
+struct GateMotion {
+  int kind;    // 0 identity, 1 rigid, 2 field
+  int radius;  // gather window radius of the transposed warp
+  T m00, m01, m10, m11, bx, by;
+  T i00, i01, i10, i11;  // inverse rotation (window centres only)
+};
+
+// Per-gate scalars of one call of Algorithm 1.
+template <typename T>
+struct GateScalars {
+  T sigma;  // sigma_i
+  T cy;     // 1 / (1 + sigma_i N / 2)
+  T coef;   // theta / p_i
+  T pad_;
+};
+
+// Device pointers of one gate for the fused dual step.
+template <typename T>
+struct GatePtrs {
+  T* y;
+  const T* d;
+};
+
+template <typename T>
+struct Geo {
+  int n, na, nd, pitch;
+  T hc;  // (n-1)/2
+  T jc;  // (n_det-1)/2
+};
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Sample position of output pixel (r, c) under the gate's motion. The forward
+// warp and the transposed warp both call this, so their weights are the same
+// floating-point numbers.
+template <typename T>
+__device__ __forceinline__ void motion_pos(const GateMotion<T>& M, const float* __restrict__ ux,
+                                           const float* __restrict__ uy, int pitch, T hc, int r,
+                                           int c, T& px, T& py) {
+  if (M.kind == 1) {
+    const T xc = T(c) - hc, yc = T(r) - hc;
+    px = fmaT(M.m00, xc, fmaT(M.m01, yc, M.bx));
+    py = fmaT(M.m10, xc, fmaT(M.m11, yc, M.by));
+  } else if (M.kind == 2) {
+    const long o = (long)r * pitch + c;
+    px = T(c) + T(ux[o]);
+    py = T(r) + T(uy[o]);
+  } else {
+    px = T(c);
+    py = T(r);
+  }
+}
+
+
+// Centre of the gather window of output pixel (qr, qc) for the transposed
+// warp: the rounded inverse image of q (rigid: analytic inverse; field: the
+// set-up table), clamped to [-1, n] so that every candidate of a window of
+// radius <= kMaxRadius lies inside the zero border.
+template <typename T>
+__device__ __forceinline__ void window_centre(const GateMotion<T>& M, const short2* __restrict__ centres,
+                                              int gate, int n, T hc, int qr, int qc, int& cr, int& cc) {
+  if (M.kind == 1) {
+    const T dx = T(qc) - M.bx, dy = T(qr) - M.by;
+    cc = (int)rint(fmaT(M.i00, dx, fmaT(M.i01, dy, hc)));
+    cr = (int)rint(fmaT(M.i10, dx, fmaT(M.i11, dy, hc)));
+    cc = min(max(cc, -1), n);
+    cr = min(max(cr, -1), n);
+  } else {
+    const short2 cen = centres[(long)gate * n * n + (long)qr * n + qc];
+    cc = cen.x;
+    cr = cen.y;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a1: forward warp  w = D_i x  (bilinear pull-back, zero outside the image).
+// One thread per output pixel, 32x32 tiles; the tile is also written
+// transposed (through LDS) so that the projector reads column-stepping
+// angles with unit stride.
+// grid (ceil(n/32), ceil(n/32), G), block (32, 8)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_warp_fwd(Geo<T> g, const GateMotion<T>* __restrict__ gm,
+                                                  int gate0, const float* __restrict__ field,
+                                                  long field_stride, long plane_stride,
+                                                  const T* __restrict__ x, long x_stride,
+                                                  T* __restrict__ wP, T* __restrict__ wTP,
+                                                  long w_stride) {
+  __shared__ T tile[32][33];
+  const int gate = gate0 + blockIdx.z;
+  const GateMotion<T> M = gm[gate];
+  const int n = g.n, pitch = g.pitch;
+  const long origin = (long)kPad * pitch + kPad;
+  const float* ux = field + gate * field_stride + origin;
+  const float* uy = ux + plane_stride;
+  const T* src = x + blockIdx.z * x_stride;
+  T* dst = wP + blockIdx.z * w_stride + origin;
+  T* dstT = wTP + blockIdx.z * w_stride + origin;
+  const int c = blockIdx.x * 32 + threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = blockIdx.y * 32 + threadIdx.y + 8 * i;
+    T v = T(0);
+    if (r < n && c < n) {
+      if (M.kind == 0) {
+        v = src[(long)r * n + c];
+      } else {
+        T px, py;
+        motion_pos(M, ux, uy, pitch, g.hc, r, c, px, py);
+        const T fc0 = floor(px), fr0 = floor(py);
+        const T fx = px - fc0, fy = py - fr0;
+        // taps outside [-1, n] contribute nothing; clamp keeps the int cast finite
+        const int c0 = (int)fmax(fmin(fc0, T(n)), T(-2));
+        const int r0 = (int)fmax(fmin(fr0, T(n)), T(-2));
+        const T w00 = (T(1) - fx) * (T(1) - fy), w01 = fx * (T(1) - fy);
+        const T w10 = (T(1) - fx) * fy, w11 = fx * fy;
+        const bool cin0 = (unsigned)c0 < (unsigned)n, cin1 = (unsigned)(c0 + 1) < (unsigned)n;
+        const bool rin0 = (unsigned)r0 < (unsigned)n, rin1 = (unsigned)(r0 + 1) < (unsigned)n;
+        T acc = T(0);
+        if (rin0 && cin0) acc = fmaT(w00, src[(long)r0 * n + c0], acc);
+        if (rin0 && cin1) acc = fmaT(w01, src[(long)r0 * n + c0 + 1], acc);
+        if (rin1 && cin0) acc = fmaT(w10, src[(long)(r0 + 1) * n + c0], acc);
+        if (rin1 && cin1) acc = fmaT(w11, src[(long)(r0 + 1) * n + c0 + 1], acc);
+        v = acc;
+      }
+      dst[(long)r * pitch + c] = v;
+    }
+    tile[threadIdx.y + 8 * i][threadIdx.x] = v;
+  }
+  __syncthreads();
+  // transposed store: thread (tx, ty) writes column blockIdx.x*32 + ty + 8i, rows along tx
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int cc = blockIdx.x * 32 + threadIdx.y + 8 * i;
+    const int rr = blockIdx.y * 32 + threadIdx.x;
+    if (cc < n && rr < n) dstT[(long)cc * pitch + rr] = tile[threadIdx.x][threadIdx.y + 8 * i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a2 (+ a3): Joseph forward projection of the padded image, one thread per
+// ray; the lanes of a wave are adjacent detector bins of one angle, so each
+// line's two taps are read along a contiguous run of the (row-major or
+// transposed) padded image. Mode 0 writes the sinogram; mode 1 fuses the
+// dual step of Algorithm 1 (ii):
+//   y' = (y + sigma (A_i x - d)) / (1 + sigma N / 2),  dy = y' - y
+// grid (ceil(n_det/256), n_angles, G), block 256
+// ---------------------------------------------------------------------------
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_joseph_fwd(Geo<T> g, const AngleT<T>* __restrict__ ang,
+                                                    const T* __restrict__ wP,
+                                                    const T* __restrict__ wTP, long w_stride,
+                                                    T* __restrict__ out, long out_stride,
+                                                    int gate0, const GateScalars<T>* __restrict__ gs,
+                                                    const GatePtrs<T>* __restrict__ gp) {
+  __shared__ int s_lo, s_hi;
+  const int k = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const AngleT<T> A = ang[k];
+  const int n = g.n, pitch = g.pitch;
+  const bool live = j < g.nd;
+  const T t = T(j) - g.jc;
+  if (threadIdx.x == 0) {
+    s_lo = n;
+    s_hi = -1;
+  }
+  __syncthreads();
+  if (live) {
+    // lines where the crossing lies in (-1, n): cf(u) = t a + hc + u beta
+    const float ta = float(t) * float(A.a) + float(g.hc);
+    const float bt = float(A.beta);
+    int lo = 0, hi = n - 1;
+    if (fabsf(bt) < 1e-12f) {
+      if (!(ta > -1.0f && ta < float(n))) {
+        lo = n;
+        hi = -1;
+      }
+    } else {
+      const float u1 = (-1.0f - ta) / bt, u2 = (float(n) - ta) / bt;
+      // clamp before the integer conversion (nearly axis-parallel rays give huge values)
+      const float l1 = fminf(fmaxf(fminf(u1, u2) + float(g.hc), -4.0f), float(n + 4));
+      const float l2 = fminf(fmaxf(fmaxf(u1, u2) + float(g.hc), -4.0f), float(n + 4));
+      lo = max(0, (int)floorf(l1) - 2);
+      hi = min(n - 1, (int)ceilf(l2) + 2);
+    }
+    if (lo <= hi) {
+      atomicMin(&s_lo, lo);
+      atomicMax(&s_hi, hi);
+    }
+  }
+  __syncthreads();
+  const int lo = s_lo, hi = s_hi;
+  const T* img = (A.rows ? wP : wTP) + blockIdx.z * w_stride + (long)kPad * pitch + kPad;
+  T acc = T(0);
+  for (int L = lo; L <= hi; ++L) {
+    const T gl = fmaT(T(L) - g.hc, A.beta, g.hc);
+    T cf = fmaT(t, A.a, gl);
+    cf = fmin(fmax(cf, T(-1)), T(n));
+    const T c0 = floor(cf);
+    const T f = cf - c0;
+    const T* p = img + (long)L * pitch + (int)c0;
+    acc += (T(1) - f) * p[0] + f * p[1];
+  }
+  if (!live) return;
+  const T s = A.ds * acc;
+  const long idx = (long)k * g.nd + j;
+  if (MODE == 0) {
+    out[blockIdx.z * out_stride + idx] = s;
+  } else {
+    const int gate = gate0 + blockIdx.z;
+    const GateScalars<T> S = gs[gate];
+    const GatePtrs<T> P = gp[gate];
+    const T yv = P.y[idx];
+    const T yn = (yv + S.sigma * (s - P.d[idx])) * S.cy;
+    P.y[idx] = yn;
+    out[blockIdx.z * out_stride + idx] = yn - yv;   // dy of this slot
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a4: exact-transpose Joseph backprojection, one thread per pixel. For each
+// angle the pixel receives from the (at most 2) rays whose line crossing lies
+// within one pixel of it; the three candidates around the nearest bin are
+// weighted with the same crossing the forward kernel computes, so the matrix
+// entries are the forward's. Output into the interior of a padded image (or
+// an unpadded image when `padded` is 0).
+// grid (ceil(n/16), ceil(n/16), G), block (16, 16)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* __restrict__ ang,
+                                                    const T* __restrict__ sino, long sino_stride,
+                                                    T* __restrict__ out, long out_stride,
+                                                    int padded) {
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c >= g.n || r >= g.n) return;
+  const T* s = sino + blockIdx.z * sino_stride;
+  const T xc = T(c) - g.hc, yr = T(r) - g.hc;
+  const T fc = T(c), fr = T(r);
+  const int nd = g.nd;
+  T acc = T(0);
+  for (int k = 0; k < g.na; ++k) {
+    const AngleT<T> A = ang[k];
+    const T uline = A.rows ? yr : xc;
+    const T pos = A.rows ? fc : fr;
+    const T gl = fmaT(uline, A.beta, g.hc);
+    const T u = fmaT(pos - gl, A.ia, g.jc);
+    const int m = (int)rint(u);
+    const T* srow = s + (long)k * nd;
+    T part = T(0);
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int j = m + dj;
+      const T t = T(j) - g.jc;
+      const T cf = fmaT(t, A.a, gl);
+      const T w = fmax(T(0), T(1) - fabs(cf - pos));
+      const bool ok = (unsigned)j < (unsigned)nd;
+      const T v = srow[ok ? j : 0];
+      part = fmaT(ok ? w : T(0), v, part);
+    }
+    acc = fmaT(A.ds, part, acc);
+  }
+  if (padded)
+    out[blockIdx.z * out_stride + (long)(r + kPad) * g.pitch + (c + kPad)] = acc;
+  else
+    out[blockIdx.z * out_stride + (long)r * g.n + c] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// a5 (+ a6): transposed warp as a gather, summed over G gates, fused with the
+// dual-image updates of Algorithm 1 (iii) and the next primal step (i).
+// Output pixel q receives from the pixels p of a (2R+1)^2 window around the
+// inverse image of q; each candidate's weight on q is recomputed with the
+// forward warp's arithmetic (motion_pos, floor, the same products), so the
+// result is the exact transpose. Candidates in the zero border of the padded
+// input contribute zero.
+//   mode 0: out = sum_g D_g^T b_g                       (plain adjoint)
+//   mode 1: out += sum_g D_g^T b_g                      (accumulate)
+//   mode 2: z += dz; zbar = z + sum_g coef_g dz_g; optionally x = (x - tau zbar) cx
+// grid (ceil(n/16), ceil(n/16)), block (16, 16)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct UpdateArgs {
+  T* x;
+  T* z;
+  T* zbar;
+  T tau, cx;
+  int do_x;
+};
+
+template <typename T, int MODE, int R>
+__global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __restrict__ gm,
+                                               int gate0, int G,
+                                               const GateScalars<T>* __restrict__ gs,
+                                               const float* __restrict__ field, long field_stride,
+                                               long plane_stride, const short2* __restrict__ centres,
+                                               const T* __restrict__ bP, long b_stride,
+                                               T* __restrict__ out, UpdateArgs<T> ua) {
+  const int qc = blockIdx.x * 16 + threadIdx.x;
+  const int qr = blockIdx.y * 16 + threadIdx.y;
+  const int n = g.n, pitch = g.pitch;
+  if (qc >= n || qr >= n) return;
+  const long origin = (long)kPad * pitch + kPad;
+  T dz = T(0), dzb = T(0);
+  for (int gi = 0; gi < G; ++gi) {
+    const int gate = gate0 + gi;
+    const GateMotion<T> M = gm[gate];
+    const T* b = bP + gi * b_stride + origin;
+    T part = T(0);
+    if (M.kind == 0) {
+      part = b[(long)qr * pitch + qc];
+    } else {
+      const float* ux = field + gate * field_stride + origin;
+      const float* uy = ux + plane_stride;
+      int cr, cc;
+      window_centre(M, centres, gate, n, g.hc, qr, qc, cr, cc);
+#pragma unroll
+      for (int ddy = -R; ddy <= R; ++ddy) {
+#pragma unroll
+        for (int ddx = -R; ddx <= R; ++ddx) {
+          const int pr = cr + ddy, pc = cc + ddx;
+          T px, py;
+          motion_pos(M, ux, uy, pitch, g.hc, pr, pc, px, py);
+          const T fc0 = floor(px), fr0 = floor(py);
+          const T fx = px - fc0, fy = py - fr0;
+          const int c0 = (int)fmax(fmin(fc0, T(n + 8)), T(-8));
+          const int r0 = (int)fmax(fmin(fr0, T(n + 8)), T(-8));
+          const T wx = (qc == c0) ? (T(1) - fx) : ((qc == c0 + 1) ? fx : T(0));
+          const T wy = (qr == r0) ? (T(1) - fy) : ((qr == r0 + 1) ? fy : T(0));
+          part = fmaT(wx * wy, b[(long)pr * pitch + pc], part);
+        }
+      }
+    }
+    dz += part;
+    if (MODE == 2) dzb = fmaT(gs[gate].coef, part, dzb);
+  }
+  const long q = (long)qr * n + qc;
+  if (MODE == 0) {
+    out[q] = dz;
+  } else if (MODE == 1) {
+    out[q] += dz;
+  } else {
+    const T z = ua.z[q] + dz;
+    const T zb = z + dzb;
+    ua.z[q] = z;
+    ua.zbar[q] = zb;
+    if (ua.do_x) ua.x[q] = (ua.x[q] - ua.tau * zb) * ua.cx;
+  }
+}
+
+// Algorithm 1 step (i) on its own: x = (x - tau zbar) cx.
+template <typename T>
+__global__ __launch_bounds__(256) void k_xstep(long count, T* __restrict__ x,
+                                               const T* __restrict__ zbar, T tau, T cx) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) x[i] = (x[i] - tau * zbar[i]) * cx;
+}
+
+// Copy an unpadded image into the interior of a padded one (converting type).
+template <typename Ts, typename Td>
+__global__ __launch_bounds__(256) void k_to_padded(int n, int pitch, const Ts* __restrict__ src,
+                                                   Td* __restrict__ dst) {
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c < n && r < n) dst[(long)(r + kPad) * pitch + c + kPad] = Td(src[(long)r * n + c]);
+}
+
+template <typename Ts, typename Td>
+__global__ __launch_bounds__(256) void k_convert(long count, const Ts* __restrict__ src,
+                                                 Td* __restrict__ dst) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) dst[i] = Td(src[i]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scale(long count, T* __restrict__ v, double s) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i < count) v[i] = T(double(v[i]) * s);
+}
+
+// ---------------------------------------------------------------------------
+// FP64 reductions, deterministic: a fixed grid of kRedBlocks blocks, each
+// folding a fixed strided subset, then one block folding the partials in
+// order. op 0: sum a^2; op 1: sum a b; op 2: sum (a - b)^2.
+// ---------------------------------------------------------------------------
+constexpr int kRedBlocks = 512;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+  }
+  return s;
+}
+
+template <typename Ta, typename Tb, int OP>
+__global__ __launch_bounds__(256) void k_reduce_partial(long count, const Ta* __restrict__ a,
+                                                        const Tb* __restrict__ b,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)kRedBlocks * 256) {
+    const double va = double(a[i]);
+    if (OP == 0) acc = __builtin_fma(va, va, acc);
+    if (OP == 1) acc = __builtin_fma(va, double(b[i]), acc);
+    if (OP == 2) {
+      const double dd = va - double(b[i]);
+      acc = __builtin_fma(dd, dd, acc);
+    }
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// Sums kRedBlocks partials in a fixed order into out[slot].
+__global__ __launch_bounds__(256) void k_reduce_final(const double* __restrict__ partial,
+                                                      double* __restrict__ out, int slot) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += 256) acc += partial[i];
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) out[slot] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Set-up of the transposed warp for displacement fields: the centre of each
+// output pixel's gather window (an estimate of phi^{-1}(q) by fixed-point
+// iteration on the bilinearly interpolated field), then a verification that
+// every nonzero forward weight falls inside its window (the largest Chebyshev
+// distance found is returned through `need`).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float field_at(const float* __restrict__ u, int n, int pitch, float x,
+                                          float y) {
+  x = fminf(fmaxf(x, 0.0f), float(n - 1));
+  y = fminf(fmaxf(y, 0.0f), float(n - 1));
+  const int c0 = min((int)x, n - 2 < 0 ? 0 : n - 2), r0 = min((int)y, n - 2 < 0 ? 0 : n - 2);
+  const float fx = x - c0, fy = y - r0;
+  const int c1 = min(c0 + 1, n - 1), r1 = min(r0 + 1, n - 1);
+  const float v00 = u[(long)r0 * pitch + c0], v01 = u[(long)r0 * pitch + c1];
+  const float v10 = u[(long)r1 * pitch + c0], v11 = u[(long)r1 * pitch + c1];
+  return (1 - fy) * ((1 - fx) * v00 + fx * v01) + fy * ((1 - fx) * v10 + fx * v11);
+}
+
+__global__ __launch_bounds__(256) void k_field_centres(int n, int pitch, const float* __restrict__ fieldP,
+                                                       long plane_stride, short2* __restrict__ centres) {
+  const int qc = blockIdx.x * 16 + threadIdx.x;
+  const int qr = blockIdx.y * 16 + threadIdx.y;
+  if (qc >= n || qr >= n) return;
+  const long origin = (long)kPad * pitch + kPad;
+  const float* ux = fieldP + origin;
+  const float* uy = ux + plane_stride;
+  float vx = float(qc) - ux[(long)qr * pitch + qc];
+  float vy = float(qr) - uy[(long)qr * pitch + qc];
+  for (int it = 0; it < 12; ++it) {
+    const float nx = float(qc) - field_at(ux, n, pitch, vx, vy);
+    const float ny = float(qr) - field_at(uy, n, pitch, vx, vy);
+    vx = nx;
+    vy = ny;
+  }
+  int cc = (int)rintf(fminf(fmaxf(vx, -1.0f), float(n)));
+  int cr = (int)rintf(fminf(fmaxf(vy, -1.0f), float(n)));
+  centres[(long)qr * n + qc] = make_short2((short)cc, (short)cr);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_window_check(Geo<T> g, const GateMotion<T>* __restrict__ gm,
+                                                      int gate, const float* __restrict__ field,
+                                                      long field_stride, long plane_stride,
+                                                      const short2* __restrict__ centres,
+                                                      int* __restrict__ need) {
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  const int n = g.n, pitch = g.pitch;
+  if (c >= n || r >= n) return;
+  const GateMotion<T> M = gm[gate];
+  if (M.kind == 0) return;
+  const long origin = (long)kPad * pitch + kPad;
+  const float* ux = field + gate * field_stride + origin;
+  const float* uy = ux + plane_stride;
+  T px, py;
+  motion_pos(M, ux, uy, pitch, g.hc, r, c, px, py);
+  const T fc0 = floor(px), fr0 = floor(py);
+  const T fx = px - fc0, fy = py - fr0;
+  const int c0 = (int)fmax(fmin(fc0, T(n + 8)), T(-8));
+  const int r0 = (int)fmax(fmin(fr0, T(n + 8)), T(-8));
+  int worst = 0;
+  for (int a = 0; a < 2; ++a) {
+    for (int bb = 0; bb < 2; ++bb) {
+      const int qr = r0 + a, qc = c0 + bb;
+      if ((unsigned)qr >= (unsigned)n || (unsigned)qc >= (unsigned)n) continue;
+      const T wx = bb ? fx : T(1) - fx;
+      const T wy = a ? fy : T(1) - fy;
+      if (wx * wy == T(0)) continue;
+      int cr, cc;
+      window_centre(M, centres, gate, n, g.hc, qr, qc, cr, cc);
+      worst = max(worst, max(abs(c - cc), abs(r - cr)));
+    }
+  }
+  if (worst > 0) atomicMax(need, worst);
+}
+
+}  // namespace mcr

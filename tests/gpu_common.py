@@ -1,0 +1,80 @@
+"""Shared set-up of the GPU tests: problems whose inputs are rounded to float32
+once and then fed to both the HIP library and the FP64 oracle."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import spdhg as ospdhg
+from oracle.operators import GatedOperators
+
+# Bars (stated per operator application and after 50 epochs, FP32 against FP64)
+F32_OP = 1e-5
+F32_EPOCHS = 1e-4
+F64_OP = 1e-12
+
+
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def f32(a):
+    return np.asarray(a, dtype=np.float32).astype(np.float64)
+
+
+class Problem:
+    """Geometry, motion, phantom and gated data (all float32-representable)."""
+
+    def __init__(self, n, na, nd, N, kind, alpha=1e-3, seed=0, max_rot=8.0, max_shift=10.0,
+                 phantom="ellipses", field_scale=1.0):
+        self.n, self.na, self.nd, self.N, self.kind, self.alpha = n, na, nd, N, kind, alpha
+        if kind == "rigid":
+            self.params = synth.rigid_params(N, seed + 1, max_rot, max_shift)
+        elif kind == "field":
+            self.params = (synth.dilatation_fields(n, N, seed + 1) * np.float32(field_scale)).astype(np.float32)
+        else:
+            self.params = None
+        self.ops = GatedOperators(n, na, nd, kind, None if self.params is None else self.params.astype(np.float64),
+                                  n_gates=N)
+        img = synth.chest_phantom(n, seed) if phantom == "chest" else synth.ellipse_phantom(n, seed)
+        self.x_true = f32(img)
+        self._seed = seed
+
+    @functools.cached_property
+    def d(self):
+        d = ospdhg.make_data(self.ops, self.x_true, synth.unit_noise((self.N, self.na, self.nd), self._seed + 2))
+        return [f32(v) for v in d]
+
+    def motion(self):
+        out = []
+        for i in range(self.N):
+            if self.kind == "rigid":
+                out.append(("rigid", tuple(float(v) for v in self.params[i])))
+            elif self.kind == "field":
+                out.append(("field", torch.from_numpy(self.params[i]).cuda()))
+            else:
+                out.append("identity")
+        return out
+
+    def handle(self, dtype=torch.float32):
+        from paper_2410_10503_amd import Handle
+        return Handle(self.n, self.na, self.nd, self.motion(), dtype=dtype)

@@ -1,0 +1,105 @@
+"""The C ABI on the CPU: the library loads, exports every function that
+include/mcr.h declares, validates arguments before touching the device, and
+its host step-size helper agrees with the oracle's rule."""
+import ctypes
+import math
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2410_10503_amd import _lib
+from oracle import spdhg
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def test_exports_every_declared_function(lib):
+    declared = _lib.header_functions()
+    assert len(declared) >= 19
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    for f in declared:
+        assert hasattr(lib, f)
+
+
+def test_binding_declares_every_function():
+    declared = set(_lib.header_functions()) - {"mcr_last_error"}
+    assert declared == set(_lib.SIGNATURES)
+
+
+@pytest.mark.parametrize("N,alpha", [(1, 1e-3), (4, 1e-2), (16, 1e-3)])
+def test_step_sizes_match_oracle(lib, N, alpha):
+    rng = np.random.default_rng(N)
+    norms = list(3.7e5 * (1 + 0.03 * rng.random(N)))
+    sig = (ctypes.c_double * N)()
+    tau, th, rate = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    arr = (ctypes.c_double * N)(*norms)
+    _lib.check(lib.mcr_step_sizes(0, N, arr, alpha, sig, ctypes.byref(tau), ctypes.byref(th), ctypes.byref(rate)))
+    s_o, t_o, th_o, rho = spdhg.step_sizes_spdhg(norms, alpha, N)
+    np.testing.assert_allclose(list(sig), s_o, rtol=1e-14)
+    assert math.isclose(tau.value, t_o, rel_tol=1e-14) and math.isclose(th.value, th_o, rel_tol=1e-14)
+    assert math.isclose(rate.value, spdhg.rate(max(norms) / (alpha * N), N), rel_tol=1e-12)
+    stacked = (ctypes.c_double * 1)(N * 3.8e5)
+    _lib.check(lib.mcr_step_sizes(1, N, stacked, alpha, sig, ctypes.byref(tau), ctypes.byref(th), ctypes.byref(rate)))
+    s_o, t_o, th_o, rho = spdhg.step_sizes_pdhg(N * 3.8e5, alpha, N)
+    np.testing.assert_allclose(list(sig), s_o, rtol=1e-14)
+    assert math.isclose(tau.value, t_o, rel_tol=1e-14) and math.isclose(th.value, th_o, rel_tol=1e-14)
+    assert math.isclose(rate.value, spdhg.rate(N * 3.8e5 / (alpha * N), 1), rel_tol=1e-12)
+
+
+def _create(lib, geo, n_gates, motion, dtype=0):
+    h = ctypes.c_void_p()
+    st = lib.mcr_create(ctypes.byref(geo) if geo is not None else None, n_gates, motion, dtype, None,
+                        ctypes.byref(h))
+    return st, h
+
+
+def _motions(*ms):
+    arr = (_lib.Motion * len(ms))()
+    for i, m in enumerate(ms):
+        arr[i] = m
+    return arr
+
+
+RIGID = _lib.Motion(_lib.MOTION_RIGID, (ctypes.c_double * 3)(0.1, 1.0, -2.0), None)
+
+
+@pytest.mark.parametrize("geo,ng,mot,dtype,needle", [
+    (None, 1, _motions(RIGID), 0, "geometry"),
+    (_lib.Geometry(0, 10, 10), 1, _motions(RIGID), 0, "n = 0"),
+    (_lib.Geometry(16, 0, 10), 1, _motions(RIGID), 0, "n_angles"),
+    (_lib.Geometry(16, 10, 20000), 1, _motions(RIGID), 0, "n_det"),
+    (_lib.Geometry(16, 10, 24), 0, _motions(RIGID), 0, "n_gates"),
+    (_lib.Geometry(16, 10, 24), 1, None, 0, "motion is null"),
+    (_lib.Geometry(16, 10, 24), 1, _motions(_lib.Motion(7, (ctypes.c_double * 3)(0, 0, 0), None)), 0, "kind"),
+    (_lib.Geometry(16, 10, 24), 1, _motions(_lib.Motion(1, (ctypes.c_double * 3)(float("nan"), 0, 0), None)), 0,
+     "not finite"),
+    (_lib.Geometry(16, 10, 24), 1, _motions(_lib.Motion(2, (ctypes.c_double * 3)(0, 0, 0), None)), 0, "field"),
+    (_lib.Geometry(16, 10, 24), 1, _motions(RIGID), 5, "dtype"),
+])
+def test_create_rejects_bad_arguments_before_device_work(lib, geo, ng, mot, dtype, needle):
+    st, h = _create(lib, geo, ng, mot, dtype)
+    assert st == _lib.MCR_ERR_ARG
+    assert not h.value
+    assert needle in lib.mcr_last_error().decode()
+
+
+def test_null_handle_is_an_argument_error(lib):
+    assert lib.mcr_apply_Ai(None, 0, None, None) == _lib.MCR_ERR_ARG
+    assert b"null handle" in lib.mcr_last_error()
+    assert lib.mcr_spdhg_epoch(None, None, None, 1.0, None, 1.0, 1.0, None, None) == _lib.MCR_ERR_ARG
+    assert lib.mcr_destroy(None) == _lib.MCR_OK
+
+
+@pytest.mark.parametrize("algo,N,norms,alpha", [(2, 1, [1.0], 1.0), (0, 0, [1.0], 1.0), (0, 2, [1.0, -1.0], 1.0),
+                                                (1, 2, [float("inf")], 1.0), (0, 1, [1.0], 0.0)])
+def test_step_sizes_reject_bad_arguments(lib, algo, N, norms, alpha):
+    sig = (ctypes.c_double * max(N, 1))()
+    assert lib.mcr_step_sizes(algo, N, (ctypes.c_double * len(norms))(*norms), alpha, sig, None, None,
+                              None) == _lib.MCR_ERR_ARG

@@ -1,0 +1,200 @@
+"""GPU parity of Algorithm 1 (SPDHG and PDHG epochs), the FP64 norms,
+objective and duality gap against the FP64 oracle on the same float32-rounded
+inputs and the same gate sequences."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import F32_EPOCHS, F64_OP, Problem, dev, f32, host, need_gpu, rel
+import synth
+from oracle import spdhg as osp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _to_dev(st, dtype):
+    from paper_2410_10503_amd import ReconState
+    return ReconState(dev(st.x, dtype), [dev(v, dtype) for v in st.y], dev(st.z, dtype), dev(st.zbar, dtype))
+
+
+def _compare(gst, ost, bar):
+    assert rel(host(gst.x), ost.x) < bar
+    assert rel(host(gst.z), ost.z) < bar
+    assert rel(host(gst.zbar), ost.zbar) < bar
+    yg = np.concatenate([host(v).ravel() for v in gst.y])
+    yo = np.concatenate([v.ravel() for v in ost.y])
+    assert rel(yg, yo) < bar
+
+
+def _steps(P, norm_scale=1.0):
+    # step sizes from a fixed norm estimate (parity does not depend on them)
+    nA = 2.0 * P.na * P.n * norm_scale
+    sig, tau, th, _ = osp.step_sizes_spdhg([nA] * P.N, P.alpha, P.N)
+    return sig, tau, th, [1.0 / P.N] * P.N
+
+
+def test_spdhg_fp64_128_rigid4_20_epochs():
+    # 128^2, 120 angles x 182 bins, 4 rigid gates (5 deg, 4 px), alpha = 1e-2, 20 epochs, FP64
+    P = Problem(128, 120, 182, 4, "rigid", alpha=1e-2, max_rot=5.0, max_shift=4.0)
+    h = P.handle(torch.float64)
+    sig, tau, th, p = _steps(P)
+    ost = osp.State.zeros(P.n, P.N, P.na, P.nd)
+    gst = h.zero_state()
+    d64 = [dev(v, torch.float64) for v in P.d]
+    for e in range(20):
+        seq = synth.gate_sequence(P.N, 3, e)
+        ost = osp.spdhg(P.ops, ost, P.d, P.alpha, sig, tau, th, p, seq)
+        h.spdhg_epoch(gst, d64, P.alpha, sig, tau, th, p, seq)
+    _compare(gst, ost, 1e-11)
+
+
+@pytest.mark.parametrize("kind", ["rigid", "field"])
+def test_spdhg_and_pdhg_fp32_50_epochs(kind):
+    P = Problem(64, 96, 92, 4, kind, alpha=1e-3, field_scale=1.0)
+    h = P.handle(torch.float32)
+    d32 = [dev(v, torch.float32) for v in P.d]
+    sig, tau, th, p = _steps(P)
+    ost = osp.State.zeros(P.n, P.N, P.na, P.nd)
+    gst = h.zero_state()
+    for e in range(50):
+        seq = synth.gate_sequence(P.N, 3, e)
+        ost = osp.spdhg(P.ops, ost, P.d, P.alpha, sig, tau, th, p, seq)
+        h.spdhg_epoch(gst, d32, P.alpha, sig, tau, th, p, seq)
+    _compare(gst, ost, F32_EPOCHS)
+    sig, tau, th, _ = osp.step_sizes_pdhg(P.N * 2.0 * P.na * P.n, P.alpha, P.N)
+    ost = osp.State.zeros(P.n, P.N, P.na, P.nd)
+    gst = h.zero_state()
+    for e in range(50):
+        ost = osp.pdhg(P.ops, ost, P.d, P.alpha, sig, tau, th)
+        h.pdhg_epoch(gst, d32, P.alpha, sig, tau, th)
+    _compare(gst, ost, F32_EPOCHS)
+
+
+def test_pdhg_equals_spdhg_single_gate_bitwise():
+    P = Problem(96, 72, 140, 1, "rigid")
+    h = P.handle(torch.float32)
+    d32 = [dev(v, torch.float32) for v in P.d]
+    sig, tau, th, _ = osp.step_sizes_pdhg(2.0 * P.na * P.n, P.alpha, 1)
+    a, b = h.zero_state(), h.zero_state()
+    for _ in range(6):
+        h.pdhg_epoch(a, d32, P.alpha, sig, tau, th)
+    h.spdhg_iterate(b, d32, P.alpha, sig, tau, th, [1.0], [0] * 6)
+    for u, v in [(a.x, b.x), (a.z, b.z), (a.zbar, b.zbar), (a.y[0], b.y[0])]:
+        assert torch.equal(u, v)
+
+
+def test_resume_equals_uninterrupted():
+    # 2 epochs in one call == the same iterations split over calls (the state is
+    # the checkpoint), bit for bit
+    P = Problem(64, 48, 92, 5, "field")
+    h = P.handle(torch.float32)
+    d32 = [dev(v, torch.float32) for v in P.d]
+    sig, tau, th, p = _steps(P)
+    seq = list(synth.gate_sequence(5, 7, 0)) + list(synth.gate_sequence(5, 7, 1))
+    a, b = h.zero_state(), h.zero_state()
+    h.spdhg_iterate(a, d32, P.alpha, sig, tau, th, p, seq)
+    h.spdhg_iterate(b, d32, P.alpha, sig, tau, th, p, seq[:3])
+    c = b.clone()
+    h.spdhg_iterate(c, d32, P.alpha, sig, tau, th, p, seq[3:])
+    for u, v in [(a.x, c.x), (a.z, c.z), (a.zbar, c.zbar)] + list(zip(a.y, c.y)):
+        assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("kind", ["rigid", "field"])
+def test_power_norms_objective_gap(kind):
+    P = Problem(48, 60, 70, 3, kind, alpha=0.5)
+    for dtype in (torch.float32, torch.float64):
+        h = P.handle(dtype)
+        v0 = f32(synth.random_image(P.n, 21))
+        v0d = dev(v0, torch.float64)
+        for g in range(P.N):
+            lam, it = h.power_norm_sq(g, v0d, max_iter=400, rtol=1e-13)
+            ref, _ = osp.gate_norm_sq(P.ops, g, v0, rtol=1e-13, max_iter=400)
+            assert abs(lam - ref) <= 1e-10 * ref
+        lam, _ = h.power_norm_sq(-1, v0d, max_iter=400, rtol=1e-13)
+        ref, _ = osp.stacked_norm_sq(P.ops, v0, rtol=1e-13, max_iter=400)
+        assert abs(lam - ref) <= 1e-10 * ref
+        # objective and gap of a random state, in FP64 on the device
+        x = f32(synth.random_image(P.n, 5))
+        ys = [f32(v) * 0.01 for v in synth.random_sinograms(P.N, P.na, P.nd, 6)]
+        dd = [dev(v, dtype) for v in P.d]
+        obj = h.objective(dev(x, dtype), dd, P.alpha)
+        assert abs(obj - osp.objective(P.ops, x, P.d, P.alpha)) <= F64_OP * abs(obj)
+        from paper_2410_10503_amd import ReconState
+        st = ReconState(dev(x, dtype), [dev(v, dtype) for v in ys], dev(x, dtype), dev(x, dtype))
+        gap = h.duality_gap(st, dd, P.alpha)
+        ref = osp.duality_gap(P.ops, x, ys, P.d, P.alpha)
+        assert abs(gap - ref) <= 1e-11 * abs(ref)
+
+
+def test_gpu_converges_to_saddle_point_in_paper_regime():
+    # kappa = |A|^2 / alpha = 70 (Section III); the FP64 GPU iterates reach the
+    # oracle's saddle point (a linear solve) and SPDHG is ahead of PDHG
+    P = Problem(20, 30, 30, 4, "rigid", max_rot=8.0, max_shift=1.5)
+    h = P.handle(torch.float64)
+    v0 = dev(f32(synth.random_image(P.n, 99)), torch.float64)
+    plain = Problem(20, 30, 30, 1, "identity").handle(torch.float64)
+    normA, _ = plain.power_norm_sq(0, v0)
+    alpha = normA / 70.0
+    d = [dev(v, torch.float64) for v in P.d]
+    xs, ys = osp.saddle_point(P.ops, P.d, alpha, dense=True)
+    gn = [h.power_norm_sq(g, v0)[0] for g in range(P.N)]
+    sn = h.power_norm_sq(-1, v0)[0]
+
+    def dist(st):
+        return float(np.sum((host(st.x) - xs) ** 2) + sum(np.sum((host(a) - b) ** 2) for a, b in zip(st.y, ys)))
+
+    from paper_2410_10503_amd import step_sizes
+    sig, tau, th, rate_p = step_sizes("pdhg", [sn], alpha, P.N)
+    st = h.zero_state()
+    dp = []
+    for e in range(30):
+        h.pdhg_epoch(st, d, alpha, sig, tau, th)
+        dp.append(dist(st))
+    sig, tau, th, rate_s = step_sizes("spdhg", gn, alpha, P.N)
+    ds = []
+    for seed in range(4):
+        st = h.zero_state()
+        cur = []
+        for e in range(30):
+            h.spdhg_epoch(st, d, alpha, sig, tau, th, [1 / P.N] * P.N, synth.gate_sequence(P.N, seed, e))
+            cur.append(dist(st))
+        ds.append(cur)
+    ds = np.mean(ds, axis=0)
+    assert dp[-1] < 1e-3 * dp[0] and ds[-1] < 1e-3 * ds[0]
+    assert ds[-1] < dp[-1]
+    slope_p = np.polyfit(np.arange(6, 30), np.log(dp[6:]), 1)[0]
+    assert slope_p <= np.log(rate_p) + 0.02
+
+
+def test_full_size_one_iteration_from_random_state():
+    # 512^2, 720 x 730, 16 non-rigid gates: one SPDHG iteration from a random
+    # state, every element of x, y_i, z, z-bar against the oracle
+    P = Problem(512, 720, 730, 16, "field", phantom="chest")
+    h = P.handle(torch.float32)
+    rng = np.random.default_rng(3)
+    x = f32(P.x_true + 0.1 * rng.standard_normal((512, 512)))
+    z = f32(0.01 * rng.standard_normal((512, 512)))
+    zb = f32(z + 0.001 * rng.standard_normal((512, 512)))
+    ys = [np.zeros((720, 730)) for _ in range(16)]
+    g = 13
+    ys[g] = f32(0.01 * rng.standard_normal((720, 730)))
+    d = [np.zeros((720, 730)) for _ in range(16)]
+    d[g] = f32(P.ops.project(P.x_true)) # a data-like sinogram for the drawn gate
+    alpha, tau, th = 1e-3, 0.8, 0.9
+    sig = [2e-3] * 16
+    p = [1 / 16] * 16
+    ost = osp.iterate(P.ops, osp.State(x, ys, z, zb), d, alpha, sig, tau, th, p, [g])
+    from paper_2410_10503_amd import ReconState
+    gst = ReconState(dev(x, torch.float32), [dev(v, torch.float32) for v in ys], dev(z, torch.float32),
+                     dev(zb, torch.float32))
+    h.spdhg_iterate(gst, [dev(v, torch.float32) for v in d], alpha, sig, tau, th, p, [g])
+    assert rel(host(gst.x), ost.x) < 1e-5
+    assert rel(host(gst.y[g]), ost.y[g]) < 1e-5
+    assert rel(host(gst.z) - z, ost.z - z) < 1e-5
+    assert rel(host(gst.zbar) - z, ost.zbar - z) < 1e-5

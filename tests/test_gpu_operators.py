@@ -1,0 +1,173 @@
+"""GPU parity of the operators (warp, projector, their transposes, A_i and
+A_i^*) against the FP64 oracle, element by element, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import F32_OP, F64_OP, Problem, dev, f32, host, need_gpu, rel
+import synth
+from oracle import projector, warp
+
+pytestmark = pytest.mark.gpu
+
+DT = [(torch.float32, F32_OP), (torch.float64, F64_OP)]
+# (n, n_angles, n_det): several detector tiles with a ragged tail, the 45/135
+# degree ties present (n_angles divisible by 4), odd and even sizes
+GEOMS = [(64, 96, 92), (75, 40, 300), (128, 120, 182)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+@pytest.mark.parametrize("dtype,bar", DT)
+@pytest.mark.parametrize("geom", GEOMS)
+def test_project_and_backproject(dtype, bar, geom):
+    n, na, nd = geom
+    P = Problem(n, na, nd, 1, "identity")
+    h = P.handle(dtype)
+    x = f32(synth.ellipse_phantom(n, 3)) + f32(synth.random_image(n, 4)) * 0.1
+    y = f32(synth.random_sinograms(1, na, nd, 5)[0])
+    s = host(h.project(dev(x, dtype)))
+    b = host(h.backproject(dev(y, dtype)))
+    assert rel(s, projector.forward(x, na, nd)) < bar
+    assert rel(b, projector.adjoint(y, n)) < bar
+
+
+@pytest.mark.parametrize("dtype,bar", DT)
+@pytest.mark.parametrize("kind", ["rigid", "field"])
+def test_warp_and_transpose(dtype, bar, kind):
+    n = 96
+    P = Problem(n, 8, 140, 4, kind, field_scale=2.0)
+    h = P.handle(dtype)
+    x = f32(synth.ellipse_phantom(n, 7))
+    b = f32(synth.random_image(n, 8))
+    for i in range(P.N):
+        pos = P.ops.pos[i]
+        w = host(h.warp(i, dev(x, dtype)))
+        wt = host(h.warp_adjoint(i, dev(b, dtype)))
+        if P.kind == "field" and i == 0:
+            np.testing.assert_array_equal(w, x)        # gate 0 of the field model is the identity
+        assert rel(w, warp.warp(x, *pos)) < bar
+        assert rel(wt, warp.warp_adjoint(b, *pos)) < bar
+
+
+@pytest.mark.parametrize("dtype,bar", DT)
+@pytest.mark.parametrize("kind", ["identity", "rigid", "field"])
+def test_apply_Ai_pair(dtype, bar, kind):
+    n, na, nd = 80, 60, 116
+    P = Problem(n, na, nd, 3, kind, field_scale=1.5)
+    h = P.handle(dtype)
+    x = f32(synth.ellipse_phantom(n, 1))
+    y = f32(synth.random_sinograms(1, na, nd, 2)[0])
+    for i in range(P.N):
+        assert rel(host(h.apply_Ai(i, dev(x, dtype))), P.ops.A(i, x)) < bar
+        assert rel(host(h.apply_Ai_adjoint(i, dev(y, dtype))), P.ops.At(i, y)) < bar
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 2e-6), (torch.float64, 1e-13)])
+@pytest.mark.parametrize("kind", ["rigid", "field"])
+def test_dot_product(dtype, tol, kind):
+    n, na, nd = 128, 120, 182
+    P = Problem(n, na, nd, 2, kind)
+    h = P.handle(dtype)
+    x = dev(f32(synth.random_image(n, 11)), dtype)
+    y = dev(f32(synth.random_sinograms(1, na, nd, 12)[0]), dtype)
+    for i in range(P.N):
+        ax = h.apply_Ai(i, x)
+        aty = h.apply_Ai_adjoint(i, y)
+        lhs = float(torch.sum(ax.double() * y.double()))
+        rhs = float(torch.sum(x.double() * aty.double()))
+        assert abs(lhs - rhs) <= tol * float(ax.double().norm() * y.double().norm())
+
+
+@pytest.mark.parametrize("kind", ["rigid", "field"])
+def test_matrix_16x16(kind):
+    # assemble the FP32 GPU forward and adjoint matrices column by column; the
+    # adjoint's entries are the forward's (the same floating-point weights)
+    n, na, nd = 16, 12, 24
+    P = Problem(n, na, nd, 1, kind, max_rot=20.0, max_shift=2.5, field_scale=0.4)
+    h = P.handle(torch.float32)
+    e = torch.zeros(n * n, device="cuda")
+    mf = np.zeros((na * nd, n * n))
+    for q in range(n * n):
+        e.zero_()
+        e[q] = 1
+        mf[:, q] = host(h.apply_Ai(0, e.view(n, n))).ravel()
+    es = torch.zeros(na * nd, device="cuda")
+    ma = np.zeros((n * n, na * nd))
+    for q in range(na * nd):
+        es.zero_()
+        es[q] = 1
+        ma[:, q] = host(h.apply_Ai_adjoint(0, es.view(na, nd))).ravel()
+    scale = np.abs(mf).max()
+    assert np.abs(ma - mf.T).max() <= 1e-6 * scale
+    # both against the oracle's dense matrix of A D_0
+    ident = np.eye(n * n)
+    mo = np.stack([P.ops.A(0, ident[q].reshape(n, n)).ravel() for q in range(n * n)], axis=1)
+    assert np.abs(mf - mo).max() <= 2e-6 * scale
+
+
+def test_determinism():
+    n, na, nd = 128, 120, 182
+    P = Problem(n, na, nd, 2, "field")
+    h = P.handle(torch.float32)
+    x = dev(f32(synth.random_image(n, 1)), torch.float32)
+    y = dev(f32(synth.random_sinograms(1, na, nd, 2)[0]), torch.float32)
+    a1, a2 = h.apply_Ai(1, x), h.apply_Ai(1, x)
+    b1, b2 = h.apply_Ai_adjoint(1, y), h.apply_Ai_adjoint(1, y)
+    assert torch.equal(a1, a2) and torch.equal(b1, b2)
+
+
+def test_full_size_field_gate():
+    # 512^2, 720 angles x 730 bins, the headline chest phantom and one
+    # non-rigid gate, in the configuration the benchmark times
+    P = Problem(512, 720, 730, 16, "field", phantom="chest")
+    h = P.handle(torch.float32)
+    i = 11
+    x = P.x_true
+    s = host(h.apply_Ai(i, dev(x, torch.float32)))
+    s_ref = P.ops.A(i, x)
+    assert rel(s, s_ref) < F32_OP
+    y = f32(synth.random_sinograms(1, 720, 730, 9)[0])
+    b = host(h.apply_Ai_adjoint(i, dev(y, torch.float32)))
+    assert rel(b, P.ops.At(i, y)) < F32_OP
+    assert h.info()["window_radius"] == 1
+
+
+def test_full_size_rigid_samples():
+    # all 16 rigid gates at 512^2: sampled rays of A_i x and sampled pixels of
+    # D_i^T b against the oracle, one by one
+    P = Problem(512, 720, 730, 16, "rigid")
+    h = P.handle(torch.float32)
+    x = P.x_true
+    xd = dev(x, torch.float32)
+    rng = np.random.default_rng(0)
+    b = f32(synth.random_image(512, 3))
+    for i in range(16):
+        s = host(h.apply_Ai(i, xd))
+        w = warp.warp(x, *P.ops.pos[i])
+        for _ in range(6):
+            k, j = int(rng.integers(720)), int(rng.integers(730))
+            ref = projector.ray_sum(w, 720, 730, k, j)
+            assert abs(s[k, j] - ref) <= 1e-5 * max(1.0, abs(ref)) + 1e-5 * np.abs(s).max()
+        wt = host(h.warp_adjoint(i, dev(b, torch.float32)))
+        assert rel(wt, warp.warp_adjoint(b, *P.ops.pos[i])) < F32_OP
+
+
+def test_argument_errors():
+    from paper_2410_10503_amd import McrError
+    P = Problem(32, 20, 48, 2, "rigid")
+    h = P.handle(torch.float32)
+    x = torch.zeros(32, 32, device="cuda")
+    with pytest.raises(McrError, match="gate 2 out of range"):
+        h.apply_Ai(2, x)
+    st = h.zero_state()
+    d = [torch.zeros(20, 48, device="cuda") for _ in range(2)]
+    with pytest.raises(McrError, match="p\\[1\\]"):
+        h.spdhg_iterate(st, d, 1.0, [1.0, 1.0], 1.0, 0.5, [0.5, 1.5], [0])
+    with pytest.raises(McrError, match="sigma\\[0\\]"):
+        h.spdhg_iterate(st, d, 1.0, [float("nan"), 1.0], 1.0, 0.5, [0.5, 0.5], [0])
+    with pytest.raises(McrError, match="alpha"):
+        h.pdhg_epoch(st, d, -1.0, [1.0, 1.0], 1.0, 0.5)
