@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mcr_kernels.h"
@@ -54,6 +55,7 @@ template <typename T>
 struct Work {
   bool ready = false;
   AngleT<T>* ang = nullptr;          // [n_angles]
+  AngleFx* angfx = nullptr;          // [n_angles] (float workspace only)
   GateMotion<T>* motion = nullptr;   // [N + 1]; entry N is the identity
   GateScalars<T>* scalars = nullptr; // [N]
   GatePtrs<T>* ptrs = nullptr;       // [N]
@@ -202,19 +204,51 @@ GateMotion<T> gate_motion(const mcr_handle* h, int gate) {
   m.kind = mo.kind;
   m.radius = h->radius[gate];
   if (mo.kind == MCR_MOTION_RIGID) {
-    const double c = std::cos(mo.rigid[0]), s = std::sin(mo.rigid[0]);
-    m.m00 = T(c);
-    m.m01 = T(-s);
-    m.m10 = T(s);
-    m.m11 = T(c);
-    m.bx = T(hc + mo.rigid[1]);
-    m.by = T(hc + mo.rigid[2]);
+    const double phi = mo.rigid[0];
+    const double c = std::cos(phi), s = std::sin(phi);
+    const double sh = std::sin(0.5 * phi);
+    m.cm1 = T(-2.0 * sh * sh);  // cos - 1 without cancellation
+    m.sn = T(s);
+    m.tx = T(mo.rigid[1]);
+    m.ty = T(mo.rigid[2]);
     m.i00 = T(c);
     m.i01 = T(s);
     m.i10 = T(-s);
     m.i11 = T(c);
+    m.bx = T(hc + mo.rigid[1]);
+    m.by = T(hc + mo.rigid[2]);
   }
   return m;
+}
+
+// Fixed-point constants of the float32 projector pair (see AngleFx).
+std::vector<AngleFx> angle_table_fx(int n, int na, int nd) {
+  std::vector<AngleFx> v(na);
+  const double hc = (n - 1) / 2.0, jc = (nd - 1) / 2.0, one = 4294967296.0;
+  for (int k = 0; k < na; ++k) {
+    const double th = M_PI * k / na;
+    const double cs = std::cos(th), sn = std::sin(th);
+    const bool rows = (4L * k <= na) || (4L * k >= 3L * na);
+    const double a = rows ? 1.0 / cs : 1.0 / sn;
+    const double beta = rows ? -sn / cs : -cs / sn;
+    const double c0 = hc - jc * a - hc * beta;  // cf(j, L) = c0 + j a + L beta
+    const double ia = 1.0 / a;
+    AngleFx f{};
+    f.C0 = std::llround(c0 * one);
+    f.A = std::llround(a * one);
+    f.B = std::llround(beta * one);
+    f.U0 = std::llround(-c0 * ia * one);
+    f.P = std::llround(ia * one);
+    f.Q = std::llround(-beta * ia * one);
+    f.a = float(a);
+    f.beta = float(beta);
+    f.absa = float(std::fabs(a));
+    f.oma = float(1.0 - std::fabs(a));
+    f.ds = float(std::fabs(a));
+    f.rows = rows ? 1 : 0;
+    v[k] = f;
+  }
+  return v;
 }
 
 template <typename T>
@@ -249,6 +283,9 @@ mcr_status init_work(mcr_handle* h) {
   HIP_OK(hipEventCreateWithFlags(&w.pin_ev, hipEventDisableTiming));
   const std::vector<AngleT<T>> at = angle_table<T>(h->geo.n_angles);
   HIP_OK(hipMemcpyAsync(w.ang, at.data(), sizeof(AngleT<T>) * at.size(), hipMemcpyHostToDevice, h->stream));
+  STATUS_OK(dmalloc(h, (void**)&w.angfx, sizeof(AngleFx) * h->geo.n_angles));
+  const std::vector<AngleFx> af = angle_table_fx(h->geo.n, h->geo.n_angles, h->geo.n_det);
+  HIP_OK(hipMemcpyAsync(w.angfx, af.data(), sizeof(AngleFx) * af.size(), hipMemcpyHostToDevice, h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
   STATUS_OK(upload_motion<T>(h));
   w.ready = true;
@@ -302,8 +339,12 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   Work<T>& w = work<T>(h);
   Timed tm(h, MCR_KERNEL_PROJECT);
   dim3 grid(cdiv(h->geo.n_det, 256), h->geo.n_angles, G), block(256);
-  hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.ang, w.wP,
-                     w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+  if constexpr (std::is_same<T, float>::value)
+    hipLaunchKernelGGL((k_joseph_fwd_fx<MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.angfx, w.wP,
+                       w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+  else
+    hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.ang, w.wP,
+                       w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
   LAUNCH_OK();
   return MCR_OK;
 }
@@ -315,8 +356,12 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_BACKPROJECT);
   dim3 grid(cdiv(n, 16), cdiv(n, 16), G), block(16, 16);
-  hipLaunchKernelGGL(k_joseph_adj<T>, grid, block, 0, h->stream, geo_of<T>(h), w.ang, sino,
-                     sino_stride, out, out_stride, padded);
+  if constexpr (std::is_same<T, float>::value)
+    hipLaunchKernelGGL(k_joseph_adj_fx, grid, block, 0, h->stream, geo_of<T>(h), w.angfx, sino,
+                       sino_stride, out, out_stride, padded);
+  else
+    hipLaunchKernelGGL(k_joseph_adj<T>, grid, block, 0, h->stream, geo_of<T>(h), w.ang, sino,
+                       sino_stride, out, out_stride, padded);
   LAUNCH_OK();
   return MCR_OK;
 }

@@ -20,6 +20,7 @@ namespace mcr {
 
 constexpr int kPad = 4;          // zero border of padded images and fields
 constexpr int kMaxRadius = 3;    // largest gather window radius of D^T
+constexpr int kLineBlock = 16;   // block length of the two-level float sums
 
 // Per-angle constants of the Joseph projector, built in FP64 on the host.
 // Along the stepping line at offset u from the centre, ray t crosses the
@@ -34,14 +35,39 @@ struct AngleT {
   int pad_;
 };
 
-// Motion of one gate. Rigid forward map in index coordinates, with
-// xc = c - hc, yc = r - hc:  px = m00 xc + m01 yc + bx,  py = m10 xc + m11 yc + by.
+// Per-angle constants of the float32 projector pair in 32.32 fixed point
+// (exact integer arithmetic, about 1e-7 px over the whole image):
+//   crossing of ray j with line L, along the interpolation axis:
+//     CF(j, L) = C0 + j A + L B          (A = 1/cos or 1/sin, B = beta)
+//   detector coordinate of the point at position s on line L (pixel units):
+//     U(s, L)  = U0 + s P + L Q          (P = 1/A, Q = -beta/A)
+// Ray j puts weight max(0, 1 - |CF/2^32 - s|) on pixel s of line L; seen from
+// the pixel this is max(0, 1 - |a| |j - U/2^32|), non-zero for the two bins
+// around U/2^32 only.
+struct AngleFx {
+  long long C0, A, B;
+  long long U0, P, Q;
+  float a, beta;  // float copies for the loop bounds
+  float absa;     // |a|
+  float oma;      // 1 - |a|
+  float ds;       // length of the ray per line
+  int rows;       // 1: lines are image rows
+};
+
+constexpr float kFix = 2.3283064365386963e-10f;  // 2^-32
+
+// Motion of one gate. The rigid map is stored as a displacement from the
+// pixel itself, phi(p) = p + delta(p) with, for xc = c - hc, yc = r - hc,
+//   delta_x = (cos - 1) xc - sin yc + t_x,   delta_y = sin xc + (cos - 1) yc + t_y,
+// so that the fractional part of the sample position keeps the precision of
+// the (small) displacement instead of that of the (large) absolute position.
 template <typename T>
 struct GateMotion {
   int kind;    // 0 identity, 1 rigid, 2 field
   int radius;  // gather window radius of the transposed warp
-  T m00, m01, m10, m11, bx, by;
-  T i00, i01, i10, i11;  // inverse rotation (window centres only)
+  T cm1, sn, tx, ty;      // cos - 1, sin, translation (rigid)
+  T i00, i01, i10, i11;   // inverse rotation (window centres only)
+  T bx, by;               // hc + t (window centres only)
 };
 
 // Per-gate scalars of one call of Algorithm 1.
@@ -70,27 +96,39 @@ struct Geo {
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-// Sample position of output pixel (r, c) under the gate's motion. The forward
-// warp and the transposed warp both call this, so their weights are the same
-// floating-point numbers.
+// Bilinear tap of output pixel (r, c) under the gate's motion: the sample
+// position is (c0 + fx, r0 + fy) with integer (c0, r0) and fx, fy in [0, 1).
+// The forward warp, the transposed warp and the window check all call this,
+// so their weights are the same floating-point numbers.
 template <typename T>
-__device__ __forceinline__ void motion_pos(const GateMotion<T>& M, const float* __restrict__ ux,
-                                           const float* __restrict__ uy, int pitch, T hc, int r,
-                                           int c, T& px, T& py) {
+struct Tap {
+  int c0, r0;
+  T fx, fy;
+};
+
+template <typename T>
+__device__ __forceinline__ Tap<T> motion_tap(const GateMotion<T>& M, const float* __restrict__ ux,
+                                             const float* __restrict__ uy, int pitch, T hc, int r,
+                                             int c) {
+  T dx = T(0), dy = T(0);
   if (M.kind == 1) {
     const T xc = T(c) - hc, yc = T(r) - hc;
-    px = fmaT(M.m00, xc, fmaT(M.m01, yc, M.bx));
-    py = fmaT(M.m10, xc, fmaT(M.m11, yc, M.by));
+    dx = fmaT(M.cm1, xc, fmaT(-M.sn, yc, M.tx));
+    dy = fmaT(M.sn, xc, fmaT(M.cm1, yc, M.ty));
   } else if (M.kind == 2) {
     const long o = (long)r * pitch + c;
-    px = T(c) + T(ux[o]);
-    py = T(r) + T(uy[o]);
-  } else {
-    px = T(c);
-    py = T(r);
+    dx = T(ux[o]);
+    dy = T(uy[o]);
   }
+  const T fdx = floor(dx), fdy = floor(dy);
+  Tap<T> t;
+  t.fx = dx - fdx;
+  t.fy = dy - fdy;
+  // far-away samples only need to stay far away; clamp keeps the int cast finite
+  t.c0 = c + (int)fmax(fmin(fdx, T(16384)), T(-16384));
+  t.r0 = r + (int)fmax(fmin(fdy, T(16384)), T(-16384));
+  return t;
 }
-
 
 // Centre of the gather window of output pixel (qr, qc) for the transposed
 // warp: the rounded inverse image of q (rigid: analytic inverse; field: the
@@ -145,13 +183,9 @@ __global__ __launch_bounds__(256) void k_warp_fwd(Geo<T> g, const GateMotion<T>*
       if (M.kind == 0) {
         v = src[(long)r * n + c];
       } else {
-        T px, py;
-        motion_pos(M, ux, uy, pitch, g.hc, r, c, px, py);
-        const T fc0 = floor(px), fr0 = floor(py);
-        const T fx = px - fc0, fy = py - fr0;
-        // taps outside [-1, n] contribute nothing; clamp keeps the int cast finite
-        const int c0 = (int)fmax(fmin(fc0, T(n)), T(-2));
-        const int r0 = (int)fmax(fmin(fr0, T(n)), T(-2));
+        const Tap<T> tp = motion_tap(M, ux, uy, pitch, g.hc, r, c);
+        const T fx = tp.fx, fy = tp.fy;
+        const int c0 = tp.c0, r0 = tp.r0;
         const T w00 = (T(1) - fx) * (T(1) - fy), w01 = fx * (T(1) - fy);
         const T w10 = (T(1) - fx) * fy, w11 = fx * fy;
         const bool cin0 = (unsigned)c0 < (unsigned)n, cin1 = (unsigned)(c0 + 1) < (unsigned)n;
@@ -231,15 +265,22 @@ __global__ __launch_bounds__(256) void k_joseph_fwd(Geo<T> g, const AngleT<T>* _
   __syncthreads();
   const int lo = s_lo, hi = s_hi;
   const T* img = (A.rows ? wP : wTP) + blockIdx.z * w_stride + (long)kPad * pitch + kPad;
+  // two-level sum (blocks of kLineBlock lines) keeps the float32 rounding of
+  // long ray sums close to that of a single block
   T acc = T(0);
-  for (int L = lo; L <= hi; ++L) {
-    const T gl = fmaT(T(L) - g.hc, A.beta, g.hc);
-    T cf = fmaT(t, A.a, gl);
-    cf = fmin(fmax(cf, T(-1)), T(n));
-    const T c0 = floor(cf);
-    const T f = cf - c0;
-    const T* p = img + (long)L * pitch + (int)c0;
-    acc += (T(1) - f) * p[0] + f * p[1];
+  for (int L0 = lo; L0 <= hi; L0 += kLineBlock) {
+    const int L1 = min(L0 + kLineBlock, hi + 1);
+    T blk = T(0);
+    for (int L = L0; L < L1; ++L) {
+      const T gl = fmaT(T(L) - g.hc, A.beta, g.hc);
+      T cf = fmaT(t, A.a, gl);
+      cf = fmin(fmax(cf, T(-1)), T(n));
+      const T c0 = floor(cf);
+      const T f = cf - c0;
+      const T* p = img + (long)L * pitch + (int)c0;
+      blk += (T(1) - f) * p[0] + f * p[1];
+    }
+    acc += blk;
   }
   if (!live) return;
   const T s = A.ds * acc;
@@ -278,8 +319,12 @@ __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* _
   const T xc = T(c) - g.hc, yr = T(r) - g.hc;
   const T fc = T(c), fr = T(r);
   const int nd = g.nd;
-  T acc = T(0);
+  T acc = T(0), blk = T(0);
   for (int k = 0; k < g.na; ++k) {
+    if ((k & (kLineBlock - 1)) == 0) {  // two-level sum over angles
+      acc += blk;
+      blk = T(0);
+    }
     const AngleT<T> A = ang[k];
     const T uline = A.rows ? yr : xc;
     const T pos = A.rows ? fc : fr;
@@ -298,8 +343,132 @@ __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* _
       const T v = srow[ok ? j : 0];
       part = fmaT(ok ? w : T(0), v, part);
     }
-    acc = fmaT(A.ds, part, acc);
+    blk = fmaT(A.ds, part, blk);
   }
+  acc += blk;
+  if (padded)
+    out[blockIdx.z * out_stride + (long)(r + kPad) * g.pitch + (c + kPad)] = acc;
+  else
+    out[blockIdx.z * out_stride + (long)r * g.n + c] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// a2 (+ a3), float32: Joseph forward projection with fixed-point crossings.
+// One thread per ray; the lanes of a wave are adjacent bins of one angle and
+// walk the lines together, so the two taps of each line are read along a
+// contiguous run of the padded image (its transpose for column stepping).
+// Modes as in k_joseph_fwd.  grid (ceil(n_det/256), n_angles, G), block 256
+// ---------------------------------------------------------------------------
+template <int MODE>
+__global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                       const float* __restrict__ wP,
+                                                       const float* __restrict__ wTP, long w_stride,
+                                                       float* __restrict__ out, long out_stride, int gate0,
+                                                       const GateScalars<float>* __restrict__ gs,
+                                                       const GatePtrs<float>* __restrict__ gp) {
+  __shared__ int s_lo, s_hi;
+  const int k = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const AngleFx A = ang[k];
+  const int n = g.n, pitch = g.pitch;
+  const bool live = j < g.nd;
+  if (threadIdx.x == 0) {
+    s_lo = n;
+    s_hi = -1;
+  }
+  __syncthreads();
+  if (live) {
+    // lines where the crossing lies in (-1, n): cf(L) = ta + hc + (L - hc) beta
+    const float ta = (float(j) - g.jc) * A.a + g.hc;
+    int lo = 0, hi = n - 1;
+    if (fabsf(A.beta) < 1e-12f) {
+      if (!(ta > -1.0f && ta < float(n))) {
+        lo = n;
+        hi = -1;
+      }
+    } else {
+      const float u1 = (-1.0f - ta) / A.beta, u2 = (float(n) - ta) / A.beta;
+      const float l1 = fminf(fmaxf(fminf(u1, u2) + g.hc, -4.0f), float(n + 4));
+      const float l2 = fminf(fmaxf(fmaxf(u1, u2) + g.hc, -4.0f), float(n + 4));
+      lo = max(0, (int)floorf(l1) - 2);
+      hi = min(n - 1, (int)ceilf(l2) + 2);
+    }
+    if (lo <= hi) {
+      atomicMin(&s_lo, lo);
+      atomicMax(&s_hi, hi);
+    }
+  }
+  __syncthreads();
+  const int lo = s_lo, hi = s_hi;
+  const float* row = (A.rows ? wP : wTP) + blockIdx.z * w_stride + (long)(kPad + lo) * pitch + kPad;
+  long long cf = A.C0 + (long long)j * A.A + (long long)lo * A.B;
+  float acc = 0.0f;
+  for (int L0 = lo; L0 <= hi; L0 += kLineBlock) {
+    const int L1 = min(L0 + kLineBlock, hi + 1);
+    float blk = 0.0f;
+    for (int L = L0; L < L1; ++L) {
+      // taps c0, c0 + 1; a clamped c0 lands in the zero border
+      const int c0 = min(max((int)(cf >> 32), -2), n);
+      const float f = float((unsigned)cf) * kFix;
+      const float p0 = row[c0], p1 = row[c0 + 1];
+      blk += fmaf(f, p1 - p0, p0);
+      cf += A.B;
+      row += pitch;
+    }
+    acc += blk;
+  }
+  if (!live) return;
+  const float s = A.ds * acc;
+  const long idx = (long)k * g.nd + j;
+  if (MODE == 0) {
+    out[blockIdx.z * out_stride + idx] = s;
+  } else {
+    const int gate = gate0 + blockIdx.z;
+    const GateScalars<float> S = gs[gate];
+    const GatePtrs<float> P = gp[gate];
+    const float yv = P.y[idx];
+    const float yn = (yv + S.sigma * (s - P.d[idx])) * S.cy;
+    P.y[idx] = yn;
+    out[blockIdx.z * out_stride + idx] = yn - yv;  // dy of this slot
+  }
+}
+
+// ---------------------------------------------------------------------------
+// a4, float32: transpose of k_joseph_fwd_fx, one thread per pixel. For each
+// angle the pixel's detector coordinate U (fixed point) gives the two bins
+// j0 = floor(U), j0 + 1 and their weights 1 - |a| d and 1 - |a| (1 - d),
+// d = frac(U): the hat weights of the forward seen from the pixel.
+// grid (ceil(n/16), ceil(n/16), G), block (16, 16)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_joseph_adj_fx(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                       const float* __restrict__ sino, long sino_stride,
+                                                       float* __restrict__ out, long out_stride, int padded) {
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c >= g.n || r >= g.n) return;
+  const float* s = sino + blockIdx.z * sino_stride;
+  const int nd = g.nd;
+  float acc = 0.0f, blk = 0.0f;
+  for (int k = 0; k < g.na; ++k) {
+    if ((k & (kLineBlock - 1)) == 0) {
+      acc += blk;
+      blk = 0.0f;
+    }
+    const AngleFx A = ang[k];
+    const int line = A.rows ? r : c;
+    const int pos = A.rows ? c : r;
+    const long long u = A.U0 + (long long)pos * A.P + (long long)line * A.Q;
+    const int j0 = (int)(u >> 32);
+    const float d = float((unsigned)u) * kFix;
+    const float w0 = fmaxf(0.0f, fmaf(-A.absa, d, 1.0f));
+    const float w1 = fmaxf(0.0f, fmaf(A.absa, d, A.oma));
+    const float* srow = s + (long)k * nd;
+    const bool ok0 = (unsigned)j0 < (unsigned)nd, ok1 = (unsigned)(j0 + 1) < (unsigned)nd;
+    const float y0 = srow[ok0 ? j0 : 0], y1 = srow[ok1 ? j0 + 1 : 0];
+    const float part = fmaf(ok1 ? w1 : 0.0f, y1, (ok0 ? w0 : 0.0f) * y0);
+    blk = fmaf(A.ds, part, blk);
+  }
+  acc += blk;
   if (padded)
     out[blockIdx.z * out_stride + (long)(r + kPad) * g.pitch + (c + kPad)] = acc;
   else
@@ -311,7 +480,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* _
 // dual-image updates of Algorithm 1 (iii) and the next primal step (i).
 // Output pixel q receives from the pixels p of a (2R+1)^2 window around the
 // inverse image of q; each candidate's weight on q is recomputed with the
-// forward warp's arithmetic (motion_pos, floor, the same products), so the
+// forward warp's arithmetic (motion_tap and the same products), so the
 // result is the exact transpose. Candidates in the zero border of the padded
 // input contribute zero.
 //   mode 0: out = sum_g D_g^T b_g                       (plain adjoint)
@@ -359,14 +528,9 @@ __global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __
 #pragma unroll
         for (int ddx = -R; ddx <= R; ++ddx) {
           const int pr = cr + ddy, pc = cc + ddx;
-          T px, py;
-          motion_pos(M, ux, uy, pitch, g.hc, pr, pc, px, py);
-          const T fc0 = floor(px), fr0 = floor(py);
-          const T fx = px - fc0, fy = py - fr0;
-          const int c0 = (int)fmax(fmin(fc0, T(n + 8)), T(-8));
-          const int r0 = (int)fmax(fmin(fr0, T(n + 8)), T(-8));
-          const T wx = (qc == c0) ? (T(1) - fx) : ((qc == c0 + 1) ? fx : T(0));
-          const T wy = (qr == r0) ? (T(1) - fy) : ((qr == r0 + 1) ? fy : T(0));
+          const Tap<T> tp = motion_tap(M, ux, uy, pitch, g.hc, pr, pc);
+          const T wx = (qc == tp.c0) ? (T(1) - tp.fx) : ((qc == tp.c0 + 1) ? tp.fx : T(0));
+          const T wy = (qr == tp.r0) ? (T(1) - tp.fy) : ((qr == tp.r0 + 1) ? tp.fy : T(0));
           part = fmaT(wx * wy, b[(long)pr * pitch + pc], part);
         }
       }
@@ -522,12 +686,9 @@ __global__ __launch_bounds__(256) void k_window_check(Geo<T> g, const GateMotion
   const long origin = (long)kPad * pitch + kPad;
   const float* ux = field + gate * field_stride + origin;
   const float* uy = ux + plane_stride;
-  T px, py;
-  motion_pos(M, ux, uy, pitch, g.hc, r, c, px, py);
-  const T fc0 = floor(px), fr0 = floor(py);
-  const T fx = px - fc0, fy = py - fr0;
-  const int c0 = (int)fmax(fmin(fc0, T(n + 8)), T(-8));
-  const int r0 = (int)fmax(fmin(fr0, T(n + 8)), T(-8));
+  const Tap<T> tp = motion_tap(M, ux, uy, pitch, g.hc, r, c);
+  const T fx = tp.fx, fy = tp.fy;
+  const int c0 = tp.c0, r0 = tp.r0;
   int worst = 0;
   for (int a = 0; a < 2; ++a) {
     for (int bb = 0; bb < 2; ++bb) {
