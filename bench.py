@@ -121,6 +121,8 @@ def main():
     p = [1.0 / N] * N
     log(f"|A_i|^2 in [{min(norms):.4g}, {max(norms):.4g}], per-epoch rate {rate:.6f}")
 
+    variant = h.autotune(1)
+    log(f"autotuned projector variants: {variant}")
     st = h.zero_state()
 
     def epoch(e):
@@ -215,6 +217,7 @@ def main():
         "us_per_pair": pair_s * 1e6,
         "ms_per_step_with_kernel_events": prof_ms,
         "kernels_us_per_launch": {k: (v[0] * 1e3 / v[1] if v[1] else None) for k, v in kstats.items()},
+        "projector_variant": variant,
         "roofline": roof,
         "cpu_baseline": None,
     }

@@ -183,6 +183,25 @@ mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq,
                           double* sigma, double* tau, double* theta, double* rate_per_epoch);
 
 /* ---------------------------------------------------------------------------
+ * Kernel variants of the float32 projector pair (no effect on FP64 handles).
+ * forward:  0 = one thread per ray, 1 = LDS-tiled (8 angles x 32 bins share a
+ *           staged image band; only where every band window fits in LDS),
+ *           2 = the same with the bands scheduled on the host and the next
+ *           band prefetched while the current one is computed;
+ * adjoint:  adj_px = 0 one thread per pixel, or 1, 2, 4 pixels per thread with
+ *           LDS-staged sinogram chunks, the angles split into adj_s (1..4)
+ *           shares whose partial images are summed in a fixed order.
+ * All variants compute the same weights; results differ only by summation
+ * order. mcr_autotune times the variants on this geometry with
+ * gates_per_launch gates per launch (1 for SPDHG, N for PDHG), keeps the
+ * fastest (remembered per geometry for the life of the process) and returns
+ * the choice (output pointers may be NULL). Synchronises the stream.
+ * ------------------------------------------------------------------------- */
+mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, int32_t* adj_px,
+                        int32_t* adj_s);
+mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t adj_s);
+
+/* ---------------------------------------------------------------------------
  * Kernel timing (diagnostic). While enabled, every kernel launch of the handle
  * is bracketed by HIP events on the handle's stream. mcr_profile_read waits
  * for the stream, then returns per kernel class the summed duration [ms] and

@@ -254,6 +254,18 @@ class Handle:
                                              float(alpha), ctypes.byref(out)))
         return out.value
 
+    def autotune(self, gates_per_launch: int = 1):
+        """Pick the fastest float32 projector-pair variants for this geometry;
+        returns {"fwd": ..., "adj_px": ..., "adj_shares": ...}."""
+        self._sync_stream()
+        f, p, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.check(self._lib.mcr_autotune(self._h, int(gates_per_launch), ctypes.byref(f), ctypes.byref(p),
+                                          ctypes.byref(s)))
+        return {"fwd": f.value, "adj_px": p.value, "adj_shares": s.value}
+
+    def set_variant(self, fwd: int, adj_px: int, adj_shares: int):
+        _lib.check(self._lib.mcr_set_variant(self._h, int(fwd), int(adj_px), int(adj_shares)))
+
     def profile(self, enable: bool = True):
         """Bracket every kernel launch with HIP events (see profile_read)."""
         _lib.check(self._lib.mcr_profile_enable(self._h, 1 if enable else 0))

@@ -62,6 +62,8 @@ SIGNATURES = {
     "mcr_duality_gap": [_P, ctypes.POINTER(State), _PP, _D, _PD],
     "mcr_step_sizes": [_I, _I, _PD, _D, _PD, _PD, _PD, _PD],
     "mcr_profile_enable": [_P, _I],
+    "mcr_autotune": [_P, _I, _PI, _PI, _PI],
+    "mcr_set_variant": [_P, _I, _I, _I],
     "mcr_profile_read": [_P, _PD, ctypes.POINTER(ctypes.c_int64)],
 }
 KERNEL_CLASSES = ["warp", "project", "backproject", "twarp", "xstep", "other"]

@@ -5,6 +5,10 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -14,6 +18,7 @@
 #include <vector>
 
 #include "mcr_kernels.h"
+#include "mcr_joseph_tiled.h"
 
 using namespace mcr;
 
@@ -48,6 +53,9 @@ mcr_status fail(mcr_status s, const char* fmt, ...) {
   } while (0)
 
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
+
+constexpr int kFwdKA = 8, kFwdJD = 32, kFwdWL = 128;  // tiled forward: angles, bins, LDS row
+constexpr int kMaxShares = 4;                          // tiled adjoint: angle shares
 
 
 // Per-precision workspace and tables.
@@ -95,6 +103,21 @@ struct mcr_handle {
   double* red_host = nullptr;      // pinned [64]
   int* need = nullptr;             // window verification
   std::vector<void*> allocs;
+  // float32 projector pair: kernel variants (chosen by mcr_autotune)
+  struct Tune {
+    int fwd = 2;     // 0 one thread per ray, 1 LDS-tiled (8 angles x 32 bins), 2 the same with a host band schedule
+    int adj_px = 4;  // 0 one thread per pixel; 1, 2, 4 pixels per thread (LDS-tiled)
+    int adj_s = 4;   // angle shares per pixel tile (LDS-tiled adjoint)
+  } tune;
+  bool fwd_lds_ok = false;         // every band window of the tiled forward fits in LDS
+  int2* chunks = nullptr;          // angle chunks of the tiled forward
+  int nchunks = 0;
+  int4* sched_chunks = nullptr;    // scheduled forward: (k0, count, shear, -) per chunk
+  int2* sched_blocks = nullptr;    // (first band, bands) per (chunk, detector tile)
+  int4* sched_bands = nullptr;     // (L0, lines, window start, window width)
+  int sched_nchunks = 0;
+  bool sched_ok = false;
+  float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
   // kernel timing
   bool prof = false;
   struct Rec {
@@ -246,6 +269,8 @@ std::vector<AngleFx> angle_table_fx(int n, int na, int nd) {
     f.oma = float(1.0 - std::fabs(a));
     f.ds = float(std::fabs(a));
     f.rows = rows ? 1 : 0;
+    f.na32 = float(-std::fabs(a) / one);
+    f.pa32 = float(std::fabs(a) / one);
     v[k] = f;
   }
   return v;
@@ -260,6 +285,124 @@ mcr_status upload_motion(mcr_handle* h) {
                         h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
   return MCR_OK;
+}
+
+// Runs of at most ka consecutive angles of one stepping type.
+std::vector<int2> angle_chunks(const std::vector<AngleFx>& af, int ka) {
+  std::vector<int2> ch;
+  int k = 0;
+  const int na = (int)af.size();
+  while (k < na) {
+    int e = k + 1;
+    while (e < na && e - k < ka && af[e].rows == af[k].rows) ++e;
+    ch.push_back(make_int2(k, e - k));
+    k = e;
+  }
+  return ch;
+}
+
+// The tiled forward stages, per band, the sheared window spanned by the
+// crossings of its corner rays. A single line's window is widest on the first
+// or the last image line (max - min of affine functions is convex); check that
+// it fits the LDS row for every chunk and detector tile.
+bool tiled_windows_fit(const mcr_handle* h, const std::vector<AngleFx>& af, const std::vector<int2>& ch) {
+  const int nd = h->geo.n_det, n = h->geo.n;
+  for (const int2& c : ch) {
+    for (int j0 = 0; j0 < nd; j0 += kFwdJD) {
+      const int j1 = std::min(j0 + kFwdJD - 1, nd - 1);
+      for (int L : {0, n - 1}) {
+        long long lo = LLONG_MAX, hi = LLONG_MIN;
+        for (int a = 0; a < c.y; ++a) {
+          const AngleFx& A = af[c.x + a];
+          for (int j : {j0, j1}) {
+            const long long v = (A.C0 + (long long)j * A.A + (long long)L * A.B) >> 32;
+            lo = std::min(lo, v);
+            hi = std::max(hi, v);
+          }
+        }
+        if (hi - lo + 3 > kFwdWL) return false;
+      }
+    }
+  }
+  return true;
+}
+
+// Band schedule of the scheduled tiled forward (see k_joseph_fwd_sched): for
+// each chunk of angles and tile of bins, the lines any of its rays crosses
+// inside (-1, n), cut into bands of at most kFwdMaxBand lines whose sheared
+// windows (over the corner rays, exact integer arithmetic) fit kFwdWL columns.
+struct Schedule {
+  std::vector<int4> chunks;
+  std::vector<int2> blocks;
+  std::vector<int4> bands;
+  bool ok = true;
+};
+
+Schedule build_schedule(int n, int nd, const std::vector<AngleFx>& af, int ka, int jd, int wl) {
+  Schedule S;
+  const std::vector<int2> ch = angle_chunks(af, ka);
+  const int ntiles = (nd + jd - 1) / jd;
+  const double hc = (n - 1) / 2.0, jc = (nd - 1) / 2.0;
+  for (const int2& c : ch) {
+    // the same shear the kernel applies: rint of the float slope of the middle angle
+    const int m = (int)std::nearbyint(af[c.x + (c.y >> 1)].beta);
+    S.chunks.push_back(make_int4(c.x, c.y, m, 0));
+  }
+  for (size_t ci = 0; ci < ch.size(); ++ci) {
+    const int2 c = ch[ci];
+    const int m = S.chunks[ci].z;
+    for (int t = 0; t < ntiles; ++t) {
+      const int jf = t * jd, jl = std::min(jf + jd - 1, nd - 1);
+      // lines where some ray of the block crosses inside (-1, n) (margin 2)
+      double lo = n, hi = -1;
+      for (int a = 0; a < c.y; ++a) {
+        const AngleFx& A = af[c.x + a];
+        const double a_ = double(A.A) / 4294967296.0, b_ = double(A.B) / 4294967296.0;
+        const double ta_f = (jf - jc) * a_ + hc, ta_l = (jl - jc) * a_ + hc;  // crossings on the centre line
+        if (std::fabs(b_) < 1e-12) {  // crossings do not move with the line
+          if (std::max(ta_f, ta_l) > -1.0 && std::min(ta_f, ta_l) < n) {
+            lo = 0;
+            hi = n - 1;
+          }
+          continue;
+        }
+        for (double ta : {ta_f, ta_l}) {
+          const double u1 = (-1.0 - ta) / b_ + hc, u2 = (n - ta) / b_ + hc;
+          lo = std::min(lo, std::min(u1, u2));
+          hi = std::max(hi, std::max(u1, u2));
+        }
+      }
+      const int L_lo = std::max(0, (int)std::floor(std::max(lo, -4.0)) - 2);
+      const int L_hi = std::min(n - 1, (int)std::ceil(std::min(hi, n + 4.0)) + 2);
+      const int first = (int)S.bands.size();
+      for (int L0 = L_lo; L0 <= L_hi;) {
+        int bl = std::min(kFwdMaxBand, L_hi - L0 + 1);
+        int S0 = 0, W = 0;
+        for (;; bl = (bl + 1) / 2) {
+          long long vmin = LLONG_MAX, vmax = LLONG_MIN;
+          for (int a = 0; a < c.y; ++a) {
+            const AngleFx& A = af[c.x + a];
+            for (int j : {jf, jl}) {
+              for (int l : {0, bl - 1}) {
+                const long long v = ((A.C0 + (long long)j * A.A + (long long)(L0 + l) * A.B) >> 32) -
+                                    (long long)l * m;
+                vmin = std::min(vmin, v);
+                vmax = std::max(vmax, v);
+              }
+            }
+          }
+          S0 = (int)vmin - 1;
+          W = (int)(vmax - vmin) + 3;
+          if (W <= wl || bl == 1) break;
+        }
+        if (W > wl) S.ok = false;
+        S.bands.push_back(make_int4(L0, bl, S0, W));
+        L0 += bl;
+      }
+      S.blocks.push_back(make_int2(first, (int)S.bands.size() - first));
+    }
+  }
+  return S;
 }
 
 template <typename T>
@@ -286,6 +429,28 @@ mcr_status init_work(mcr_handle* h) {
   STATUS_OK(dmalloc(h, (void**)&w.angfx, sizeof(AngleFx) * h->geo.n_angles));
   const std::vector<AngleFx> af = angle_table_fx(h->geo.n, h->geo.n_angles, h->geo.n_det);
   HIP_OK(hipMemcpyAsync(w.angfx, af.data(), sizeof(AngleFx) * af.size(), hipMemcpyHostToDevice, h->stream));
+  if constexpr (std::is_same<T, float>::value) {
+    std::vector<int2> ch = angle_chunks(af, kFwdKA);
+    h->fwd_lds_ok = tiled_windows_fit(h, af, ch);
+    h->nchunks = (int)ch.size();
+    STATUS_OK(dmalloc(h, (void**)&h->chunks, sizeof(int2) * ch.size()));
+    HIP_OK(hipMemcpyAsync(h->chunks, ch.data(), sizeof(int2) * ch.size(), hipMemcpyHostToDevice, h->stream));
+    STATUS_OK(dmalloc(h, (void**)&h->parts, sizeof(float) * kMaxShares * N * n2));
+    const Schedule sc = build_schedule(h->geo.n, h->geo.n_det, af, kFwdKA, kFwdJD, kFwdWL);
+    h->sched_ok = sc.ok;
+    h->sched_nchunks = (int)sc.chunks.size();
+    STATUS_OK(dmalloc(h, (void**)&h->sched_chunks, sizeof(int4) * sc.chunks.size()));
+    STATUS_OK(dmalloc(h, (void**)&h->sched_blocks, sizeof(int2) * sc.blocks.size()));
+    STATUS_OK(dmalloc(h, (void**)&h->sched_bands, sizeof(int4) * std::max<size_t>(1, sc.bands.size())));
+    HIP_OK(hipMemcpyAsync(h->sched_chunks, sc.chunks.data(), sizeof(int4) * sc.chunks.size(), hipMemcpyHostToDevice,
+                          h->stream));
+    HIP_OK(hipMemcpyAsync(h->sched_blocks, sc.blocks.data(), sizeof(int2) * sc.blocks.size(), hipMemcpyHostToDevice,
+                          h->stream));
+    if (!sc.bands.empty())
+      HIP_OK(hipMemcpyAsync(h->sched_bands, sc.bands.data(), sizeof(int4) * sc.bands.size(), hipMemcpyHostToDevice,
+                            h->stream));
+    HIP_OK(hipStreamSynchronize(h->stream));
+  }
   HIP_OK(hipStreamSynchronize(h->stream));
   STATUS_OK(upload_motion<T>(h));
   w.ready = true;
@@ -339,10 +504,22 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   Work<T>& w = work<T>(h);
   Timed tm(h, MCR_KERNEL_PROJECT);
   dim3 grid(cdiv(h->geo.n_det, 256), h->geo.n_angles, G), block(256);
-  if constexpr (std::is_same<T, float>::value)
-    hipLaunchKernelGGL((k_joseph_fwd_fx<MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.angfx, w.wP,
-                       w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
-  else
+  if constexpr (std::is_same<T, float>::value) {
+    if (h->tune.fwd == 2 && h->sched_ok) {
+      dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->sched_nchunks, G);
+      hipLaunchKernelGGL((k_joseph_fwd_sched<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
+                         geo_of<T>(h), w.angfx, h->sched_chunks, h->sched_blocks, h->sched_bands, w.wP, w.wTP,
+                         h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+    } else if (h->tune.fwd == 1 && h->fwd_lds_ok) {
+      dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->nchunks, G);
+      hipLaunchKernelGGL((k_joseph_fwd_lds<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
+                         geo_of<T>(h), w.angfx, h->chunks, w.wP, w.wTP, h->padded, out, out_stride, gate0,
+                         w.scalars, w.ptrs);
+    } else {
+      hipLaunchKernelGGL((k_joseph_fwd_fx<MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.angfx, w.wP,
+                         w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+    }
+  } else
     hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.ang, w.wP,
                        w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
   LAUNCH_OK();
@@ -356,10 +533,35 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_BACKPROJECT);
   dim3 grid(cdiv(n, 16), cdiv(n, 16), G), block(16, 16);
-  if constexpr (std::is_same<T, float>::value)
-    hipLaunchKernelGGL(k_joseph_adj_fx, grid, block, 0, h->stream, geo_of<T>(h), w.angfx, sino,
-                       sino_stride, out, out_stride, padded);
-  else
+  if constexpr (std::is_same<T, float>::value) {
+    const int px = h->tune.adj_px, S = px > 0 ? h->tune.adj_s : 1;
+    if (px > 0) {
+      const long n2 = (long)n * n;
+      // S > 1: partial images per angle share, then a fixed-order sum
+      float* dst = S > 1 ? h->parts : out;
+      const long dst_stride = S > 1 ? n2 : out_stride;
+      const long part_stride = n2 * h->N;
+      dim3 gt(cdiv(n, 8 * px), cdiv(n, 32), G * S);
+#define ADJ(PX)                                                                                           \
+  hipLaunchKernelGGL(k_joseph_adj_lds<PX>, gt, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx, sino, \
+                     sino_stride, dst, dst_stride, padded, S, part_stride)
+      if (px == 1)
+        ADJ(1);
+      else if (px == 2)
+        ADJ(2);
+      else
+        ADJ(4);
+#undef ADJ
+      LAUNCH_OK();
+      if (S > 1) {
+        hipLaunchKernelGGL(k_sum_parts, grid, block, 0, h->stream, n, h->pitch, S, h->parts, part_stride, n2,
+                           out, out_stride, padded);
+      }
+    } else {
+      hipLaunchKernelGGL(k_joseph_adj_fx, grid, block, 0, h->stream, geo_of<T>(h), w.angfx, sino,
+                         sino_stride, out, out_stride, padded);
+    }
+  } else
     hipLaunchKernelGGL(k_joseph_adj<T>, grid, block, 0, h->stream, geo_of<T>(h), w.ang, sino,
                        sino_stride, out, out_stride, padded);
   LAUNCH_OK();
@@ -644,6 +846,33 @@ mcr_status gap_impl(mcr_handle* h, const mcr_state* st, const void* const* d, do
 
 }  // namespace
 
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, mcr_handle::Tune> g_tune_cache;
+
+// Average duration [ms] of `reps` launches made by fn after two warm-up launches.
+template <typename F>
+mcr_status time_launches(mcr_handle* h, F fn, int reps, float* ms) {
+  hipEvent_t a, b;
+  HIP_OK(hipEventCreate(&a));
+  HIP_OK(hipEventCreate(&b));
+  mcr_status st = MCR_OK;
+  for (int i = 0; i < 2 && st == MCR_OK; ++i) st = fn();
+  if (st == MCR_OK) {
+    (void)hipEventRecord(a, h->stream);
+    for (int i = 0; i < reps && st == MCR_OK; ++i) st = fn();
+    (void)hipEventRecord(b, h->stream);
+    (void)hipEventSynchronize(b);
+    float t = 0.0f;
+    (void)hipEventElapsedTime(&t, a, b);
+    *ms = t / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return st;
+}
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -711,6 +940,7 @@ mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motio
   if ((s = init_work<double>(h)) != MCR_OK) return cleanup(s);
   if (dtype == MCR_F32 && (s = init_work<float>(h)) != MCR_OK) return cleanup(s);
   if ((s = mcr_set_motion(h, -1, nullptr)) != MCR_OK) return cleanup(s);
+  h->tune.fwd = h->sched_ok ? 2 : 0;
   *out = h;
   return MCR_OK;
 }
@@ -961,6 +1191,82 @@ mcr_status mcr_duality_gap(mcr_handle* h, const mcr_state* st, const void* const
   }
   if (!(alpha > 0) || !std::isfinite(alpha)) return fail(MCR_ERR_ARG, "alpha must be finite and > 0");
   return DISPATCH(gap_impl, h, st, d, alpha, out);
+}
+
+
+mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, int32_t* adj_px, int32_t* adj_s) {
+  STATUS_OK(check_handle(h));
+  if (gates_per_launch < 1 || gates_per_launch > h->N)
+    return fail(MCR_ERR_ARG, "gates_per_launch = %d must be in [1, %d]", gates_per_launch, h->N);
+  if (h->dtype == MCR_F32) {
+    const auto key = std::make_tuple(h->geo.n, h->geo.n_angles, h->geo.n_det, gates_per_launch);
+    bool cached = false;
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune_cache.find(key);
+      if (it != g_tune_cache.end()) {
+        h->tune = it->second;
+        cached = true;
+      }
+    }
+    if (!cached) {
+      HIP_OK(hipStreamSynchronize(h->stream));
+      const bool prof = h->prof;
+      h->prof = false;
+      Work<float>& w = h->wf;
+      const int G = gates_per_launch;
+      mcr_handle::Tune best = h->tune;
+      float best_ms = 1e30f, ms = 0.0f;
+      mcr_status st = MCR_OK;
+      for (int f = 0; f <= 2 && st == MCR_OK; ++f) {
+        if ((f == 1 && !h->fwd_lds_ok) || (f == 2 && !h->sched_ok)) continue;
+        h->tune.fwd = f;
+        st = time_launches(h, [&] { return launch_project<float, 0>(h, 0, G, w.dy, h->sino); }, 5, &ms);
+        if (st == MCR_OK && ms < best_ms) {
+          best_ms = ms;
+          best.fwd = f;
+        }
+      }
+      h->tune.fwd = best.fwd;
+      const int cand[][2] = {{0, 1}, {1, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {4, 4}};
+      best_ms = 1e30f;
+      for (const auto& c : cand) {
+        if (st != MCR_OK) break;
+        h->tune.adj_px = c[0];
+        h->tune.adj_s = c[1];
+        st = time_launches(h, [&] { return launch_backproject<float>(h, G, w.dy, h->sino, w.bP, h->padded, 1); }, 5,
+                           &ms);
+        if (st == MCR_OK && ms < best_ms) {
+          best_ms = ms;
+          best.adj_px = c[0];
+          best.adj_s = c[1];
+        }
+      }
+      h->prof = prof;
+      h->tune = best;
+      STATUS_OK(st);
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      g_tune_cache[key] = best;
+    }
+  }
+  if (fwd) *fwd = h->tune.fwd;
+  if (adj_px) *adj_px = h->tune.adj_px;
+  if (adj_s) *adj_s = h->tune.adj_s;
+  return MCR_OK;
+}
+
+mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t adj_s) {
+  STATUS_OK(check_handle(h));
+  if (fwd < 0 || fwd > 2) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1 or 2", fwd);
+  if (h->dtype == MCR_F32 && ((fwd == 1 && !h->fwd_lds_ok) || (fwd == 2 && !h->sched_ok)))
+    return fail(MCR_ERR_STATE, "the tiled forward's band windows do not fit this geometry");
+  if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4)
+    return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2 or 4", adj_px);
+  if (adj_s < 1 || adj_s > kMaxShares) return fail(MCR_ERR_ARG, "angle shares %d must be in [1, %d]", adj_s, kMaxShares);
+  h->tune.fwd = fwd;
+  h->tune.adj_px = adj_px;
+  h->tune.adj_s = adj_s;
+  return MCR_OK;
 }
 
 mcr_status mcr_profile_enable(mcr_handle* h, int32_t enable) {

@@ -52,6 +52,8 @@ struct AngleFx {
   float oma;      // 1 - |a|
   float ds;       // length of the ray per line
   int rows;       // 1: lines are image rows
+  float na32;     // -|a| 2^-32 and |a| 2^-32: hat weights from the raw fraction
+  float pa32;
 };
 
 constexpr float kFix = 2.3283064365386963e-10f;  // 2^-32
@@ -400,22 +402,53 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const Angle
   }
   __syncthreads();
   const int lo = s_lo, hi = s_hi;
-  const float* row = (A.rows ? wP : wTP) + blockIdx.z * w_stride + (long)(kPad + lo) * pitch + kPad;
-  long long cf = A.C0 + (long long)j * A.A + (long long)lo * A.B;
+  // wave-uniform start of the padded row (column -kPad), taps addressed by a
+  // 32-bit byte offset: the loads use the scalar-base + vector-offset form
+  const char* row = (const char*)((A.rows ? wP : wTP) + blockIdx.z * w_stride + (long)(kPad + lo) * pitch);
+  const unsigned rowb = (unsigned)pitch * 4u;
+  // the crossing is carried 2 columns to the right, so that one unsigned min
+  // maps every tap left of column -1 or right of column n to the zero column n
+  long long cf = A.C0 + (long long)j * A.A + (long long)lo * A.B + (2LL << 32);
+  const unsigned cmax = (unsigned)(n + 2);
   float acc = 0.0f;
-  for (int L0 = lo; L0 <= hi; L0 += kLineBlock) {
-    const int L1 = min(L0 + kLineBlock, hi + 1);
-    float blk = 0.0f;
-    for (int L = L0; L < L1; ++L) {
-      // taps c0, c0 + 1; a clamped c0 lands in the zero border
-      const int c0 = min(max((int)(cf >> 32), -2), n);
-      const float f = float((unsigned)cf) * kFix;
-      const float p0 = row[c0], p1 = row[c0 + 1];
-      blk += fmaf(f, p1 - p0, p0);
+  int L0 = lo;
+  // full blocks of kLineBlock lines: every tap of the block is loaded before
+  // the first is used, so a wave keeps kLineBlock loads in flight. The sample
+  // p0 + f (p1 - p0) is accumulated as sum p0 + 2^-32 sum F (p1 - p0) with
+  // F = 2^32 f the raw fraction.
+  for (; L0 + kLineBlock - 1 <= hi; L0 += kLineBlock) {
+    float p0[kLineBlock], p1[kLineBlock], f[kLineBlock];
+#pragma unroll
+    for (int i = 0; i < kLineBlock; ++i) {
+      const unsigned cc = min((unsigned)(cf >> 32), cmax);  // column + 2
+      const unsigned off = (cc + (unsigned)(kPad - 2)) * 4u + (unsigned)i * rowb;
+      f[i] = float((unsigned)cf);
+      p0[i] = *(const float*)(row + off);
+      p1[i] = *(const float*)(row + off + 4);
       cf += A.B;
-      row += pitch;
     }
-    acc += blk;
+    float b0 = 0.0f, b1 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kLineBlock; ++i) {
+      b0 += p0[i];
+      b1 = fmaf(f[i], p1[i] - p0[i], b1);
+    }
+    acc += fmaf(b1, kFix, b0);
+    row += (long)kLineBlock * rowb;
+  }
+  {
+    float b0 = 0.0f, b1 = 0.0f;
+    for (int L = L0; L <= hi; ++L) {
+      const unsigned cc = min((unsigned)(cf >> 32), cmax);
+      const unsigned off = (cc + (unsigned)(kPad - 2)) * 4u;
+      const float f = float((unsigned)cf);
+      const float p0 = *(const float*)(row + off), p1 = *(const float*)(row + off + 4);
+      b0 += p0;
+      b1 = fmaf(f, p1 - p0, b1);
+      cf += A.B;
+      row += rowb;
+    }
+    acc += fmaf(b1, kFix, b0);
   }
   if (!live) return;
   const float s = A.ds * acc;

@@ -35,6 +35,43 @@ def test_project_and_backproject(dtype, bar, geom):
     assert rel(b, projector.adjoint(y, n)) < bar
 
 
+# (forward, adjoint pixels per thread, adjoint angle shares)
+VARIANTS = [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 2), (1, 4, 1), (1, 4, 4), (0, 4, 3), (2, 4, 4), (2, 2, 1)]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("geom", [(64, 96, 92), (75, 40, 300), (200, 90, 290), (33, 16, 48)])
+def test_projector_variants(variant, geom):
+    from paper_2410_10503_amd import McrError
+    n, na, nd = geom
+    P = Problem(n, na, nd, 2, "rigid")
+    h = P.handle(torch.float32)
+    try:
+        h.set_variant(*variant)
+    except McrError as e:
+        assert "do not fit" in str(e)
+        h.set_variant(0, variant[1], variant[2])
+    x = f32(synth.ellipse_phantom(n, 3)) + f32(synth.random_image(n, 4)) * 0.1
+    y = f32(synth.random_sinograms(1, na, nd, 5)[0])
+    assert rel(host(h.project(dev(x, torch.float32))), projector.forward(x, na, nd)) < F32_OP
+    assert rel(host(h.backproject(dev(y, torch.float32))), projector.adjoint(y, n)) < F32_OP
+    assert rel(host(h.apply_Ai(1, dev(x, torch.float32))), P.ops.A(1, x)) < F32_OP
+    assert rel(host(h.apply_Ai_adjoint(1, dev(y, torch.float32))), P.ops.At(1, y)) < F32_OP
+
+
+def test_autotune_keeps_parity():
+    P = Problem(128, 120, 182, 3, "field")
+    h = P.handle(torch.float32)
+    choice = h.autotune(1)
+    assert choice["fwd"] in (0, 1, 2) and choice["adj_px"] in (0, 1, 2, 4) and 1 <= choice["adj_shares"] <= 4
+    assert h.autotune(3) is not None
+    x = f32(synth.ellipse_phantom(128, 1))
+    y = f32(synth.random_sinograms(1, 120, 182, 2)[0])
+    for i in range(3):
+        assert rel(host(h.apply_Ai(i, dev(x, torch.float32))), P.ops.A(i, x)) < F32_OP
+        assert rel(host(h.apply_Ai_adjoint(i, dev(y, torch.float32))), P.ops.At(i, y)) < F32_OP
+
+
 @pytest.mark.parametrize("dtype,bar", DT)
 @pytest.mark.parametrize("kind", ["rigid", "field"])
 def test_warp_and_transpose(dtype, bar, kind):
