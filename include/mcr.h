@@ -150,6 +150,37 @@ mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const*
                           double alpha, const double* sigma, double tau, double theta);
 
 /* ---------------------------------------------------------------------------
+ * Differentiation through unrolled SPDHG iterations (reverse mode; not in the
+ * paper, built on its Algorithm 1). Gradients and checkpoints have the
+ * handle's dtype; rigid motion gradients are FP64.
+ * ------------------------------------------------------------------------- */
+/* As mcr_spdhg_iterate, and before iteration k (gate g = gate_seq[k]) has
+ * touched the duals it stores x after step (i) into x1_ckpt[k] ([n][n]) and
+ * y_g into y_ckpt[k] ([n_angles][n_det]): host arrays of n_iter device
+ * pointers. Same results as mcr_spdhg_iterate, bit for bit.                    */
+mcr_status mcr_spdhg_iterate_ckpt(mcr_handle* h, const mcr_state* st, const void* const* d,
+                                  double alpha, const double* sigma, double tau, double theta,
+                                  const double* p, const int32_t* gate_seq, int32_t n_iter,
+                                  void* const* x1_ckpt, void* const* y_ckpt);
+/* Reverse of one SPDHG iteration on `gate` from its checkpoint (x1, y_before)
+ * and the gate's data d_gate, with that iteration's sigma (of the gate), tau,
+ * theta, p (of the gate). On entry gx, gy_gate, gz, gzbar ([n][n] except
+ * gy_gate [n_angles][n_det]) hold the adjoints of the iteration's outputs
+ * x, y_gate, z, z-bar; on return those of its inputs. grad_motion (may be
+ * NULL) accumulates d/d(motion of gate): device double[3] (phi, t_x, t_y) for
+ * rigid gates, device [2][n][n] (u_x, u_y planes) for fields, unused for the
+ * identity. The reverse map is the transpose of the iteration (see
+ * mcr_grad.h); each call costs two projections and two backprojections.      */
+mcr_status mcr_spdhg_step_backward(mcr_handle* h, int32_t gate, const void* x1,
+                                   const void* y_before, const void* d_gate, double alpha,
+                                   double sigma, double tau, double theta, double p, void* gx,
+                                   void* gy_gate, void* gz, void* gzbar, void* grad_motion);
+/* grad_motion += d/d(motion of gate) <img, D_gate v> (img, v: [n][n]); layout
+ * of grad_motion as above.                                                     */
+mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, const void* v,
+                                void* grad_motion);
+
+/* ---------------------------------------------------------------------------
  * FP64 diagnostics (Theorem 1 and the model of Section II-A), computed on the
  * device in double precision whatever the handle's dtype; they synchronise.
  * ------------------------------------------------------------------------- */

@@ -86,6 +86,7 @@ class Handle:
         keep = []
         for i, m in enumerate(motion):
             arr[i] = self._motion(m, keep)
+        self._kinds = [arr[i].kind for i in range(self.n_gates)]
         geo = _lib.Geometry(self.n, self.n_angles, self.n_det)
         self._stream = _stream_ptr(self.device)
         _lib.check(self._lib.mcr_create(ctypes.byref(geo), self.n_gates, arr, _DTYPES[dtype],
@@ -160,6 +161,7 @@ class Handle:
         keep = []
         m = self._motion(motion, keep)
         _lib.check(self._lib.mcr_set_motion(self._h, int(gate), ctypes.byref(m)))
+        self._kinds[int(gate)] = m.kind
 
     def warp(self, gate, x, out=None):
         self._sync_stream()
@@ -227,6 +229,49 @@ class Handle:
         self._sync_stream()
         _lib.check(self._lib.mcr_pdhg_epoch(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
                                             float(alpha), _dbl_array(sigma), float(tau), float(theta)))
+
+    # -- differentiation ----------------------------------------------------
+    def spdhg_iterate_ckpt(self, st: ReconState, d, alpha, sigma, tau, theta, p, gate_seq, x1_ckpt, y_ckpt):
+        """spdhg_iterate that also stores, per iteration, x after step (i) and the drawn gate's old dual."""
+        self._sync_stream()
+        seq = [int(g) for g in gate_seq]
+        if len(x1_ckpt) != len(seq) or len(y_ckpt) != len(seq):
+            raise ValueError("one image and one sinogram checkpoint per iteration")
+        c_seq = (ctypes.c_int32 * max(1, len(seq)))(*seq)
+        xs = (ctypes.c_void_p * max(1, len(seq)))(*[self._img(t, "x1_ckpt") for t in x1_ckpt])
+        ys = (ctypes.c_void_p * max(1, len(seq)))(*[self._sino(t, "y_ckpt") for t in y_ckpt])
+        _lib.check(self._lib.mcr_spdhg_iterate_ckpt(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
+                                                    float(alpha), _dbl_array(sigma), float(tau), float(theta),
+                                                    _dbl_array(p), c_seq, len(seq), xs, ys))
+
+    def _grad_motion_ptr(self, gate, gm):
+        if gm is None:
+            return None
+        kind = self._kinds[int(gate)]
+        if kind == _lib.MOTION_RIGID:
+            if not (gm.dtype == torch.float64 and gm.is_cuda and gm.numel() == 3 and gm.is_contiguous()):
+                raise ValueError("a rigid motion gradient is a contiguous float64 device tensor of 3 values")
+        elif kind == _lib.MOTION_FIELD:
+            if not (gm.dtype == self.dtype and gm.is_cuda and tuple(gm.shape) == (2, self.n, self.n)
+                    and gm.is_contiguous()):
+                raise ValueError(f"a field gradient is a contiguous {self.dtype} device tensor [2][n][n]")
+        return gm.data_ptr()
+
+    def spdhg_step_backward(self, gate, x1, y_before, d_gate, alpha, sigma_g, tau, theta, p_g, gx, gy, gz, gzbar,
+                            grad_motion=None):
+        """Reverse of one SPDHG iteration (adjoints updated in place, motion gradient accumulated)."""
+        self._sync_stream()
+        _lib.check(self._lib.mcr_spdhg_step_backward(
+            self._h, int(gate), self._img(x1, "x1"), self._sino(y_before, "y_before"), self._sino(d_gate, "d_gate"),
+            float(alpha), float(sigma_g), float(tau), float(theta), float(p_g), self._img(gx, "gx"),
+            self._sino(gy, "gy"), self._img(gz, "gz"), self._img(gzbar, "gzbar"),
+            self._grad_motion_ptr(gate, grad_motion)))
+
+    def warp_motion_grad(self, gate, img, v, grad_motion):
+        """grad_motion += d/d(motion of gate) <img, D_gate v>."""
+        self._sync_stream()
+        _lib.check(self._lib.mcr_warp_motion_grad(self._h, int(gate), self._img(img, "img"), self._img(v, "v"),
+                                                  self._grad_motion_ptr(gate, grad_motion)))
 
     # -- FP64 diagnostics ----------------------------------------------------
     def power_norm_sq(self, gate: int, v0, max_iter: int = 500, rtol: float = 1e-12):

@@ -19,6 +19,7 @@
 
 #include "mcr_kernels.h"
 #include "mcr_joseph_tiled.h"
+#include "mcr_grad.h"
 
 using namespace mcr;
 
@@ -79,6 +80,8 @@ struct Work {
   hipEvent_t pin_ev = nullptr;
   bool pin_recorded = false;
   std::vector<char> last;
+  std::vector<GateScalars<T>> sc_host;  // last tables handed to upload_params
+  std::vector<GatePtrs<T>> pt_host;
 };
 
 }  // namespace
@@ -102,6 +105,7 @@ struct mcr_handle {
   double* red_out = nullptr;       // [64] result slots
   double* red_host = nullptr;      // pinned [64]
   int* need = nullptr;             // window verification
+  double* mgrad_partial = nullptr; // [ceil(n/16)^2][3] motion-gradient partial sums
   std::vector<void*> allocs;
   // float32 projector pair: kernel variants (chosen by mcr_autotune)
   struct Tune {
@@ -706,7 +710,109 @@ mcr_status set_params(mcr_handle* h, const mcr_state* st, const void* const* d, 
     pt[i].y = (T*)st->y[i];
     pt[i].d = (const T*)d[i];
   }
+  Work<T>& w = work<T>(h);
+  w.sc_host = sc;
+  w.pt_host = pt;
   return upload_params<T>(h, sc, pt);
+}
+
+// ---------------------------------------------------------------------------
+// Differentiation through unrolled SPDHG iterations
+// ---------------------------------------------------------------------------
+template <typename T>
+mcr_status launch_motion_grad(mcr_handle* h, int gate, const T* hP, const T* v, void* gmot) {
+  const int kind = h->motion[gate].kind;
+  if (kind == MCR_MOTION_IDENTITY || !gmot) return MCR_OK;
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  Timed tm(h, MCR_KERNEL_OTHER);
+  dim3 grid(cdiv(n, 16), cdiv(n, 16)), block(16, 16);
+  hipLaunchKernelGGL(k_motion_grad<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate, h->fieldP,
+                     2 * h->padded, h->padded, hP, v, h->mgrad_partial, (T*)gmot);
+  LAUNCH_OK();
+  if (kind == MCR_MOTION_RIGID) {
+    hipLaunchKernelGGL(k_motion_grad_final, dim3(1), dim3(256), 0, h->stream, h->mgrad_partial,
+                       (int)(grid.x * grid.y), (double*)gmot);
+    LAUNCH_OK();
+  }
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status spdhg_ckpt_impl(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                           const double* sigma, double tau, double theta, const double* p, const int32_t* seq,
+                           int n_iter, void* const* x1c, void* const* yc) {
+  STATUS_OK(set_params<T>(h, st, d, sigma, theta, p));
+  const T t = T(tau), cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
+  const long n2 = (long)h->geo.n * h->geo.n;
+  for (int k = 0; k < n_iter; ++k) {
+    const int g = seq[k];
+    STATUS_OK(launch_xstep<T>(h, (T*)st->x, (const T*)st->zbar, t, cx));
+    HIP_OK(hipMemcpyAsync(x1c[k], st->x, sizeof(T) * n2, hipMemcpyDeviceToDevice, h->stream));
+    HIP_OK(hipMemcpyAsync(yc[k], st->y[g], sizeof(T) * h->sino, hipMemcpyDeviceToDevice, h->stream));
+    STATUS_OK(iteration<T>(h, st, g, 1, false, false, t, cx));
+  }
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status step_backward_impl(mcr_handle* h, int gate, const void* x1, const void* yb, const void* dg,
+                              double alpha, double sigma, double tau, double theta, double p, void* gx,
+                              void* gy, void* gz, void* gzb, void* gmot) {
+  Work<T>& w = work<T>(h);
+  const int N = h->N;
+  if ((int)w.sc_host.size() != N) {
+    w.sc_host.assign(N, GateScalars<T>{});
+    w.pt_host.assign(N, GatePtrs<T>{});
+  }
+  const double cyd = 1.0 / (1.0 + sigma * N / 2.0);
+  w.sc_host[gate] = GateScalars<T>{T(sigma), T(cyd), T(theta / p), T(0)};
+  w.pt_host[gate] = GatePtrs<T>{(T*)yb, (const T*)dg};
+  STATUS_OK(upload_params<T>(h, w.sc_host, w.pt_host));
+  const long n2 = (long)h->geo.n * h->geo.n;
+  const T cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
+  const dim3 gi(cdiv(n2, 256)), gs(cdiv(h->sino, 256)), blk(256);
+  // recompute dy = y1 - y and b = A^T dy from the checkpoint
+  STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)x1));
+  STATUS_OK((launch_project<T, 2>(h, gate, 1, w.dy, h->sino)));
+  STATUS_OK(launch_backproject<T>(h, 1, w.dy, h->sino, w.bP, h->padded, 1));
+  // z / z-bar
+  {
+    Timed tm(h, MCR_KERNEL_OTHER);
+    hipLaunchKernelGGL(k_bwd_z<T>, gi, blk, 0, h->stream, n2, (T*)gz, (const T*)gzb, w.img, T(1.0 + theta / p));
+    LAUNCH_OK();
+  }
+  // dz = D^T b: gb = D gdz, and the motion through D^T
+  STATUS_OK(launch_motion_grad<T>(h, gate, w.bP, w.img, gmot));
+  STATUS_OK(launch_warp<T>(h, gate, 1, w.img));
+  // b = A^T dy, dy = y1 - y, y1 = c_y (y + sigma (s - d))
+  STATUS_OK((launch_project<T, 0>(h, gate, 1, w.dy, h->sino)));
+  {
+    Timed tm(h, MCR_KERNEL_OTHER);
+    hipLaunchKernelGGL(k_bwd_dual<T>, gs, blk, 0, h->stream, h->sino, (T*)gy, w.dy, T(cyd), T(sigma));
+    LAUNCH_OK();
+  }
+  // s = A D x1: gw = A^T gs, gx1 = gx + D^T gw, and the motion through D
+  STATUS_OK(launch_backproject<T>(h, 1, w.dy, h->sino, w.bP, h->padded, 1));
+  STATUS_OK(launch_motion_grad<T>(h, gate, w.bP, (const T*)x1, gmot));
+  STATUS_OK((launch_twarp<T, 1>(h, gate, 1, (T*)gx, UpdateArgs<T>{})));
+  // x1 = c_x (x - tau zbar)
+  {
+    Timed tm(h, MCR_KERNEL_OTHER);
+    hipLaunchKernelGGL(k_bwd_x<T>, gi, blk, 0, h->stream, n2, (T*)gx, (T*)gzb, cx, T(tau));
+    LAUNCH_OK();
+  }
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status motion_grad_impl(mcr_handle* h, int gate, const void* himg, const void* v, void* gmot) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  hipLaunchKernelGGL((k_to_padded<T, T>), dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n,
+                     h->pitch, (const T*)himg, w.bP);
+  LAUNCH_OK();
+  return launch_motion_grad<T>(h, gate, w.bP, (const T*)v, gmot);
 }
 
 template <typename T>
@@ -921,6 +1027,8 @@ mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motio
   if ((s = dmalloc(h, (void**)&h->red_partial, sizeof(double) * kRedBlocks)) != MCR_OK) return cleanup(s);
   if ((s = dmalloc(h, (void**)&h->red_out, sizeof(double) * 64)) != MCR_OK) return cleanup(s);
   if ((s = dmalloc(h, (void**)&h->need, sizeof(int) * 4)) != MCR_OK) return cleanup(s);
+  if ((s = dmalloc(h, (void**)&h->mgrad_partial, sizeof(double) * 3 * cdiv(n, 16) * cdiv(n, 16))) != MCR_OK)
+    return cleanup(s);
   if (hipHostMalloc((void**)&h->red_host, sizeof(double) * 64, hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(MCR_ERR_NOMEM, "pinned allocation failed"));
   // copy fields into the padded layout and build the window centres
@@ -1119,6 +1227,57 @@ mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const*
   STATUS_OK(check_handle(h));
   STATUS_OK(check_alg(h, st, d, alpha, sigma, tau, theta, nullptr));
   return DISPATCH(pdhg_impl, h, st, d, alpha, sigma, tau, theta);
+}
+
+mcr_status mcr_spdhg_iterate_ckpt(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                                  const double* sigma, double tau, double theta, const double* p,
+                                  const int32_t* gate_seq, int32_t n_iter, void* const* x1_ckpt,
+                                  void* const* y_ckpt) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_alg(h, st, d, alpha, sigma, tau, theta, p));
+  STATUS_OK(check_ptr(p, "p"));
+  STATUS_OK(check_ptr(gate_seq, "gate_seq"));
+  if (n_iter < 0) return fail(MCR_ERR_ARG, "n_iter = %d must be >= 0", n_iter);
+  if (n_iter > 0) {
+    STATUS_OK(check_ptr(x1_ckpt, "x1_ckpt"));
+    STATUS_OK(check_ptr(y_ckpt, "y_ckpt"));
+  }
+  for (int k = 0; k < n_iter; ++k) {
+    STATUS_OK(check_gate(h, gate_seq[k]));
+    if (!x1_ckpt[k] || !y_ckpt[k]) return fail(MCR_ERR_ARG, "checkpoint %d is null", k);
+  }
+  if (n_iter == 0) return MCR_OK;
+  return DISPATCH(spdhg_ckpt_impl, h, st, d, alpha, sigma, tau, theta, p, gate_seq, n_iter, x1_ckpt, y_ckpt);
+}
+
+mcr_status mcr_spdhg_step_backward(mcr_handle* h, int32_t gate, const void* x1, const void* y_before,
+                                   const void* d_gate, double alpha, double sigma, double tau, double theta,
+                                   double p, void* gx, void* gy_gate, void* gz, void* gzbar, void* grad_motion) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(x1, "x1"));
+  STATUS_OK(check_ptr(y_before, "y_before"));
+  STATUS_OK(check_ptr(d_gate, "d_gate"));
+  STATUS_OK(check_ptr(gx, "gx"));
+  STATUS_OK(check_ptr(gy_gate, "gy_gate"));
+  STATUS_OK(check_ptr(gz, "gz"));
+  STATUS_OK(check_ptr(gzbar, "gzbar"));
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(MCR_ERR_ARG, "alpha = %g must be finite and > 0", alpha);
+  if (!(sigma > 0) || !std::isfinite(sigma)) return fail(MCR_ERR_ARG, "sigma = %g must be finite and > 0", sigma);
+  if (!(tau > 0) || !std::isfinite(tau)) return fail(MCR_ERR_ARG, "tau = %g must be finite and > 0", tau);
+  if (!(theta >= 0) || !std::isfinite(theta)) return fail(MCR_ERR_ARG, "theta = %g must be finite and >= 0", theta);
+  if (!(p > 0) || !(p <= 1)) return fail(MCR_ERR_ARG, "p = %g must be in (0, 1]", p);
+  return DISPATCH(step_backward_impl, h, gate, x1, y_before, d_gate, alpha, sigma, tau, theta, p, gx, gy_gate, gz,
+                  gzbar, grad_motion);
+}
+
+mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, const void* v, void* grad_motion) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(img, "img"));
+  STATUS_OK(check_ptr(v, "v"));
+  STATUS_OK(check_ptr(grad_motion, "grad_motion"));
+  return DISPATCH(motion_grad_impl, h, gate, img, v, grad_motion);
 }
 
 mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int32_t max_iter, double rtol,

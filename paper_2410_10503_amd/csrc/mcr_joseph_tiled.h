@@ -143,17 +143,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_lds(Geo<float> g, const Angl
   if (!live) return;
   const float s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  if (MODE == 0) {
-    out[blockIdx.z * out_stride + idx] = s;
-  } else {
-    const int gate = gate0 + blockIdx.z;
-    const GateScalars<float> S = gs[gate];
-    const GatePtrs<float> P = gp[gate];
-    const float yv = P.y[idx];
-    const float yn = (yv + S.sigma * (s - P.d[idx])) * S.cy;
-    P.y[idx] = yn;
-    out[blockIdx.z * out_stride + idx] = yn - yv;
-  }
+  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
 }
 
 // Scheduled variant of the tiled forward: the line bands of every block, with
@@ -230,17 +220,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_sched(Geo<float> g, const An
   if (!live) return;
   const float s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  if (MODE == 0) {
-    out[blockIdx.z * out_stride + idx] = s;
-  } else {
-    const int gate = gate0 + blockIdx.z;
-    const GateScalars<float> S = gs[gate];
-    const GatePtrs<float> P = gp[gate];
-    const float yv = P.y[idx];
-    const float yn = (yv + S.sigma * (s - P.d[idx])) * S.cy;
-    P.y[idx] = yn;
-    out[blockIdx.z * out_stride + idx] = yn - yv;
-  }
+  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
 }
 
 constexpr int kAdjKC = 32;  // angles per staged chunk

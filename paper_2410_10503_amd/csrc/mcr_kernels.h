@@ -152,6 +152,27 @@ __device__ __forceinline__ void window_centre(const GateMotion<T>& M, const shor
   }
 }
 
+// Epilogue of the projection kernels for ray idx of gate slot z:
+//   MODE 0: out = A_i x
+//   MODE 1: Algorithm 1 (ii): y' = (y + sigma (A_i x - d)) / (1 + sigma N/2),
+//           y <- y', out = y' - y
+//   MODE 2: the same dy without writing y (recomputation in the reverse pass)
+template <typename T, int MODE>
+__device__ __forceinline__ void project_epilogue(T s, long idx, T* __restrict__ out, int gate,
+                                                 const GateScalars<T>* __restrict__ gs,
+                                                 const GatePtrs<T>* __restrict__ gp) {
+  if (MODE == 0) {
+    out[idx] = s;
+  } else {
+    const GateScalars<T> S = gs[gate];
+    const GatePtrs<T> P = gp[gate];
+    const T yv = P.y[idx];
+    const T yn = (yv + S.sigma * (s - P.d[idx])) * S.cy;
+    if (MODE == 1) P.y[idx] = yn;
+    out[idx] = yn - yv;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // a1: forward warp  w = D_i x  (bilinear pull-back, zero outside the image).
 // One thread per output pixel, 32x32 tiles; the tile is also written
@@ -287,17 +308,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd(Geo<T> g, const AngleT<T>* _
   if (!live) return;
   const T s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  if (MODE == 0) {
-    out[blockIdx.z * out_stride + idx] = s;
-  } else {
-    const int gate = gate0 + blockIdx.z;
-    const GateScalars<T> S = gs[gate];
-    const GatePtrs<T> P = gp[gate];
-    const T yv = P.y[idx];
-    const T yn = (yv + S.sigma * (s - P.d[idx])) * S.cy;
-    P.y[idx] = yn;
-    out[blockIdx.z * out_stride + idx] = yn - yv;   // dy of this slot
-  }
+  project_epilogue<T, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
 }
 
 // ---------------------------------------------------------------------------
@@ -453,17 +464,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const Angle
   if (!live) return;
   const float s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  if (MODE == 0) {
-    out[blockIdx.z * out_stride + idx] = s;
-  } else {
-    const int gate = gate0 + blockIdx.z;
-    const GateScalars<float> S = gs[gate];
-    const GatePtrs<float> P = gp[gate];
-    const float yv = P.y[idx];
-    const float yn = (yv + S.sigma * (s - P.d[idx])) * S.cy;
-    P.y[idx] = yn;
-    out[blockIdx.z * out_stride + idx] = yn - yv;  // dy of this slot
-  }
+  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
 }
 
 // ---------------------------------------------------------------------------
