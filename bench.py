@@ -70,6 +70,90 @@ def cpu_baseline(wl, x_true, fields_or_params):
                       f"{dt:.1f} s, scaled by 1/N"}
 
 
+def batched_measurement(steps: int, seed: int = 4):
+    """64 independent 256^2 slices (360 x 366), gate counts uniform in {4..32},
+    rigid and non-rigid motion alternating: epochs/s of the batched, graph-
+    replayed epoch, of the same without the graph, and of the per-slice form
+    (one handle per slice, epochs one after the other)."""
+    import torch
+    import synth
+    from paper_2410_10503_amd import BatchHandle, Handle, step_sizes
+    rng = np.random.default_rng(seed)
+    S, n, na, nd = 64, 256, 360, 366
+    ngs = [int(v) for v in rng.integers(4, 33, size=S)]
+    motion, images = [], []
+    for s_ in range(S):
+        ng = ngs[s_]
+        if s_ % 2:
+            f = synth.dilatation_fields(n, ng, 100 + s_)
+            motion += [("field", torch.from_numpy(f[i]).cuda()) for i in range(ng)]
+        else:
+            r = synth.rigid_params(ng, 100 + s_, 8.0, 10.0)
+            motion += [("rigid", tuple(r[i])) for i in range(ng)]
+        images.append(synth.ellipse_phantom(n, 200 + s_))
+    bh = BatchHandle(n, na, nd, ngs, motion, dtype=torch.float32)
+    G = sum(ngs)
+    d = torch.empty((G, na, nd), dtype=torch.float32, device="cuda")
+    for s_ in range(S):
+        xg = torch.from_numpy(images[s_]).cuda()
+        scale = 0.01 * float(bh.project(xg).abs().max()) / math.sqrt(ngs[s_])
+        for k in range(ngs[s_]):
+            gid = bh.offsets[s_] + k
+            bh.apply_Ai(gid, xg, d[gid])
+        noise = torch.from_numpy(synth.unit_noise((ngs[s_], na, nd), 300 + s_).astype(np.float32)).cuda()
+        d[bh.offsets[s_]:bh.offsets[s_] + ngs[s_]] += scale * noise
+    alpha = [1e-3] * S
+    sig, tau, th, p = [], [], [], []
+    for s_ in range(S):
+        a, b, c, _ = step_sizes("spdhg", [2.0 * na * n] * ngs[s_], alpha[s_], ngs[s_])
+        sig += a
+        tau.append(b)
+        th.append(c)
+        p += [1.0 / ngs[s_]] * ngs[s_]
+    variant = bh.autotune(1)
+
+    def seqs(e):
+        return [int(g) for s_ in range(S) for g in synth.gate_sequence(ngs[s_], 500 + s_, e)]
+
+    out = {"workload": f"{S} slices of {n}^2, {na}x{nd}, gates U{{4..32}} (sum {G}), rigid/field alternating",
+           "gate_iterations_per_epoch": G, "projector_variant": variant}
+    for use_graph in (True, False):
+        st = bh.zero_batch_state()
+        bh.batch_spdhg_epoch(st, d, alpha, sig, tau, th, p, seqs(0), use_graph=use_graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in range(steps):
+            bh.batch_spdhg_epoch(st, d, alpha, sig, tau, th, p, seqs(1 + e), use_graph=use_graph)
+        torch.cuda.synchronize()
+        out["epochs_per_s_graph" if use_graph else "epochs_per_s_plain"] = steps / (time.perf_counter() - t0)
+    # per-slice form: one handle per slice, same kernels and variant
+    handles = []
+    for s_ in range(S):
+        h = Handle(n, na, nd, motion[bh.offsets[s_]:bh.offsets[s_] + ngs[s_]], dtype=torch.float32)
+        h.set_variant(variant["fwd"], variant["adj_px"], variant["adj_shares"])
+        dd = [d[bh.offsets[s_] + k] for k in range(ngs[s_])]
+        handles.append((h, h.zero_state(), dd))
+
+    def per_slice_epoch(e):
+        sq = seqs(e)
+        for s_, (h, st_, dd) in enumerate(handles):
+            o = bh.offsets[s_]
+            h.spdhg_epoch(st_, dd, alpha[s_], sig[o:o + ngs[s_]], tau[s_], th[s_], p[o:o + ngs[s_]],
+                          sq[o:o + ngs[s_]])
+
+    per_slice_epoch(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(steps):
+        per_slice_epoch(1 + e)
+    torch.cuda.synchronize()
+    out["epochs_per_s_per_slice"] = steps / (time.perf_counter() - t0)
+    for h, _, _ in handles:
+        h.close()
+    bh.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,6 +162,7 @@ def main():
     ap.add_argument("--workload", default="chest512_field16")
     ap.add_argument("--pairs", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 64 x 256^2 measurement")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -221,6 +306,10 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if not args.no_batch:
+        log("batched workload: 64 slices of 256^2 ...")
+        out["batched"] = batched_measurement(max(2, args.steps // 3))
+        log(f"batched: {out['batched']}")
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on one iteration ...")
         out["cpu_baseline"] = cpu_baseline(wl, x_true, params)

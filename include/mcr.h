@@ -150,6 +150,29 @@ mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const*
                           double alpha, const double* sigma, double tau, double theta);
 
 /* ---------------------------------------------------------------------------
+ * Batches of independent slices (one geometry): slice s has gates_per_slice[s]
+ * gates; `motion` lists all gates slice after slice (global gate index =
+ * first gate of the slice + local gate). The operator entry points accept the
+ * global gate index. Workspaces hold one slot per slice; PDHG over all gates
+ * and the stacked norm are not available on a batch handle (MCR_ERR_STATE).
+ * ------------------------------------------------------------------------- */
+mcr_status mcr_batch_create(const mcr_geometry* geom, int32_t n_slices, const int32_t* gates_per_slice,
+                            const mcr_motion* motion, mcr_dtype dtype, void* stream, mcr_handle** out);
+/* One SPDHG epoch of every slice (Algorithm 1 with serial sampling; slice s
+ * runs N_s iterations): all slices take step (i), then at every step t the
+ * slices with N_s > t advance together, one launch per phase. Device arrays
+ * (handle dtype): x, z, zbar [S][n][n]; y, d [sum N_s][n_angles][n_det] in
+ * global gate order. Host arrays: alpha, tau, theta [S]; sigma, p [sum N_s];
+ * gate_seq [sum N_s], slice s's draws (local gate indices) at its first global
+ * gate. use_graph != 0 replays the epoch as a HIP graph (captured on first use
+ * and whenever x, z or zbar move) on a stream of the handle, ordered after
+ * and before the handle's stream by events.                                   */
+mcr_status mcr_batch_spdhg_epoch(mcr_handle* h, void* x, void* z, void* zbar, void* y, const void* d,
+                                 const double* alpha, const double* sigma, const double* tau,
+                                 const double* theta, const double* p, const int32_t* gate_seq,
+                                 int32_t use_graph);
+
+/* ---------------------------------------------------------------------------
  * Differentiation through unrolled SPDHG iterations (reverse mode; not in the
  * paper, built on its Algorithm 1). Gradients and checkpoints have the
  * handle's dtype; rigid motion gradients are FP64.

@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import McrError  # noqa: F401
 
-__all__ = ["Handle", "ReconState", "McrError", "step_sizes"]
+__all__ = ["Handle", "BatchHandle", "ReconState", "McrError", "step_sizes"]
 
 _DTYPES = {torch.float32: _lib.MCR_F32, torch.float64: _lib.MCR_F64}
 
@@ -329,3 +329,67 @@ class Handle:
                                           ctypes.byref(rad)))
         return {"n": geo.n, "n_angles": geo.n_angles, "n_det": geo.n_det, "n_gates": ng.value,
                 "dtype": dt.value, "window_radius": rad.value}
+
+
+class BatchHandle(Handle):
+    """S independent slices sharing one geometry, advanced one SPDHG epoch per
+    call (all slices together; optionally replayed as a HIP graph).
+
+    gates_per_slice: list of N_s; motion: one entry per gate, slice after
+    slice. State: x, z, zbar [S][n][n]; y [sum N_s][n_angles][n_det]."""
+
+    def __init__(self, n: int, n_angles: int, n_det: int, gates_per_slice, motion, dtype=torch.float32,
+                 device="cuda"):
+        self._lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the library runs on the HIP device only")
+        if dtype not in _DTYPES:
+            raise ValueError(f"dtype must be float32 or float64, not {dtype}")
+        self.n, self.n_angles, self.n_det = int(n), int(n_angles), int(n_det)
+        self.dtype = dtype
+        self.gates_per_slice = [int(v) for v in gates_per_slice]
+        self.n_slices = len(self.gates_per_slice)
+        self.n_gates = sum(self.gates_per_slice)
+        self.offsets = [sum(self.gates_per_slice[:s]) for s in range(self.n_slices)]
+        if len(motion) != self.n_gates:
+            raise ValueError(f"need {self.n_gates} motion entries, got {len(motion)}")
+        self._h = ctypes.c_void_p()
+        arr = (_lib.Motion * self.n_gates)()
+        keep = []
+        for i, m in enumerate(motion):
+            arr[i] = self._motion(m, keep)
+        self._kinds = [arr[i].kind for i in range(self.n_gates)]
+        geo = _lib.Geometry(self.n, self.n_angles, self.n_det)
+        ng = (ctypes.c_int32 * self.n_slices)(*self.gates_per_slice)
+        self._stream = _stream_ptr(self.device)
+        _lib.check(self._lib.mcr_batch_create(ctypes.byref(geo), self.n_slices, ng, arr, _DTYPES[dtype],
+                                              ctypes.c_void_p(self._stream), ctypes.byref(self._h)))
+
+    def zero_batch_state(self):
+        z = lambda *shape: torch.zeros(shape, dtype=self.dtype, device=self.device)  # noqa: E731
+        S, n = self.n_slices, self.n
+        return {"x": z(S, n, n), "z": z(S, n, n), "zbar": z(S, n, n),
+                "y": z(self.n_gates, self.n_angles, self.n_det)}
+
+    def _batch_arr(self, t, shape, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == self.dtype and tuple(t.shape) == shape
+                and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {self.dtype} device tensor of shape {shape}")
+        return t.data_ptr()
+
+    def batch_spdhg_epoch(self, st, d, alpha, sigma, tau, theta, p, gate_seq, use_graph: bool = True):
+        """alpha, tau, theta: per slice; sigma, p, gate_seq: per gate (global order);
+        gate_seq holds each slice's N_s local draws at the slice's first gate."""
+        self._sync_stream()
+        S, n, G = self.n_slices, self.n, self.n_gates
+        img = (S, n, n)
+        sino = (G, self.n_angles, self.n_det)
+        seq = [int(v) for v in gate_seq]
+        if len(seq) != G or len(sigma) != G or len(p) != G or len(alpha) != S or len(tau) != S or len(theta) != S:
+            raise ValueError("per-slice arrays need S entries and per-gate arrays sum(N_s)")
+        _lib.check(self._lib.mcr_batch_spdhg_epoch(
+            self._h, self._batch_arr(st["x"], img, "x"), self._batch_arr(st["z"], img, "z"),
+            self._batch_arr(st["zbar"], img, "zbar"), self._batch_arr(st["y"], sino, "y"),
+            self._batch_arr(d, sino, "d"), _dbl_array(alpha), _dbl_array(sigma), _dbl_array(tau),
+            _dbl_array(theta), _dbl_array(p), (ctypes.c_int32 * G)(*seq), 1 if use_graph else 0))

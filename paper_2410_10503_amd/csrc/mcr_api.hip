@@ -89,6 +89,7 @@ struct Work {
 struct mcr_handle {
   mcr_geometry geo{};
   int N = 0;
+  int nslots = 0;  // workspace slots: gates one launch may cover (N, or the slices of a batch)
   mcr_dtype dtype = MCR_F32;
   hipStream_t stream = nullptr;
   int pitch = 0;
@@ -122,6 +123,25 @@ struct mcr_handle {
   int sched_nchunks = 0;
   bool sched_ok = false;
   float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
+  // batched SPDHG (mcr_batch_create): S independent slices sharing the geometry
+  struct Batch {
+    int S = 0;                        // 0: not a batch handle
+    std::vector<int> ng, off;         // gates per slice, first global gate of each slice
+    int tmax = 0;                     // largest gate count
+    std::vector<int> nact;            // slices still iterating at step t
+    int rmax = 1;                     // largest gather-window radius
+    SlotInfo* slots = nullptr;        // device [tmax][S]
+    void* tc = nullptr;               // device [S][2] (tau, c_x) in the handle's dtype
+    void* pin = nullptr;              // pinned staging of slots + tc
+    size_t pin_bytes = 0;
+    hipEvent_t pin_ev = nullptr;
+    bool pin_recorded = false;
+    hipStream_t gstream = nullptr;    // stream the epoch graph runs on
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* key[3] = {nullptr, nullptr, nullptr};  // x, z, zbar baked into the graph
+  } batch;
   // kernel timing
   bool prof = false;
   struct Rec {
@@ -419,10 +439,11 @@ mcr_status init_work(mcr_handle* h) {
   STATUS_OK(dmalloc(h, (void**)&w.motion, sizeof(GateMotion<T>) * (N + 1)));
   STATUS_OK(dmalloc(h, (void**)&w.scalars, sizeof(GateScalars<T>) * N));
   STATUS_OK(dmalloc(h, (void**)&w.ptrs, sizeof(GatePtrs<T>) * N));
-  STATUS_OK(dmalloc(h, (void**)&w.wP, sizeof(T) * h->padded * N));
-  STATUS_OK(dmalloc(h, (void**)&w.wTP, sizeof(T) * h->padded * N));
-  STATUS_OK(dmalloc(h, (void**)&w.bP, sizeof(T) * h->padded * N));
-  STATUS_OK(dmalloc(h, (void**)&w.dy, sizeof(T) * h->sino * N));
+  const int ns = h->nslots;
+  STATUS_OK(dmalloc(h, (void**)&w.wP, sizeof(T) * h->padded * ns));
+  STATUS_OK(dmalloc(h, (void**)&w.wTP, sizeof(T) * h->padded * ns));
+  STATUS_OK(dmalloc(h, (void**)&w.bP, sizeof(T) * h->padded * ns));
+  STATUS_OK(dmalloc(h, (void**)&w.dy, sizeof(T) * h->sino * ns));
   STATUS_OK(dmalloc(h, (void**)&w.img, sizeof(T) * n2));
   STATUS_OK(dmalloc(h, (void**)&w.img2, sizeof(T) * n2));
   w.pin_bytes = (sizeof(GateScalars<T>) + sizeof(GatePtrs<T>)) * N;
@@ -439,7 +460,7 @@ mcr_status init_work(mcr_handle* h) {
     h->nchunks = (int)ch.size();
     STATUS_OK(dmalloc(h, (void**)&h->chunks, sizeof(int2) * ch.size()));
     HIP_OK(hipMemcpyAsync(h->chunks, ch.data(), sizeof(int2) * ch.size(), hipMemcpyHostToDevice, h->stream));
-    STATUS_OK(dmalloc(h, (void**)&h->parts, sizeof(float) * kMaxShares * N * n2));
+    STATUS_OK(dmalloc(h, (void**)&h->parts, sizeof(float) * kMaxShares * ns * n2));
     const Schedule sc = build_schedule(h->geo.n, h->geo.n_det, af, kFwdKA, kFwdJD, kFwdWL);
     h->sched_ok = sc.ok;
     h->sched_nchunks = (int)sc.chunks.size();
@@ -492,19 +513,21 @@ int max_radius(const mcr_handle* h, int gate0, int G) {
 // Launch helpers
 // ---------------------------------------------------------------------------
 template <typename T>
-mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x) {
+mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotInfo* slots = nullptr,
+                       long x_stride = 0) {
   Work<T>& w = work<T>(h);
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_WARP);
   dim3 grid(cdiv(n, 32), cdiv(n, 32), G), block(32, 8);
   hipLaunchKernelGGL(k_warp_fwd<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate0,
-                     h->fieldP, 2 * h->padded, h->padded, x, 0L, w.wP, w.wTP, h->padded);
+                     h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, w.wTP, h->padded, slots);
   LAUNCH_OK();
   return MCR_OK;
 }
 
 template <typename T, int MODE>
-mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stride) {
+mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stride,
+                          const SlotInfo* slots = nullptr) {
   Work<T>& w = work<T>(h);
   Timed tm(h, MCR_KERNEL_PROJECT);
   dim3 grid(cdiv(h->geo.n_det, 256), h->geo.n_angles, G), block(256);
@@ -513,19 +536,19 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
       dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->sched_nchunks, G);
       hipLaunchKernelGGL((k_joseph_fwd_sched<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
                          geo_of<T>(h), w.angfx, h->sched_chunks, h->sched_blocks, h->sched_bands, w.wP, w.wTP,
-                         h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+                         h->padded, out, out_stride, gate0, w.scalars, w.ptrs, slots);
     } else if (h->tune.fwd == 1 && h->fwd_lds_ok) {
       dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->nchunks, G);
       hipLaunchKernelGGL((k_joseph_fwd_lds<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
                          geo_of<T>(h), w.angfx, h->chunks, w.wP, w.wTP, h->padded, out, out_stride, gate0,
-                         w.scalars, w.ptrs);
+                         w.scalars, w.ptrs, slots);
     } else {
       hipLaunchKernelGGL((k_joseph_fwd_fx<MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.angfx, w.wP,
-                         w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+                         w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs, slots);
     }
   } else
     hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.ang, w.wP,
-                       w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs);
+                       w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs, slots);
   LAUNCH_OK();
   return MCR_OK;
 }
@@ -544,7 +567,7 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
       // S > 1: partial images per angle share, then a fixed-order sum
       float* dst = S > 1 ? h->parts : out;
       const long dst_stride = S > 1 ? n2 : out_stride;
-      const long part_stride = n2 * h->N;
+      const long part_stride = n2 * h->nslots;
       dim3 gt(cdiv(n, 8 * px), cdiv(n, 32), G * S);
 #define ADJ(PX)                                                                                           \
   hipLaunchKernelGGL(k_joseph_adj_lds<PX>, gt, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx, sino, \
@@ -573,17 +596,18 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
 }
 
 template <typename T, int MODE>
-mcr_status launch_twarp(mcr_handle* h, int gate0, int G, T* out, UpdateArgs<T> ua) {
+mcr_status launch_twarp(mcr_handle* h, int gate0, int G, T* out, UpdateArgs<T> ua, const SlotInfo* slots = nullptr,
+                        int nslots = 0, const T* slice_tc = nullptr, int radius = 0) {
   Work<T>& w = work<T>(h);
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_TWARP);
-  dim3 grid(cdiv(n, 16), cdiv(n, 16)), block(16, 16);
-  const int R = max_radius(h, gate0, G);
+  dim3 grid(cdiv(n, 16), cdiv(n, 16), slots ? nslots : 1), block(16, 16);
+  const int R = slots ? radius : max_radius(h, gate0, G);
   const Geo<T> g = geo_of<T>(h);
 #define TW(RR)                                                                                   \
   hipLaunchKernelGGL((k_twarp<T, MODE, RR>), grid, block, 0, h->stream, g, w.motion, gate0, G,   \
                      w.scalars, h->fieldP, 2 * h->padded, h->padded, h->centres, w.bP, h->padded, \
-                     out, ua)
+                     out, ua, slots, (long)n * n, slice_tc)
   if (R <= 1)
     TW(1);
   else if (R == 2)
@@ -899,8 +923,9 @@ mcr_status objective_impl(mcr_handle* h, const void* x, const void* const* d, do
   // chunks of up to 32 gates share one warp and one projection launch;
   // each gate's residual norm goes to result slot 1 + (gate - g0)
   double resid = 0.0;
-  for (int g0 = 0; g0 < N; g0 += 32) {
-    const int G = std::min(32, N - g0);
+  const int chunk = std::min(32, h->nslots);
+  for (int g0 = 0; g0 < N; g0 += chunk) {
+    const int G = std::min(chunk, N - g0);
     STATUS_OK(launch_warp<double>(h, g0, G, x64));
     STATUS_OK((launch_project<double, 0>(h, g0, G, w.dy, h->sino)));
     for (int i = 0; i < G; ++i)
@@ -923,8 +948,9 @@ mcr_status gap_impl(mcr_handle* h, const mcr_state* st, const void* const* d, do
   const long n2 = (long)h->geo.n * h->geo.n;
   // z = sum_i A_i^* y_i in FP64, 32 gates per launch, accumulated into img2
   double dual = 0.0;
-  for (int g0 = 0; g0 < N; g0 += 32) {
-    const int G = std::min(32, N - g0);
+  const int chunk = std::min(32, h->nslots);
+  for (int g0 = 0; g0 < N; g0 += chunk) {
+    const int G = std::min(chunk, N - g0);
     for (int i = 0; i < G; ++i) {
       hipLaunchKernelGGL((k_convert<T, double>), dim3(cdiv(h->sino, 256)), dim3(256), 0, h->stream, h->sino,
                          (const T*)st->y[g0 + i], w.dy + i * h->sino);
@@ -947,6 +973,127 @@ mcr_status gap_impl(mcr_handle* h, const mcr_state* st, const void* const* d, do
   const double val = obj + h->red_host[0] / (4.0 * alpha) + dual;
   if (!std::isfinite(val)) return fail(MCR_ERR_NONFINITE, "duality gap is not finite");
   *out = val;
+  return MCR_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// One SPDHG epoch of every slice of a batch: step (i) for all slices, then for
+// each step t the four phases over the slices still iterating (one launch
+// each, block z = slot). Kernels read gates, slices and per-slice scalars from
+// device tables, so the launch sequence does not depend on the gate draws and
+// can be replayed as a graph.
+template <typename T>
+mcr_status batch_launches(mcr_handle* h, T* x, T* z, T* zbar) {
+  Work<T>& w = work<T>(h);
+  mcr_handle::Batch& B = h->batch;
+  const long n2 = (long)h->geo.n * h->geo.n;
+  const T* tc = (const T*)B.tc;
+  {
+    Timed tm(h, MCR_KERNEL_XSTEP);
+    hipLaunchKernelGGL(k_xstep_batch<T>, dim3(cdiv(n2, 256), B.S), dim3(256), 0, h->stream, n2, x, zbar, tc);
+    LAUNCH_OK();
+  }
+  for (int t = 0; t < B.tmax; ++t) {
+    const int cnt = B.nact[t];
+    const SlotInfo* sl = B.slots + (long)t * B.S;
+    STATUS_OK(launch_warp<T>(h, 0, cnt, x, sl, n2));
+    STATUS_OK((launch_project<T, 1>(h, 0, cnt, w.dy, h->sino, sl)));
+    STATUS_OK(launch_backproject<T>(h, cnt, w.dy, h->sino, w.bP, h->padded, 1));
+    STATUS_OK((launch_twarp<T, 2>(h, 0, 1, nullptr, UpdateArgs<T>{x, z, zbar, T(0), T(0), 0}, sl, cnt, tc, B.rmax)));
+  }
+  return MCR_OK;
+}
+
+template <typename T>
+mcr_status batch_epoch_impl(mcr_handle* h, void* x, void* z, void* zbar, void* y, const void* d,
+                            const double* alpha, const double* sigma, const double* tau, const double* theta,
+                            const double* p, const int32_t* seq, int use_graph) {
+  mcr_handle::Batch& B = h->batch;
+  const int N = h->N, S = B.S;
+  // per-gate scalars and pointers (slice s has N_s gates, serial sampling p)
+  std::vector<GateScalars<T>> sc(N);
+  std::vector<GatePtrs<T>> pt(N);
+  for (int s = 0; s < S; ++s) {
+    for (int k = 0; k < B.ng[s]; ++k) {
+      const int gid = B.off[s] + k;
+      sc[gid].sigma = T(sigma[gid]);
+      sc[gid].cy = T(1.0 / (1.0 + sigma[gid] * B.ng[s] / 2.0));
+      sc[gid].coef = T(theta[s] / p[gid]);
+      sc[gid].pad_ = T(0);
+      pt[gid].y = (T*)y + (long)gid * h->sino;
+      pt[gid].d = (const T*)d + (long)gid * h->sino;
+    }
+  }
+  Work<T>& w = work<T>(h);
+  w.sc_host = sc;
+  w.pt_host = pt;
+  STATUS_OK(upload_params<T>(h, sc, pt));
+  // slot tables of this epoch's draws and the slices' (tau, c_x)
+  const size_t slot_bytes = sizeof(SlotInfo) * (size_t)B.tmax * S;
+  if (B.pin_recorded) HIP_OK(hipEventSynchronize(B.pin_ev));
+  SlotInfo* hs = (SlotInfo*)B.pin;
+  for (int t = 0; t < B.tmax; ++t) {
+    int c = 0;
+    for (int s = 0; s < S; ++s) {
+      if (B.ng[s] <= t) continue;
+      hs[(long)t * S + c] = SlotInfo{s, B.off[s] + seq[B.off[s] + t], t + 1 < B.ng[s] ? 1 : 0, 0};
+      ++c;
+    }
+    for (; c < S; ++c) hs[(long)t * S + c] = SlotInfo{0, 0, 0, 0};
+  }
+  T* htc = (T*)((char*)B.pin + slot_bytes);
+  for (int s = 0; s < S; ++s) {
+    htc[2 * s] = T(tau[s]);
+    htc[2 * s + 1] = T(1.0 / (1.0 + 2.0 * tau[s] * alpha[s]));
+  }
+  HIP_OK(hipMemcpyAsync(B.slots, B.pin, slot_bytes, hipMemcpyHostToDevice, h->stream));
+  HIP_OK(hipMemcpyAsync(B.tc, htc, sizeof(T) * 2 * S, hipMemcpyHostToDevice, h->stream));
+  HIP_OK(hipEventRecord(B.pin_ev, h->stream));
+  B.pin_recorded = true;
+  if (!use_graph) return batch_launches<T>(h, (T*)x, (T*)z, (T*)zbar);
+  // graph: captured once per (x, z, zbar), replayed on the batch stream after
+  // the uploads above (event ordering keeps the caller's stream semantics)
+  if (!B.exec || B.key[0] != x || B.key[1] != z || B.key[2] != zbar) {
+    if (B.exec) {
+      (void)hipGraphExecDestroy(B.exec);
+      B.exec = nullptr;
+    }
+    if (B.graph) {
+      (void)hipGraphDestroy(B.graph);
+      B.graph = nullptr;
+    }
+    hipStream_t caller = h->stream;
+    const bool prof = h->prof;
+    h->prof = false;
+    h->stream = B.gstream;
+    HIP_OK(hipStreamBeginCapture(B.gstream, hipStreamCaptureModeThreadLocal));
+    mcr_status st = batch_launches<T>(h, (T*)x, (T*)z, (T*)zbar);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(B.gstream, &g);
+    h->stream = caller;
+    h->prof = prof;
+    if (st != MCR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return fail(MCR_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    B.graph = g;
+    HIP_OK(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    B.key[0] = x;
+    B.key[1] = z;
+    B.key[2] = zbar;
+  }
+  HIP_OK(hipEventRecord(B.ev_in, h->stream));
+  HIP_OK(hipStreamWaitEvent(B.gstream, B.ev_in, 0));
+  {
+    Timed tm(h, MCR_KERNEL_OTHER);
+    HIP_OK(hipGraphLaunch(B.exec, B.gstream));
+  }
+  HIP_OK(hipEventRecord(B.ev_out, B.gstream));
+  HIP_OK(hipStreamWaitEvent(h->stream, B.ev_out, 0));
   return MCR_OK;
 }
 
@@ -979,6 +1126,11 @@ mcr_status time_launches(mcr_handle* h, F fn, int reps, float* ms) {
 }
 }  // namespace
 
+namespace {
+mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_motion* motion, mcr_dtype dtype,
+                       void* stream, int nslots, mcr_handle** out);
+}  // namespace
+
 // ===========================================================================
 // C ABI
 // ===========================================================================
@@ -988,6 +1140,14 @@ const char* mcr_last_error(void) { return g_err.c_str(); }
 
 mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motion* motion, mcr_dtype dtype,
                       void* stream, mcr_handle** out) {
+  return create_impl(geom, n_gates, motion, dtype, stream, 0, out);
+}
+
+}  // extern "C"
+
+namespace {
+mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_motion* motion, mcr_dtype dtype,
+                       void* stream, int nslots, mcr_handle** out) {
   if (!out) return fail(MCR_ERR_ARG, "out is null");
   *out = nullptr;
   if (!geom) return fail(MCR_ERR_ARG, "geometry is null");
@@ -1006,6 +1166,7 @@ mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motio
   h->N = n_gates;
   h->dtype = dtype;
   h->stream = (hipStream_t)stream;
+  h->nslots = nslots > 0 ? std::min(nslots, (int)n_gates) : n_gates;
   h->pitch = geom->n + 2 * kPad;
   h->padded = (long)h->pitch * h->pitch;
   h->sino = (long)geom->n_angles * geom->n_det;
@@ -1052,6 +1213,9 @@ mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motio
   *out = h;
   return MCR_OK;
 }
+}  // namespace
+
+extern "C" {
 
 mcr_status mcr_destroy(mcr_handle* h) {
   if (!h) return MCR_OK;
@@ -1068,6 +1232,13 @@ mcr_status mcr_destroy(mcr_handle* h) {
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : h->spare) (void)hipEventDestroy(e);
+  if (h->batch.exec) (void)hipGraphExecDestroy(h->batch.exec);
+  if (h->batch.graph) (void)hipGraphDestroy(h->batch.graph);
+  if (h->batch.pin) (void)hipHostFree(h->batch.pin);
+  if (h->batch.pin_ev) (void)hipEventDestroy(h->batch.pin_ev);
+  if (h->batch.ev_in) (void)hipEventDestroy(h->batch.ev_in);
+  if (h->batch.ev_out) (void)hipEventDestroy(h->batch.ev_out);
+  if (h->batch.gstream) (void)hipStreamDestroy(h->batch.gstream);
   delete h;
   return MCR_OK;
 }
@@ -1226,6 +1397,7 @@ mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const*
                           const double* sigma, double tau, double theta) {
   STATUS_OK(check_handle(h));
   STATUS_OK(check_alg(h, st, d, alpha, sigma, tau, theta, nullptr));
+  if (h->nslots < h->N) return fail(MCR_ERR_STATE, "PDHG over all gates is not available on a batch handle");
   return DISPATCH(pdhg_impl, h, st, d, alpha, sigma, tau, theta);
 }
 
@@ -1284,6 +1456,8 @@ mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int3
                              double* out, int32_t* iters) {
   STATUS_OK(check_handle(h));
   if (gate != -1) STATUS_OK(check_gate(h, gate));
+  if (gate == -1 && h->nslots < h->N)
+    return fail(MCR_ERR_STATE, "the stacked norm over all gates is not available on a batch handle");
   STATUS_OK(check_ptr(v0, "v0"));
   STATUS_OK(check_ptr(out, "out"));
   if (max_iter < 1) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 1", max_iter);
@@ -1426,6 +1600,88 @@ mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t a
   h->tune.adj_px = adj_px;
   h->tune.adj_s = adj_s;
   return MCR_OK;
+}
+
+mcr_status mcr_batch_create(const mcr_geometry* geom, int32_t n_slices, const int32_t* gates_per_slice,
+                            const mcr_motion* motion, mcr_dtype dtype, void* stream, mcr_handle** out) {
+  if (!out) return fail(MCR_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (n_slices < 1 || n_slices > 4096) return fail(MCR_ERR_ARG, "n_slices = %d must be in [1, 4096]", n_slices);
+  STATUS_OK(check_ptr(gates_per_slice, "gates_per_slice"));
+  long total = 0;
+  int tmax = 0;
+  for (int s = 0; s < n_slices; ++s) {
+    if (gates_per_slice[s] < 1) return fail(MCR_ERR_ARG, "slice %d has %d gates", s, gates_per_slice[s]);
+    total += gates_per_slice[s];
+    tmax = std::max(tmax, (int)gates_per_slice[s]);
+  }
+  if (total > 4096) return fail(MCR_ERR_ARG, "%ld gates in total exceed 4096", total);
+  mcr_handle* h = nullptr;
+  STATUS_OK(create_impl(geom, (int)total, motion, dtype, stream, n_slices, &h));
+  mcr_handle::Batch& B = h->batch;
+  B.S = n_slices;
+  B.ng.assign(gates_per_slice, gates_per_slice + n_slices);
+  B.off.resize(n_slices);
+  for (int s = 0, o = 0; s < n_slices; o += B.ng[s], ++s) B.off[s] = o;
+  B.tmax = tmax;
+  B.nact.resize(tmax);
+  for (int t = 0; t < tmax; ++t) {
+    int c = 0;
+    for (int s = 0; s < n_slices; ++s) c += B.ng[s] > t;
+    B.nact[t] = c;
+  }
+  for (int r : h->radius) B.rmax = std::max(B.rmax, r);
+  const size_t esz = dtype == MCR_F32 ? sizeof(float) : sizeof(double);
+  const size_t slot_bytes = sizeof(SlotInfo) * (size_t)tmax * n_slices;
+  mcr_status st = dmalloc(h, (void**)&B.slots, slot_bytes);
+  if (st == MCR_OK) st = dmalloc(h, &B.tc, esz * 2 * n_slices);
+  B.pin_bytes = slot_bytes + esz * 2 * n_slices;
+  if (st == MCR_OK && hipHostMalloc(&B.pin, B.pin_bytes, hipHostMallocDefault) != hipSuccess)
+    st = fail(MCR_ERR_NOMEM, "pinned allocation failed");
+  if (st == MCR_OK && (hipEventCreateWithFlags(&B.pin_ev, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming) != hipSuccess ||
+                       hipEventCreateWithFlags(&B.ev_out, hipEventDisableTiming) != hipSuccess ||
+                       hipStreamCreateWithFlags(&B.gstream, hipStreamNonBlocking) != hipSuccess))
+    st = fail(MCR_ERR_HIP, "could not create the batch stream and events");
+  if (st == MCR_OK && hipStreamSynchronize(h->stream) != hipSuccess) st = fail(MCR_ERR_HIP, "batch set-up failed");
+  if (st != MCR_OK) {
+    mcr_destroy(h);
+    return st;
+  }
+  *out = h;
+  return MCR_OK;
+}
+
+mcr_status mcr_batch_spdhg_epoch(mcr_handle* h, void* x, void* z, void* zbar, void* y, const void* d,
+                                 const double* alpha, const double* sigma, const double* tau, const double* theta,
+                                 const double* p, const int32_t* gate_seq, int32_t use_graph) {
+  STATUS_OK(check_handle(h));
+  if (h->batch.S == 0) return fail(MCR_ERR_STATE, "not a batch handle (use mcr_batch_create)");
+  STATUS_OK(check_ptr(x, "x"));
+  STATUS_OK(check_ptr(z, "z"));
+  STATUS_OK(check_ptr(zbar, "zbar"));
+  STATUS_OK(check_ptr(y, "y"));
+  STATUS_OK(check_ptr(d, "d"));
+  STATUS_OK(check_ptr(alpha, "alpha"));
+  STATUS_OK(check_ptr(sigma, "sigma"));
+  STATUS_OK(check_ptr(tau, "tau"));
+  STATUS_OK(check_ptr(theta, "theta"));
+  STATUS_OK(check_ptr(p, "p"));
+  STATUS_OK(check_ptr(gate_seq, "gate_seq"));
+  const mcr_handle::Batch& B = h->batch;
+  for (int s = 0; s < B.S; ++s) {
+    if (!(alpha[s] > 0) || !std::isfinite(alpha[s])) return fail(MCR_ERR_ARG, "alpha[%d] must be finite and > 0", s);
+    if (!(tau[s] > 0) || !std::isfinite(tau[s])) return fail(MCR_ERR_ARG, "tau[%d] must be finite and > 0", s);
+    if (!(theta[s] >= 0) || !std::isfinite(theta[s])) return fail(MCR_ERR_ARG, "theta[%d] must be finite and >= 0", s);
+    for (int k = 0; k < B.ng[s]; ++k) {
+      const int gid = B.off[s] + k;
+      if (!(sigma[gid] > 0) || !std::isfinite(sigma[gid])) return fail(MCR_ERR_ARG, "sigma[%d] must be finite and > 0", gid);
+      if (!(p[gid] > 0) || !(p[gid] <= 1)) return fail(MCR_ERR_ARG, "p[%d] must be in (0, 1]", gid);
+      if (gate_seq[gid] < 0 || gate_seq[gid] >= B.ng[s])
+        return fail(MCR_ERR_ARG, "gate_seq[%d] = %d is not a gate of slice %d (it has %d)", gid, gate_seq[gid], s, B.ng[s]);
+    }
+  }
+  return DISPATCH(batch_epoch_impl, h, x, z, zbar, y, d, alpha, sigma, tau, theta, p, gate_seq, use_graph);
 }
 
 mcr_status mcr_profile_enable(mcr_handle* h, int32_t enable) {

@@ -30,7 +30,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_lds(Geo<float> g, const Angl
                                                         const float* __restrict__ wTP, long w_stride,
                                                         float* __restrict__ out, long out_stride, int gate0,
                                                         const GateScalars<float>* __restrict__ gs,
-                                                        const GatePtrs<float>* __restrict__ gp) {
+                                                        const GatePtrs<float>* __restrict__ gp,
+                                                        const SlotInfo* __restrict__ slots) {
   static_assert(KA * JD == 256, "one ray per thread");
   __shared__ float st[kFwdMaxBand * WL];
   __shared__ int s_lo, s_hi;
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_lds(Geo<float> g, const Angl
   if (!live) return;
   const float s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
+  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, slot_gate(slots, gate0), gs, gp);
 }
 
 // Scheduled variant of the tiled forward: the line bands of every block, with
@@ -164,7 +165,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_sched(Geo<float> g, const An
                                                           const float* __restrict__ wTP, long w_stride,
                                                           float* __restrict__ out, long out_stride, int gate0,
                                                           const GateScalars<float>* __restrict__ gs,
-                                                          const GatePtrs<float>* __restrict__ gp) {
+                                                          const GatePtrs<float>* __restrict__ gp,
+                                                          const SlotInfo* __restrict__ slots) {
   static_assert(KA * JD == 256, "one ray per thread");
   constexpr int kPer = kFwdMaxBand * WL / 256;
   __shared__ float st[kFwdMaxBand * WL];
@@ -220,7 +222,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_sched(Geo<float> g, const An
   if (!live) return;
   const float s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
+  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, slot_gate(slots, gate0), gs, gp);
 }
 
 constexpr int kAdjKC = 32;  // angles per staged chunk

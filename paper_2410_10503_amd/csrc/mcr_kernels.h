@@ -95,6 +95,20 @@ struct Geo {
   T jc;  // (n_det-1)/2
 };
 
+// Batched launches: block z works on slot z, which belongs to image `slice`
+// and gate `gate` (an index into the handle's flat gate tables); do_x asks the
+// update to fuse the next step (i) of that slice.
+struct SlotInfo {
+  int slice;
+  int gate;
+  int do_x;
+  int pad_;
+};
+
+__device__ __forceinline__ int slot_gate(const SlotInfo* slots, int gate0) {
+  return slots ? slots[blockIdx.z].gate : gate0 + (int)blockIdx.z;
+}
+
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -186,15 +200,16 @@ __global__ __launch_bounds__(256) void k_warp_fwd(Geo<T> g, const GateMotion<T>*
                                                   long field_stride, long plane_stride,
                                                   const T* __restrict__ x, long x_stride,
                                                   T* __restrict__ wP, T* __restrict__ wTP,
-                                                  long w_stride) {
+                                                  long w_stride, const SlotInfo* __restrict__ slots) {
   __shared__ T tile[32][33];
-  const int gate = gate0 + blockIdx.z;
+  const int gate = slot_gate(slots, gate0);
+  const int slice = slots ? slots[blockIdx.z].slice : (int)blockIdx.z;
   const GateMotion<T> M = gm[gate];
   const int n = g.n, pitch = g.pitch;
   const long origin = (long)kPad * pitch + kPad;
   const float* ux = field + gate * field_stride + origin;
   const float* uy = ux + plane_stride;
-  const T* src = x + blockIdx.z * x_stride;
+  const T* src = x + slice * x_stride;
   T* dst = wP + blockIdx.z * w_stride + origin;
   T* dstT = wTP + blockIdx.z * w_stride + origin;
   const int c = blockIdx.x * 32 + threadIdx.x;
@@ -249,7 +264,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd(Geo<T> g, const AngleT<T>* _
                                                     const T* __restrict__ wTP, long w_stride,
                                                     T* __restrict__ out, long out_stride,
                                                     int gate0, const GateScalars<T>* __restrict__ gs,
-                                                    const GatePtrs<T>* __restrict__ gp) {
+                                                    const GatePtrs<T>* __restrict__ gp,
+                                                    const SlotInfo* __restrict__ slots) {
   __shared__ int s_lo, s_hi;
   const int k = blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
@@ -308,7 +324,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd(Geo<T> g, const AngleT<T>* _
   if (!live) return;
   const T s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  project_epilogue<T, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
+  project_epilogue<T, MODE>(s, idx, out + blockIdx.z * out_stride, slot_gate(slots, gate0), gs, gp);
 }
 
 // ---------------------------------------------------------------------------
@@ -378,7 +394,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const Angle
                                                        const float* __restrict__ wTP, long w_stride,
                                                        float* __restrict__ out, long out_stride, int gate0,
                                                        const GateScalars<float>* __restrict__ gs,
-                                                       const GatePtrs<float>* __restrict__ gp) {
+                                                       const GatePtrs<float>* __restrict__ gp,
+                                                       const SlotInfo* __restrict__ slots) {
   __shared__ int s_lo, s_hi;
   const int k = blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
@@ -464,7 +481,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const Angle
   if (!live) return;
   const float s = A.ds * acc;
   const long idx = (long)k * g.nd + j;
-  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, gate0 + blockIdx.z, gs, gp);
+  project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, slot_gate(slots, gate0), gs, gp);
 }
 
 // ---------------------------------------------------------------------------
@@ -531,6 +548,9 @@ struct UpdateArgs {
   int do_x;
 };
 
+// With a slot table (batched SPDHG) block z handles slot z alone (G = 1): its
+// gate, its slice's x, z, zbar (slice_stride apart), that slice's (tau, c_x)
+// from slice_tc and the slot's do_x.
 template <typename T, int MODE, int R>
 __global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __restrict__ gm,
                                                int gate0, int G,
@@ -538,17 +558,33 @@ __global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __
                                                const float* __restrict__ field, long field_stride,
                                                long plane_stride, const short2* __restrict__ centres,
                                                const T* __restrict__ bP, long b_stride,
-                                               T* __restrict__ out, UpdateArgs<T> ua) {
+                                               T* __restrict__ out, UpdateArgs<T> ua,
+                                               const SlotInfo* __restrict__ slots, long slice_stride,
+                                               const T* __restrict__ slice_tc) {
   const int qc = blockIdx.x * 16 + threadIdx.x;
   const int qr = blockIdx.y * 16 + threadIdx.y;
   const int n = g.n, pitch = g.pitch;
   if (qc >= n || qr >= n) return;
   const long origin = (long)kPad * pitch + kPad;
+  int slot0 = 0;
+  if (slots) {
+    const SlotInfo si = slots[blockIdx.z];
+    slot0 = (int)blockIdx.z;
+    gate0 = si.gate;
+    G = 1;
+    const long off = (long)si.slice * slice_stride;
+    ua.x += off;
+    ua.z += off;
+    ua.zbar += off;
+    ua.tau = slice_tc[2 * si.slice];
+    ua.cx = slice_tc[2 * si.slice + 1];
+    ua.do_x = si.do_x;
+  }
   T dz = T(0), dzb = T(0);
   for (int gi = 0; gi < G; ++gi) {
     const int gate = gate0 + gi;
     const GateMotion<T> M = gm[gate];
-    const T* b = bP + gi * b_stride + origin;
+    const T* b = bP + (slot0 + gi) * b_stride + origin;
     T part = T(0);
     if (M.kind == 0) {
       part = b[(long)qr * pitch + qc];
@@ -592,6 +628,18 @@ __global__ __launch_bounds__(256) void k_xstep(long count, T* __restrict__ x,
                                                const T* __restrict__ zbar, T tau, T cx) {
   const long i = (long)blockIdx.x * 256 + threadIdx.x;
   if (i < count) x[i] = (x[i] - tau * zbar[i]) * cx;
+}
+
+// Step (i) for every slice of a batch: x = (x - tau zbar) c_x with the
+// slice's (tau, c_x). grid (ceil(n*n/256), slices)
+template <typename T>
+__global__ __launch_bounds__(256) void k_xstep_batch(long count, T* __restrict__ x, const T* __restrict__ zbar,
+                                                     const T* __restrict__ slice_tc) {
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const long o = (long)blockIdx.y * count + i;
+  const T tau = slice_tc[2 * blockIdx.y], cx = slice_tc[2 * blockIdx.y + 1];
+  x[o] = (x[o] - tau * zbar[o]) * cx;
 }
 
 // Copy an unpadded image into the interior of a padded one (converting type).
