@@ -51,6 +51,27 @@ def joseph_nnz(n: int, na: int, nd: int) -> int:
     return total
 
 
+def measured_traffic(dominant: str, variant: dict):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/), or None when that summary is for another kernel or
+    the kernel sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_joseph_fwd_chest512_field16.md")
+    if dominant != "project" or variant.get("fwd") != 2 or not os.path.exists(path):
+        return None
+    line = next((ln for ln in open(path) if ln.startswith("traffic: ")), None)
+    if line is None:
+        return None
+    fields = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
+    h = hashlib.sha256()
+    for src in ("mcr_joseph_tiled.h", "mcr_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2410_10503_amd", "csrc", src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest()[:16] != fields.get("sources_sha256_16"):
+        return None
+    return float(fields["fetch_bytes"]) + float(fields["write_bytes"])
+
+
 def cpu_baseline(wl, x_true, fields_or_params):
     """The FP64 oracle (untuned) on one SPDHG iteration of the same workload,
     scaled to epochs/s (an epoch is N such iterations)."""
@@ -163,6 +184,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64 x 256^2 measurement")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also copy 256 MiB once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -277,7 +300,7 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, variant)
     roof["kernel"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
     roof["hbm_gbs_algorithmic"] = bytes_ / avg_s / 1e9
@@ -306,6 +329,14 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if args.copy_probe:
+        a = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        bcopy = torch.empty_like(a)
+        torch.cuda.synchronize()
+        bcopy.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = a.numel() * 4
+        del a, bcopy
     if not args.no_batch:
         log("batched workload: 64 slices of 256^2 ...")
         out["batched"] = batched_measurement(max(2, args.steps // 3))
