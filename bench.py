@@ -175,6 +175,55 @@ def batched_measurement(steps: int, seed: int = 4):
     return out
 
 
+def autograd_measurement(reps: int = 3):
+    """Differentiation through 10 unrolled SPDHG iterations at 512^2, 720 x 730,
+    16 rigid gates: the plain 10 iterations against the checkpointed forward
+    plus the reverse pass (image and 48 motion gradients)."""
+    import torch
+    import synth
+    from paper_2410_10503_amd import Handle, step_sizes
+    from paper_2410_10503_amd.autograd import unrolled_spdhg
+    wl = synth.WORKLOADS["ellipses512_rigid16"]
+    N = wl.n_gates
+    params = wl.rigid()
+    h = Handle(wl.n, wl.n_angles, wl.n_det, [("rigid", tuple(params[i])) for i in range(N)], dtype=torch.float32)
+    h.autotune(1)
+    xg = torch.from_numpy(wl.image()).cuda()
+    d = [h.apply_Ai(i, xg) for i in range(N)]
+    sigma, tau, theta, _ = step_sizes("spdhg", [3.7e5] * N, wl.alpha, N)
+    p = [1.0 / N] * N
+    seq = [int(g) for g in synth.gate_sequence(N, wl.gate_seed, 0, length=10)]
+    x0 = (0.8 * xg).contiguous()
+    mot = torch.tensor(params, dtype=torch.float64, device="cuda")
+
+    def plain():
+        st = h.zero_state()
+        st.x.copy_(x0)
+        h.spdhg_iterate(st, d, wl.alpha, sigma, tau, theta, p, seq)
+        return st.x
+
+    def with_grad():
+        xr = x0.clone().requires_grad_(True)
+        mr = mot.clone().requires_grad_(True)
+        xk = unrolled_spdhg(h, xr, mr, d, wl.alpha, sigma, tau, theta, p, seq)
+        torch.sum((xk - xg) ** 2).backward()
+        return xr.grad
+
+    out = {"workload": "10 unrolled SPDHG iterations, 512^2, 720x730, 16 rigid gates, gradients w.r.t. "
+                       "the start image and 48 rigid parameters"}
+    for name, fn in (("plain_forward_ms", plain), ("forward_and_backward_ms", with_grad)):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = 1e3 * (time.perf_counter() - t0) / reps
+    out["ratio"] = out["forward_and_backward_ms"] / out["plain_forward_ms"]
+    h.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -184,6 +233,7 @@ def main():
     ap.add_argument("--pairs", type=int, default=160)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64 x 256^2 measurement")
+    ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -341,6 +391,10 @@ def main():
         log("batched workload: 64 slices of 256^2 ...")
         out["batched"] = batched_measurement(max(2, args.steps // 3))
         log(f"batched: {out['batched']}")
+    if not args.no_autograd:
+        log("differentiation through 10 unrolled iterations ...")
+        out["autograd"] = autograd_measurement()
+        log(f"autograd: {out['autograd']}")
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on one iteration ...")
         out["cpu_baseline"] = cpu_baseline(wl, x_true, params)
