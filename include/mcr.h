@@ -109,6 +109,11 @@ mcr_status mcr_destroy(mcr_handle* h);
 mcr_status mcr_set_stream(mcr_handle* h, void* stream);
 /* Replace the motion of one gate (synchronises the handle's stream first). */
 mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion);
+/* Replace the rigid parameters of every gate at once (host [N][3] doubles:
+ * phi, t_x, t_y); all gates must be rigid. Asynchronous: the update is queued
+ * on the handle's stream (no synchronisation, no window check: a 3 x 3 gather
+ * window covers any rotation).                                                */
+mcr_status mcr_set_rigid_params(mcr_handle* h, const double* params);
 /* Sizes and settings of a handle (any pointer may be NULL). */
 mcr_status mcr_get_info(const mcr_handle* h, mcr_geometry* geom, int32_t* n_gates,
                         mcr_dtype* dtype, int32_t* window_radius);

@@ -163,6 +163,14 @@ class Handle:
         _lib.check(self._lib.mcr_set_motion(self._h, int(gate), ctypes.byref(m)))
         self._kinds[int(gate)] = m.kind
 
+    def set_rigid_params(self, params):
+        """All gates' rigid (phi, t_x, t_y) at once, [N][3]; queued on the stream."""
+        vals = [float(v) for row in params for v in row]
+        if len(vals) != 3 * self.n_gates:
+            raise ValueError(f"need {self.n_gates} x 3 rigid parameters")
+        self._sync_stream()
+        _lib.check(self._lib.mcr_set_rigid_params(self._h, _dbl_array(vals)))
+
     def warp(self, gate, x, out=None):
         self._sync_stream()
         out = self.new_image() if out is None else out

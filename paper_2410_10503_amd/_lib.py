@@ -47,6 +47,7 @@ SIGNATURES = {
     "mcr_destroy": [_P],
     "mcr_set_stream": [_P, _P],
     "mcr_set_motion": [_P, _I, ctypes.POINTER(Motion)],
+    "mcr_set_rigid_params": [_P, _PD],
     "mcr_get_info": [_P, ctypes.POINTER(Geometry), _PI, _PI, _PI],
     "mcr_warp": [_P, _I, _P, _P],
     "mcr_warp_adjoint": [_P, _I, _P, _P],

@@ -16,11 +16,11 @@ import torch
 
 
 def _apply_motion(handle, kind: str, motion: torch.Tensor):
+    if kind == "rigid":
+        handle.set_rigid_params(motion.detach().to(torch.float64).cpu().tolist())
+        return
     for i in range(handle.n_gates):
-        if kind == "rigid":
-            handle.set_motion(i, ("rigid", tuple(float(v) for v in motion[i].detach().cpu().tolist())))
-        else:
-            handle.set_motion(i, ("field", motion[i].detach().to(torch.float32).contiguous()))
+        handle.set_motion(i, ("field", motion[i].detach().to(torch.float32).contiguous()))
 
 
 class UnrolledSPDHG(torch.autograd.Function):

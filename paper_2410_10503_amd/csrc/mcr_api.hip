@@ -107,6 +107,9 @@ struct mcr_handle {
   double* red_host = nullptr;      // pinned [64]
   int* need = nullptr;             // window verification
   double* mgrad_partial = nullptr; // [ceil(n/16)^2][3] motion-gradient partial sums
+  void* mot_pin = nullptr;         // pinned staging of the motion tables (mcr_set_rigid_params)
+  hipEvent_t mot_ev = nullptr;
+  bool mot_recorded = false;
   std::vector<void*> allocs;
   // float32 projector pair: kernel variants (chosen by mcr_autotune)
   struct Tune {
@@ -1232,6 +1235,8 @@ mcr_status mcr_destroy(mcr_handle* h) {
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : h->spare) (void)hipEventDestroy(e);
+  if (h->mot_pin) (void)hipHostFree(h->mot_pin);
+  if (h->mot_ev) (void)hipEventDestroy(h->mot_ev);
   if (h->batch.exec) (void)hipGraphExecDestroy(h->batch.exec);
   if (h->batch.graph) (void)hipGraphDestroy(h->batch.graph);
   if (h->batch.pin) (void)hipHostFree(h->batch.pin);
@@ -1305,6 +1310,43 @@ mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion)
   }
   STATUS_OK(upload_motion<double>(h));
   if (h->wf.ready) STATUS_OK(upload_motion<float>(h));
+  return MCR_OK;
+}
+
+// Rigid motion needs no window check. Output pixel p of the transposed warp
+// gathers from the pixels q whose sample position R q + t lies within one
+// pixel of p (per axis), i.e. q in R^T (p - t + (-1, 1)^2): per axis within
+// |cos| + |sin| <= sqrt(2) of the exact inverse image c = R^T (p - t). Centred
+// on round(c), every such q is within sqrt(2) + 1/2 < 2, hence (being integer)
+// within 1: the 3 x 3 window holds them all.
+mcr_status mcr_set_rigid_params(mcr_handle* h, const double* params) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_ptr(params, "params"));
+  for (int i = 0; i < h->N; ++i) {
+    if (h->motion[i].kind != MCR_MOTION_RIGID) return fail(MCR_ERR_STATE, "gate %d is not rigid", i);
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(params[3 * i + k])) return fail(MCR_ERR_ARG, "params[%d][%d] is not finite", i, k);
+  }
+  const size_t bd = sizeof(GateMotion<double>) * (h->N + 1), bf = sizeof(GateMotion<float>) * (h->N + 1);
+  if (!h->mot_pin) {
+    HIP_OK(hipHostMalloc(&h->mot_pin, bd + bf, hipHostMallocDefault));
+    HIP_OK(hipEventCreateWithFlags(&h->mot_ev, hipEventDisableTiming));
+  }
+  if (h->mot_recorded) HIP_OK(hipEventSynchronize(h->mot_ev));
+  for (int i = 0; i < h->N; ++i) {
+    for (int k = 0; k < 3; ++k) h->motion[i].rigid[k] = params[3 * i + k];
+    h->radius[i] = 1;
+  }
+  GateMotion<double>* md = (GateMotion<double>*)h->mot_pin;
+  GateMotion<float>* mf = (GateMotion<float>*)((char*)h->mot_pin + bd);
+  for (int i = 0; i <= h->N; ++i) {
+    md[i] = gate_motion<double>(h, i);
+    mf[i] = gate_motion<float>(h, i);
+  }
+  HIP_OK(hipMemcpyAsync(h->wd.motion, md, bd, hipMemcpyHostToDevice, h->stream));
+  if (h->wf.ready) HIP_OK(hipMemcpyAsync(h->wf.motion, mf, bf, hipMemcpyHostToDevice, h->stream));
+  HIP_OK(hipEventRecord(h->mot_ev, h->stream));
+  h->mot_recorded = true;
   return MCR_OK;
 }
 

@@ -147,3 +147,36 @@ def test_full_size_rigid16_ten_iterations():
                 fd = (run(h64, torch.float64, d64, pp, False) - run(h64, torch.float64, d64, pm, False)) / (2 * hstep)
                 an = float(gm64[g, m])
                 assert abs(fd - an) <= tol * max(abs(an), 1e-2 * scale), (hstep, g, m, fd, an)
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_set_rigid_params_equals_set_motion(dtype):
+    # the queued all-gates update gives the same operators, bit for bit, as
+    # per-gate updates (which verify their windows on the device)
+    P = Problem(96, 80, 140, 5, "rigid", max_rot=20.0, max_shift=6.0)
+    new = synth.rigid_params(5, 77, 25.0, 8.0)
+    a, b = P.handle(dtype), P.handle(dtype)
+    for i in range(5):
+        a.set_motion(i, ("rigid", tuple(float(v) for v in new[i])))
+    b.set_rigid_params(new.astype(np.float64).tolist())
+    x = dev(f32(synth.random_image(96, 3)), dtype)
+    y = dev(f32(synth.random_sinograms(1, 80, 140, 4)[0]), dtype)
+    for i in range(5):
+        assert torch.equal(a.apply_Ai(i, x), b.apply_Ai(i, x))
+        assert torch.equal(a.apply_Ai_adjoint(i, y), b.apply_Ai_adjoint(i, y))
+        assert torch.equal(a.warp_adjoint(i, x), b.warp_adjoint(i, x))
+    # twice in a row: the staging is reused once the previous upload is done
+    b.set_rigid_params(P.params.astype(np.float64).tolist())
+    c = P.handle(dtype)
+    for i in range(5):
+        assert torch.equal(c.apply_Ai(i, x), b.apply_Ai(i, x))
+
+
+def test_set_rigid_params_rejects_field_handles():
+    from paper_2410_10503_amd import McrError
+    P = Problem(32, 20, 46, 2, "field")
+    h = P.handle(torch.float32)
+    with pytest.raises(McrError):
+        h.set_rigid_params([[0.0, 0.0, 0.0]] * 2)
+    with pytest.raises(ValueError):
+        h.set_rigid_params([[0.0, 0.0, 0.0]])
