@@ -57,12 +57,14 @@ def measured_traffic(dominant: str, variant: dict):
     the kernel sources have changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_joseph_fwd_chest512_field16.md")
-    if dominant != "project" or variant.get("fwd") != 2 or not os.path.exists(path):
+    if dominant != "project" or not os.path.exists(path):
         return None
     line = next((ln for ln in open(path) if ln.startswith("traffic: ")), None)
     if line is None:
         return None
     fields = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
+    if fields.get("fwd") != str(variant.get("fwd")):
+        return None
     h = hashlib.sha256()
     for src in ("mcr_joseph_tiled.h", "mcr_kernels.h"):
         with open(os.path.join(ROOT, "paper_2410_10503_amd", "csrc", src), "rb") as f:

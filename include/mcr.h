@@ -246,7 +246,10 @@ mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq,
  * forward:  0 = one thread per ray, 1 = LDS-tiled (8 angles x 32 bins share a
  *           staged image band; only where every band window fits in LDS),
  *           2 = the same with the bands scheduled on the host and the next
- *           band prefetched while the current one is computed;
+ *           band prefetched while the current one is computed,
+ *           3 = host-scheduled bands whose window shifts line by line with
+ *           the chunk's mean ray slope (up to 16 angles x 32 bins, two rays
+ *           per thread; the default where it applies);
  * adjoint:  adj_px = 0 one thread per pixel, or 1, 2, 4 pixels per thread with
  *           LDS-staged sinogram chunks, the angles split into adj_s (1..4)
  *           shares whose partial images are summed in a fixed order.

@@ -113,7 +113,8 @@ struct mcr_handle {
   std::vector<void*> allocs;
   // float32 projector pair: kernel variants (chosen by mcr_autotune)
   struct Tune {
-    int fwd = 2;     // 0 one thread per ray, 1 LDS-tiled (8 angles x 32 bins), 2 the same with a host band schedule
+    int fwd = 3;     // 0 one thread per ray, 1 LDS-tiled (8 angles x 32 bins), 2 the same with a host band
+                     // schedule, 3 line-sheared bands (16 angles x 32 bins, two rays per thread)
     int adj_px = 4;  // 0 one thread per pixel; 1, 2, 4 pixels per thread (LDS-tiled)
     int adj_s = 4;   // angle shares per pixel tile (LDS-tiled adjoint)
   } tune;
@@ -125,6 +126,10 @@ struct mcr_handle {
   int4* sched_bands = nullptr;     // (L0, lines, window start, window width)
   int sched_nchunks = 0;
   bool sched_ok = false;
+  int4* shear_chunks = nullptr;    // line-sheared forward: (k0, count, Bm low, Bm high) per chunk
+  int2* shear_blocks = nullptr;    // (first band, bands) per (chunk, detector tile)
+  int4* shear_bands = nullptr;     // (L0, lines, window start, log2 of the LDS line pitch)
+  int shear_nchunks = 0;
   float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
   // batched SPDHG (mcr_batch_create): S independent slices sharing the geometry
   struct Batch {
@@ -365,11 +370,116 @@ struct Schedule {
   bool ok = true;
 };
 
+// Lines [L_lo, L_hi] on which some ray of angles [k0, k0 + cnt) and bins
+// [jf, jl] crosses inside (-1, n), widened by a margin of 2; empty if L_lo > L_hi.
+void block_lines(int n, int nd, const std::vector<AngleFx>& af, int k0, int cnt, int jf, int jl, int& L_lo,
+                 int& L_hi) {
+  const double hc = (n - 1) / 2.0, jc = (nd - 1) / 2.0;
+  double lo = n, hi = -1;
+  for (int a = 0; a < cnt; ++a) {
+    const AngleFx& A = af[k0 + a];
+    const double a_ = double(A.A) / 4294967296.0, b_ = double(A.B) / 4294967296.0;
+    const double ta_f = (jf - jc) * a_ + hc, ta_l = (jl - jc) * a_ + hc;  // crossings on the centre line
+    if (std::fabs(b_) < 1e-12) {  // crossings do not move with the line
+      if (std::max(ta_f, ta_l) > -1.0 && std::min(ta_f, ta_l) < n) {
+        lo = 0;
+        hi = n - 1;
+      }
+      continue;
+    }
+    for (double ta : {ta_f, ta_l}) {
+      const double u1 = (-1.0 - ta) / b_ + hc, u2 = (n - ta) / b_ + hc;
+      lo = std::min(lo, std::min(u1, u2));
+      hi = std::max(hi, std::max(u1, u2));
+    }
+  }
+  L_lo = std::max(0, (int)std::floor(std::max(lo, -4.0)) - 2);
+  L_hi = std::min(n - 1, (int)std::ceil(std::min(hi, n + 4.0)) + 2);
+}
+
+// Bands of one block of the line-sheared forward (exact integer arithmetic on
+// the kernel's constants): the window of band line l is shifted by
+// o_l = floor(l Bm / 2^32). A band of BL lines with window width W is staged
+// with a power-of-two line pitch P >= max(64, W) and needs BL * P <= kShCap
+// entries; bands start at kShBL lines and are shortened until they fit.
+// Returns false if a single line does not fit.
+bool shear_tile_bands(int n, int nd, const std::vector<AngleFx>& af, int k0, int cnt, long long Bm, int jf, int jl,
+                      std::vector<int4>& bands) {
+  int L_lo, L_hi;
+  block_lines(n, nd, af, k0, cnt, jf, jl, L_lo, L_hi);
+  for (int L0 = L_lo; L0 <= L_hi;) {
+    int bl = std::min(kShBL, L_hi - L0 + 1);
+    int S0 = 0, lp = 6;
+    for (;;) {
+      long long vmin = LLONG_MAX, vmax = LLONG_MIN;
+      for (int a = 0; a < cnt; ++a) {
+        const AngleFx& A = af[k0 + a];
+        for (int j : {jf, jl}) {
+          const long long base = A.C0 + (long long)j * A.A + (long long)L0 * A.B;
+          for (int l = 0; l < bl; ++l) {
+            const long long v = ((base + (long long)l * A.B) >> 32) - (((long long)l * Bm) >> 32);
+            vmin = std::min(vmin, v);
+            vmax = std::max(vmax, v);
+          }
+        }
+      }
+      S0 = (int)vmin - 1;
+      const long long W = vmax - vmin + 3;
+      lp = 6;
+      while ((1LL << lp) < W) ++lp;
+      if ((long long)bl << lp <= kShCap) break;
+      if (bl == 1) return false;
+      bl = std::max(1, (int)(kShCap >> lp));
+    }
+    bands.push_back(make_int4(L0, bl, S0, lp));
+    L0 += bl;
+  }
+  return true;
+}
+
+// Chunks of up to kShKA angles of one stepping type, halved where a line of
+// some detector tile does not fit the window.
+Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af) {
+  Schedule S;
+  const int ntiles = (nd + kShJD - 1) / kShJD;
+  for (const int2& run : angle_chunks(af, INT_MAX)) {
+    for (int k0 = run.x; k0 < run.x + run.y;) {
+      int cnt = std::min(kShKA, run.x + run.y - k0);
+      std::vector<int2> blocks;
+      std::vector<int4> bands;
+      for (;;) {
+        const long long Bm = af[k0 + cnt / 2].B;
+        blocks.clear();
+        bands.clear();
+        bool fit = true;
+        for (int t = 0; t < ntiles && fit; ++t) {
+          const int jf = t * kShJD, jl = std::min(jf + kShJD - 1, nd - 1);
+          const int first = (int)(S.bands.size() + bands.size());
+          fit = shear_tile_bands(n, nd, af, k0, cnt, Bm, jf, jl, bands);
+          blocks.push_back(make_int2(first, (int)(S.bands.size() + bands.size()) - first));
+        }
+        if (fit) {
+          S.chunks.push_back(make_int4(k0, cnt, (int)(unsigned)(Bm & 0xffffffffLL), (int)(Bm >> 32)));
+          break;
+        }
+        if (cnt == 1) {
+          S.ok = false;
+          return S;
+        }
+        cnt = (cnt + 1) / 2;
+      }
+      S.blocks.insert(S.blocks.end(), blocks.begin(), blocks.end());
+      S.bands.insert(S.bands.end(), bands.begin(), bands.end());
+      k0 += cnt;
+    }
+  }
+  return S;
+}
+
 Schedule build_schedule(int n, int nd, const std::vector<AngleFx>& af, int ka, int jd, int wl) {
   Schedule S;
   const std::vector<int2> ch = angle_chunks(af, ka);
   const int ntiles = (nd + jd - 1) / jd;
-  const double hc = (n - 1) / 2.0, jc = (nd - 1) / 2.0;
   for (const int2& c : ch) {
     // the same shear the kernel applies: rint of the float slope of the middle angle
     const int m = (int)std::nearbyint(af[c.x + (c.y >> 1)].beta);
@@ -380,27 +490,8 @@ Schedule build_schedule(int n, int nd, const std::vector<AngleFx>& af, int ka, i
     const int m = S.chunks[ci].z;
     for (int t = 0; t < ntiles; ++t) {
       const int jf = t * jd, jl = std::min(jf + jd - 1, nd - 1);
-      // lines where some ray of the block crosses inside (-1, n) (margin 2)
-      double lo = n, hi = -1;
-      for (int a = 0; a < c.y; ++a) {
-        const AngleFx& A = af[c.x + a];
-        const double a_ = double(A.A) / 4294967296.0, b_ = double(A.B) / 4294967296.0;
-        const double ta_f = (jf - jc) * a_ + hc, ta_l = (jl - jc) * a_ + hc;  // crossings on the centre line
-        if (std::fabs(b_) < 1e-12) {  // crossings do not move with the line
-          if (std::max(ta_f, ta_l) > -1.0 && std::min(ta_f, ta_l) < n) {
-            lo = 0;
-            hi = n - 1;
-          }
-          continue;
-        }
-        for (double ta : {ta_f, ta_l}) {
-          const double u1 = (-1.0 - ta) / b_ + hc, u2 = (n - ta) / b_ + hc;
-          lo = std::min(lo, std::min(u1, u2));
-          hi = std::max(hi, std::max(u1, u2));
-        }
-      }
-      const int L_lo = std::max(0, (int)std::floor(std::max(lo, -4.0)) - 2);
-      const int L_hi = std::min(n - 1, (int)std::ceil(std::min(hi, n + 4.0)) + 2);
+      int L_lo, L_hi;
+      block_lines(n, nd, af, c.x, c.y, jf, jl, L_lo, L_hi);
       const int first = (int)S.bands.size();
       for (int L0 = L_lo; L0 <= L_hi;) {
         int bl = std::min(kFwdMaxBand, L_hi - L0 + 1);
@@ -478,6 +569,21 @@ mcr_status init_work(mcr_handle* h) {
       HIP_OK(hipMemcpyAsync(h->sched_bands, sc.bands.data(), sizeof(int4) * sc.bands.size(), hipMemcpyHostToDevice,
                             h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
+    const Schedule ss = build_shear_schedule(h->geo.n, h->geo.n_det, af);
+    if (ss.ok) {
+      h->shear_nchunks = (int)ss.chunks.size();
+      STATUS_OK(dmalloc(h, (void**)&h->shear_chunks, sizeof(int4) * ss.chunks.size()));
+      STATUS_OK(dmalloc(h, (void**)&h->shear_blocks, sizeof(int2) * ss.blocks.size()));
+      STATUS_OK(dmalloc(h, (void**)&h->shear_bands, sizeof(int4) * std::max<size_t>(1, ss.bands.size())));
+      HIP_OK(hipMemcpyAsync(h->shear_chunks, ss.chunks.data(), sizeof(int4) * ss.chunks.size(),
+                            hipMemcpyHostToDevice, h->stream));
+      HIP_OK(hipMemcpyAsync(h->shear_blocks, ss.blocks.data(), sizeof(int2) * ss.blocks.size(),
+                            hipMemcpyHostToDevice, h->stream));
+      if (!ss.bands.empty())
+        HIP_OK(hipMemcpyAsync(h->shear_bands, ss.bands.data(), sizeof(int4) * ss.bands.size(), hipMemcpyHostToDevice,
+                              h->stream));
+      HIP_OK(hipStreamSynchronize(h->stream));
+    }
   }
   HIP_OK(hipStreamSynchronize(h->stream));
   STATUS_OK(upload_motion<T>(h));
@@ -535,7 +641,12 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   Timed tm(h, MCR_KERNEL_PROJECT);
   dim3 grid(cdiv(h->geo.n_det, 256), h->geo.n_angles, G), block(256);
   if constexpr (std::is_same<T, float>::value) {
-    if (h->tune.fwd == 2 && h->sched_ok) {
+    if (h->tune.fwd == 3 && h->shear_nchunks > 0) {
+      dim3 gt(cdiv(h->geo.n_det, kShJD), h->shear_nchunks, G);
+      hipLaunchKernelGGL((k_joseph_fwd_shear<MODE>), gt, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx,
+                         h->shear_chunks, h->shear_blocks, h->shear_bands, w.wP, w.wTP, h->padded, out, out_stride,
+                         gate0, w.scalars, w.ptrs, slots);
+    } else if (h->tune.fwd == 2 && h->sched_ok) {
       dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->sched_nchunks, G);
       hipLaunchKernelGGL((k_joseph_fwd_sched<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
                          geo_of<T>(h), w.angfx, h->sched_chunks, h->sched_blocks, h->sched_bands, w.wP, w.wTP,
@@ -1212,7 +1323,7 @@ mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_moti
   if ((s = init_work<double>(h)) != MCR_OK) return cleanup(s);
   if (dtype == MCR_F32 && (s = init_work<float>(h)) != MCR_OK) return cleanup(s);
   if ((s = mcr_set_motion(h, -1, nullptr)) != MCR_OK) return cleanup(s);
-  h->tune.fwd = h->sched_ok ? 2 : 0;
+  h->tune.fwd = h->shear_nchunks > 0 ? 3 : (h->sched_ok ? 2 : 0);
   *out = h;
   return MCR_OK;
 }
@@ -1569,6 +1680,12 @@ mcr_status mcr_duality_gap(mcr_handle* h, const mcr_state* st, const void* const
 }
 
 
+namespace {
+bool fwd_variant_ok(const mcr_handle* h, int f) {
+  return f == 0 || (f == 1 && h->fwd_lds_ok) || (f == 2 && h->sched_ok) || (f == 3 && h->shear_nchunks > 0);
+}
+}  // namespace
+
 mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, int32_t* adj_px, int32_t* adj_s) {
   STATUS_OK(check_handle(h));
   if (gates_per_launch < 1 || gates_per_launch > h->N)
@@ -1593,8 +1710,8 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       mcr_handle::Tune best = h->tune;
       float best_ms = 1e30f, ms = 0.0f;
       mcr_status st = MCR_OK;
-      for (int f = 0; f <= 2 && st == MCR_OK; ++f) {
-        if ((f == 1 && !h->fwd_lds_ok) || (f == 2 && !h->sched_ok)) continue;
+      for (int f = 0; f <= 3 && st == MCR_OK; ++f) {
+        if (!fwd_variant_ok(h, f)) continue;
         h->tune.fwd = f;
         st = time_launches(h, [&] { return launch_project<float, 0>(h, 0, G, w.dy, h->sino); }, 5, &ms);
         if (st == MCR_OK && ms < best_ms) {
@@ -1632,8 +1749,8 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
 
 mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t adj_s) {
   STATUS_OK(check_handle(h));
-  if (fwd < 0 || fwd > 2) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1 or 2", fwd);
-  if (h->dtype == MCR_F32 && ((fwd == 1 && !h->fwd_lds_ok) || (fwd == 2 && !h->sched_ok)))
+  if (fwd < 0 || fwd > 3) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1, 2 or 3", fwd);
+  if (h->dtype == MCR_F32 && !fwd_variant_ok(h, fwd))
     return fail(MCR_ERR_STATE, "the tiled forward's band windows do not fit this geometry");
   if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4)
     return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2 or 4", adj_px);

@@ -225,6 +225,153 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_sched(Geo<float> g, const An
   project_epilogue<float, MODE>(s, idx, out + blockIdx.z * out_stride, slot_gate(slots, gate0), gs, gp);
 }
 
+// Line-sheared scheduled forward. A block owns up to 16 consecutive angles of
+// one stepping type times 32 detector bins; thread (kk, jj) computes the rays
+// of angles kk and kk + 8 at bin jj, so every staged value serves two rays
+// per thread. Band lines are staged one per wave (64 columns each) with a
+// per-line shift o_l = floor(l Bm / 2^32), Bm the fixed-point slope of the
+// chunk's middle angle: the window follows the mean ray direction, so its
+// width is set by the spread of the block's rays on one line (about 50
+// columns at 720 angles). The LDS line pitch is a power of two >= 64 chosen
+// per band (wide windows get fewer lines), at most kShCap entries. Each staged entry holds
+// the pixel and its difference to the next column, (x[c], x[c+1] - x[c]), so
+// a tap is one 8-byte LDS read and two FMAs. The ray position is carried as
+// two 32-bit words (window column, fraction) of the 32.32 crossing; the LDS
+// address is the column word shifted plus a block-uniform line offset.
+// Staged columns are clamped into the zero halo of the padded image, so no
+// per-lane bounds test is needed.
+//   chunks : (first angle, angle count, low and high words of Bm)
+//   blocks : per (chunk, detector tile): (first band, band count)
+//   bands  : (first line L0, lines BL, window start S0, log2 pitch lp); the
+//            taps of every ray of the block on band line l lie in window
+//            columns [1, 2^lp - 2] after the shift o_l, BL 2^lp <= kShCap
+// grid (ceil(n_det/32), n_chunks, G), block 256
+constexpr int kShCap = 4096;  // staged entries per band
+constexpr int kShBL = 64;     // lines per band at most
+constexpr int kShKA = 16;  // angles per chunk at most
+constexpr int kShJD = 32;  // detector bins per block
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                          const int4* __restrict__ chunks,
+                                                          const int2* __restrict__ blocks,
+                                                          const int4* __restrict__ bands,
+                                                          const float* __restrict__ wP,
+                                                          const float* __restrict__ wTP, long w_stride,
+                                                          float* __restrict__ out, long out_stride, int gate0,
+                                                          const GateScalars<float>* __restrict__ gs,
+                                                          const GatePtrs<float>* __restrict__ gp,
+                                                          const SlotInfo* __restrict__ slots) {
+  constexpr int kPer = kShCap / 256;  // staged entries per thread
+  __shared__ float2 st[kShCap];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int4 ch = chunks[blockIdx.y];
+  const long long Bm = (long long)(((unsigned long long)(unsigned)ch.w << 32) | (unsigned)ch.z);
+  const int2 bb = blocks[blockIdx.y * gridDim.x + blockIdx.x];
+  const int kk = tid >> 5;
+  const int j = blockIdx.x * kShJD + (tid & 31);
+  const int jc = min(j, g.nd - 1);
+  const AngleFx& A0 = ang[ch.x + min(kk, ch.y - 1)];
+  const AngleFx& A1 = ang[ch.x + min(kk + 8, ch.y - 1)];
+  // per-line steps of the crossings
+  const unsigned long long S0 = (unsigned long long)A0.B;
+  const unsigned long long S1 = (unsigned long long)A1.B;
+  const unsigned s0lo = (unsigned)S0, s0hi = (unsigned)(S0 >> 32);
+  const unsigned s1lo = (unsigned)S1, s1hi = (unsigned)(S1 >> 32);
+  const long long c0j = A0.C0 + (long long)jc * A0.A;
+  const long long c1j = A1.C0 + (long long)jc * A1.A;
+  const int n = g.n, pitch = g.pitch;
+  const float* img = (ang[ch.x].rows ? wP : wTP) + blockIdx.z * w_stride + (long)kPad * pitch + kPad;
+  float pre[kPer], prd[kPer];
+  // entry i = l * pitch + q of a band; a wave's 64 entries share one line
+  auto fetch = [&](const int4 bd) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int ib = 256 * e + 64 * wv;
+      const int l = ib >> bd.w;
+      float v = 0.0f, v1 = 0.0f;
+      if (l < bd.y) {
+        const int o = (int)(((long long)l * Bm) >> 32);
+        const int c = bd.z + o + (ib & ((1 << bd.w) - 1)) + lane;
+        const float* row = img + (long)(bd.x + l) * pitch;
+        v = row[min(max(c, -kPad), n + kPad - 1)];
+        v1 = row[min(max(c + 1, -kPad), n + kPad - 1)];
+      }
+      pre[e] = v;
+      prd[e] = v1 - v;
+    }
+  };
+  if (bb.y > 0) fetch(bands[bb.x]);
+  float acc0 = 0.0f, acc1 = 0.0f;
+  for (int b = 0; b < bb.y; ++b) {
+    const int4 bd = bands[bb.x + b];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) st[256 * e + tid] = make_float2(pre[e], prd[e]);
+    __syncthreads();
+    if (b + 1 < bb.y) fetch(bands[bb.x + b + 1]);
+    const unsigned long long p0 = (unsigned long long)(c0j + (long long)bd.x * A0.B - ((long long)bd.z << 32));
+    const unsigned long long p1 = (unsigned long long)(c1j + (long long)bd.x * A1.B - ((long long)bd.z << 32));
+    unsigned lo0 = (unsigned)p0, hi0 = (unsigned)(p0 >> 32);
+    unsigned lo1 = (unsigned)p1, hi1 = (unsigned)(p1 >> 32);
+    long long om = 0;
+    float a0 = 0.0f, f0 = 0.0f, a1 = 0.0f, f1 = 0.0f;
+    const char* base = (const char*)st;
+    // the tap pair of both rays on the current line; so = 8 (l pitch - o_l)
+    // >= 0 is the byte offset of line l's window (uniform)
+    auto tap = [&](int so, float2& x0, float& w0, float2& x1, float& w1) {
+      x0 = *(const float2*)(base + ((hi0 << 3) + (unsigned)so));
+      x1 = *(const float2*)(base + ((hi1 << 3) + (unsigned)so));
+      w0 = float(lo0);
+      w1 = float(lo1);
+      unsigned c0, c1;
+      lo0 = __builtin_addc(lo0, s0lo, 0u, &c0);
+      hi0 = __builtin_addc(hi0, s0hi, c0, &c0);
+      lo1 = __builtin_addc(lo1, s1lo, 0u, &c1);
+      hi1 = __builtin_addc(hi1, s1hi, c1, &c1);
+    };
+    int l = 0;
+    for (; l + 4 <= bd.y; l += 4) {
+      float2 x0[4], x1[4];
+      float w0[4], w1[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int so = 8 * (((l + t) << bd.w) - (int)(om >> 32));
+        om += Bm;
+        tap(so, x0[t], w0[t], x1[t], w1[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a0 += x0[t].x;
+        f0 = fmaf(w0[t], x0[t].y, f0);
+        a1 += x1[t].x;
+        f1 = fmaf(w1[t], x1[t].y, f1);
+      }
+    }
+    for (; l < bd.y; ++l) {
+      float2 x0, x1;
+      float w0, w1;
+      const int so = 8 * ((l << bd.w) - (int)(om >> 32));
+      om += Bm;
+      tap(so, x0, w0, x1, w1);
+      a0 += x0.x;
+      f0 = fmaf(w0, x0.y, f0);
+      a1 += x1.x;
+      f1 = fmaf(w1, x1.y, f1);
+    }
+    acc0 += fmaf(f0, kFix, a0);
+    acc1 += fmaf(f1, kFix, a1);
+    __syncthreads();
+  }
+  if (j >= g.nd) return;
+  const int gate = slot_gate(slots, gate0);
+  float* o = out + blockIdx.z * out_stride;
+  if (kk < ch.y) project_epilogue<float, MODE>(A0.ds * acc0, (long)(ch.x + kk) * g.nd + j, o, gate, gs, gp);
+  if (kk + 8 < ch.y)
+    project_epilogue<float, MODE>(A1.ds * acc1, (long)(ch.x + kk + 8) * g.nd + j, o, gate, gs, gp);
+}
+
 constexpr int kAdjKC = 32;  // angles per staged chunk
 constexpr int kAdjW = 64;   // bins staged per angle
 
