@@ -127,9 +127,13 @@ struct mcr_handle {
   int sched_nchunks = 0;
   bool sched_ok = false;
   int4* shear_chunks = nullptr;    // line-sheared forward: (k0, count, Bm low, Bm high) per chunk
-  int2* shear_blocks = nullptr;    // (first band, bands) per (chunk, detector tile)
+  int4* shear_pieces = nullptr;    // (first band, bands, unit, piece) per block
+  int4* shear_units = nullptr;     // (chunk, detector tile, pieces, partial-sum offset) per unit
   int4* shear_bands = nullptr;     // (L0, lines, window start, log2 of the LDS line pitch)
-  int shear_nchunks = 0;
+  float* shear_part = nullptr;     // [slots][part_floats] partial ray sums of multi-piece units
+  int* shear_multi = nullptr;      // units cut into several pieces
+  int shear_npieces = 0, shear_nmulti = 0;
+  long shear_part_floats = 0;
   float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
   // batched SPDHG (mcr_batch_create): S independent slices sharing the geometry
   struct Batch {
@@ -368,6 +372,11 @@ struct Schedule {
   std::vector<int2> blocks;
   std::vector<int4> bands;
   bool ok = true;
+  // line-sheared forward only: work pieces and units (see k_joseph_fwd_shear)
+  std::vector<int4> pieces;  // (first band, bands, unit, piece index)
+  std::vector<int4> units;   // (chunk, detector tile, pieces P, offset of the unit's partial sums)
+  std::vector<int> multi;    // units with P > 1
+  long part_floats = 0;      // partial sums per gate slot
 };
 
 // Lines [L_lo, L_hi] on which some ray of angles [k0, k0 + cnt) and bins
@@ -473,6 +482,30 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af) {
       k0 += cnt;
     }
   }
+  // cut every (chunk, tile) unit into pieces of about kShPieceLines lines so
+  // that the blocks carry similar work; pieces of one unit are numbered in
+  // line order and their partial sums are added in that order
+  for (int c = 0; c < (int)S.chunks.size(); ++c) {
+    for (int t = 0; t < ntiles; ++t) {
+      const int u = c * ntiles + t;
+      const int2 bl = S.blocks[u];
+      const int first_piece = (int)S.pieces.size();
+      int b0 = bl.x, lines = 0, pc = 0;
+      for (int b = bl.x; b < bl.x + bl.y; ++b) {
+        if (b > b0 && lines + S.bands[b].y > kShPieceLines) {
+          S.pieces.push_back(make_int4(b0, b - b0, u, pc++));
+          b0 = b;
+          lines = 0;
+        }
+        lines += S.bands[b].y;
+      }
+      S.pieces.push_back(make_int4(b0, bl.x + bl.y - b0, u, pc++));
+      if (pc > 1) S.multi.push_back((int)S.units.size());
+      S.units.push_back(make_int4(c, t, pc, (int)S.part_floats));
+      if (pc > 1) S.part_floats += (long)pc * 512;
+      (void)first_piece;
+    }
+  }
   return S;
 }
 
@@ -571,13 +604,23 @@ mcr_status init_work(mcr_handle* h) {
     HIP_OK(hipStreamSynchronize(h->stream));
     const Schedule ss = build_shear_schedule(h->geo.n, h->geo.n_det, af);
     if (ss.ok) {
-      h->shear_nchunks = (int)ss.chunks.size();
+      h->shear_npieces = (int)ss.pieces.size();
+      h->shear_nmulti = (int)ss.multi.size();
+      h->shear_part_floats = ss.part_floats;
       STATUS_OK(dmalloc(h, (void**)&h->shear_chunks, sizeof(int4) * ss.chunks.size()));
-      STATUS_OK(dmalloc(h, (void**)&h->shear_blocks, sizeof(int2) * ss.blocks.size()));
+      STATUS_OK(dmalloc(h, (void**)&h->shear_pieces, sizeof(int4) * ss.pieces.size()));
+      STATUS_OK(dmalloc(h, (void**)&h->shear_units, sizeof(int4) * ss.units.size()));
       STATUS_OK(dmalloc(h, (void**)&h->shear_bands, sizeof(int4) * std::max<size_t>(1, ss.bands.size())));
+      STATUS_OK(dmalloc(h, (void**)&h->shear_part, sizeof(float) * std::max<long>(1, ss.part_floats) * ns));
+      STATUS_OK(dmalloc(h, (void**)&h->shear_multi, sizeof(int) * std::max<size_t>(1, ss.multi.size())));
+      if (!ss.multi.empty())
+        HIP_OK(hipMemcpyAsync(h->shear_multi, ss.multi.data(), sizeof(int) * ss.multi.size(), hipMemcpyHostToDevice,
+                              h->stream));
       HIP_OK(hipMemcpyAsync(h->shear_chunks, ss.chunks.data(), sizeof(int4) * ss.chunks.size(),
                             hipMemcpyHostToDevice, h->stream));
-      HIP_OK(hipMemcpyAsync(h->shear_blocks, ss.blocks.data(), sizeof(int2) * ss.blocks.size(),
+      HIP_OK(hipMemcpyAsync(h->shear_pieces, ss.pieces.data(), sizeof(int4) * ss.pieces.size(),
+                            hipMemcpyHostToDevice, h->stream));
+      HIP_OK(hipMemcpyAsync(h->shear_units, ss.units.data(), sizeof(int4) * ss.units.size(),
                             hipMemcpyHostToDevice, h->stream));
       if (!ss.bands.empty())
         HIP_OK(hipMemcpyAsync(h->shear_bands, ss.bands.data(), sizeof(int4) * ss.bands.size(), hipMemcpyHostToDevice,
@@ -641,11 +684,17 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   Timed tm(h, MCR_KERNEL_PROJECT);
   dim3 grid(cdiv(h->geo.n_det, 256), h->geo.n_angles, G), block(256);
   if constexpr (std::is_same<T, float>::value) {
-    if (h->tune.fwd == 3 && h->shear_nchunks > 0) {
-      dim3 gt(cdiv(h->geo.n_det, kShJD), h->shear_nchunks, G);
+    if (h->tune.fwd == 3 && h->shear_npieces > 0) {
+      dim3 gt(h->shear_npieces, 1, G);
       hipLaunchKernelGGL((k_joseph_fwd_shear<MODE>), gt, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx,
-                         h->shear_chunks, h->shear_blocks, h->shear_bands, w.wP, w.wTP, h->padded, out, out_stride,
-                         gate0, w.scalars, w.ptrs, slots);
+                         h->shear_chunks, h->shear_pieces, h->shear_units, h->shear_bands, w.wP, w.wTP, h->padded,
+                         out, out_stride, gate0, w.scalars, w.ptrs, slots, h->shear_part, h->shear_part_floats);
+      if (h->shear_nmulti > 0) {
+        LAUNCH_OK();
+        hipLaunchKernelGGL((k_joseph_fwd_shear_finish<MODE>), dim3(h->shear_nmulti, 1, G), dim3(256), 0, h->stream,
+                           geo_of<T>(h), w.angfx, h->shear_chunks, h->shear_units, h->shear_multi, h->shear_part,
+                           h->shear_part_floats, out, out_stride, gate0, w.scalars, w.ptrs, slots);
+      }
     } else if (h->tune.fwd == 2 && h->sched_ok) {
       dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->sched_nchunks, G);
       hipLaunchKernelGGL((k_joseph_fwd_sched<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
@@ -1323,7 +1372,7 @@ mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_moti
   if ((s = init_work<double>(h)) != MCR_OK) return cleanup(s);
   if (dtype == MCR_F32 && (s = init_work<float>(h)) != MCR_OK) return cleanup(s);
   if ((s = mcr_set_motion(h, -1, nullptr)) != MCR_OK) return cleanup(s);
-  h->tune.fwd = h->shear_nchunks > 0 ? 3 : (h->sched_ok ? 2 : 0);
+  h->tune.fwd = h->shear_npieces > 0 ? 3 : (h->sched_ok ? 2 : 0);
   *out = h;
   return MCR_OK;
 }
@@ -1682,7 +1731,7 @@ mcr_status mcr_duality_gap(mcr_handle* h, const mcr_state* st, const void* const
 
 namespace {
 bool fwd_variant_ok(const mcr_handle* h, int f) {
-  return f == 0 || (f == 1 && h->fwd_lds_ok) || (f == 2 && h->sched_ok) || (f == 3 && h->shear_nchunks > 0);
+  return f == 0 || (f == 1 && h->fwd_lds_ok) || (f == 2 && h->sched_ok) || (f == 3 && h->shear_npieces > 0);
 }
 }  // namespace
 

@@ -240,13 +240,20 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_sched(Geo<float> g, const An
 // address is the column word shifted plus a block-uniform line offset.
 // Staged columns are clamped into the zero halo of the padded image, so no
 // per-lane bounds test is needed.
+// The bands of a (chunk, detector tile) unit are split into pieces of about
+// kShPieceLines lines, one block each, so that blocks carry similar work. A
+// unit of P > 1 pieces writes P partial sums per ray, which
+// k_joseph_fwd_shear_finish adds in piece order before the epilogue.
 //   chunks : (first angle, angle count, low and high words of Bm)
-//   blocks : per (chunk, detector tile): (first band, band count)
+//   pieces : per block: (first band, band count, unit, piece index)
+//   units  : (chunk, detector tile, pieces P, offset of the unit's P x 512
+//            partial sums in part)
 //   bands  : (first line L0, lines BL, window start S0, log2 pitch lp); the
 //            taps of every ray of the block on band line l lie in window
 //            columns [1, 2^lp - 2] after the shift o_l, BL 2^lp <= kShCap
-// grid (ceil(n_det/32), n_chunks, G), block 256
+// grid (n_pieces, 1, G), block 256
 constexpr int kShCap = 4096;  // staged entries per band
+constexpr int kShPieceLines = 128;  // target lines per block
 constexpr int kShBL = 64;     // lines per band at most
 constexpr int kShKA = 16;  // angles per chunk at most
 constexpr int kShJD = 32;  // detector bins per block
@@ -254,24 +261,28 @@ constexpr int kShJD = 32;  // detector bins per block
 template <int MODE>
 __global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const AngleFx* __restrict__ ang,
                                                           const int4* __restrict__ chunks,
-                                                          const int2* __restrict__ blocks,
+                                                          const int4* __restrict__ pieces,
+                                                          const int4* __restrict__ units,
                                                           const int4* __restrict__ bands,
                                                           const float* __restrict__ wP,
                                                           const float* __restrict__ wTP, long w_stride,
                                                           float* __restrict__ out, long out_stride, int gate0,
                                                           const GateScalars<float>* __restrict__ gs,
                                                           const GatePtrs<float>* __restrict__ gp,
-                                                          const SlotInfo* __restrict__ slots) {
+                                                          const SlotInfo* __restrict__ slots,
+                                                          float* __restrict__ part, long part_stride) {
   constexpr int kPer = kShCap / 256;  // staged entries per thread
   __shared__ float2 st[kShCap];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int4 ch = chunks[blockIdx.y];
+  const int4 pc = pieces[blockIdx.x];
+  const int4 un = units[pc.z];
+  const int4 ch = chunks[un.x];
   const long long Bm = (long long)(((unsigned long long)(unsigned)ch.w << 32) | (unsigned)ch.z);
-  const int2 bb = blocks[blockIdx.y * gridDim.x + blockIdx.x];
+  const int2 bb = make_int2(pc.x, pc.y);
   const int kk = tid >> 5;
-  const int j = blockIdx.x * kShJD + (tid & 31);
+  const int j = un.y * kShJD + (tid & 31);
   const int jc = min(j, g.nd - 1);
   const AngleFx& A0 = ang[ch.x + min(kk, ch.y - 1)];
   const AngleFx& A1 = ang[ch.x + min(kk + 8, ch.y - 1)];
@@ -364,12 +375,51 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const An
     acc1 += fmaf(f1, kFix, a1);
     __syncthreads();
   }
+  if (un.z > 1) {  // partial sums; k_joseph_fwd_shear_finish adds them
+    float* pu = part + blockIdx.z * part_stride + un.w + pc.w * 512;
+    pu[tid] = acc0;
+    pu[256 + tid] = acc1;
+    return;
+  }
   if (j >= g.nd) return;
   const int gate = slot_gate(slots, gate0);
   float* o = out + blockIdx.z * out_stride;
   if (kk < ch.y) project_epilogue<float, MODE>(A0.ds * acc0, (long)(ch.x + kk) * g.nd + j, o, gate, gs, gp);
   if (kk + 8 < ch.y)
     project_epilogue<float, MODE>(A1.ds * acc1, (long)(ch.x + kk + 8) * g.nd + j, o, gate, gs, gp);
+}
+
+// Sum of the partial sums of the multi-piece units in piece order, then the
+// projection epilogue. grid (n_multi, 1, G), block 256; multi lists the units
+// with P > 1.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                                 const int4* __restrict__ chunks,
+                                                                 const int4* __restrict__ units,
+                                                                 const int* __restrict__ multi,
+                                                                 const float* __restrict__ part, long part_stride,
+                                                                 float* __restrict__ out, long out_stride, int gate0,
+                                                                 const GateScalars<float>* __restrict__ gs,
+                                                                 const GatePtrs<float>* __restrict__ gp,
+                                                                 const SlotInfo* __restrict__ slots) {
+  const int tid = threadIdx.x;
+  const int4 un = units[multi[blockIdx.x]];
+  const int4 ch = chunks[un.x];
+  const int kk = tid >> 5;
+  const int j = un.y * kShJD + (tid & 31);
+  if (j >= g.nd) return;
+  const float* pu = part + blockIdx.z * part_stride + un.w;
+  float acc0 = 0.0f, acc1 = 0.0f;
+  for (int q = 0; q < un.z; ++q) {
+    acc0 += pu[q * 512 + tid];
+    acc1 += pu[q * 512 + 256 + tid];
+  }
+  const int gate = slot_gate(slots, gate0);
+  float* o = out + blockIdx.z * out_stride;
+  if (kk < ch.y)
+    project_epilogue<float, MODE>(ang[ch.x + kk].ds * acc0, (long)(ch.x + kk) * g.nd + j, o, gate, gs, gp);
+  if (kk + 8 < ch.y)
+    project_epilogue<float, MODE>(ang[ch.x + kk + 8].ds * acc1, (long)(ch.x + kk + 8) * g.nd + j, o, gate, gs, gp);
 }
 
 constexpr int kAdjKC = 32;  // angles per staged chunk
