@@ -410,9 +410,20 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
   if (j >= g.nd) return;
   const float* pu = part + blockIdx.z * part_stride + un.w;
   float acc0 = 0.0f, acc1 = 0.0f;
-  for (int q = 0; q < un.z; ++q) {
-    acc0 += pu[q * 512 + tid];
-    acc1 += pu[q * 512 + 256 + tid];
+  // loads of up to 8 pieces in flight, then their sum in piece order
+  for (int q0 = 0; q0 < un.z; q0 += 8) {
+    float a[8], b[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const bool in = q0 + q < un.z;
+      a[q] = in ? pu[(q0 + q) * 512 + tid] : 0.0f;
+      b[q] = in ? pu[(q0 + q) * 512 + 256 + tid] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      acc0 += a[q];
+      acc1 += b[q];
+    }
   }
   const int gate = slot_gate(slots, gate0);
   float* o = out + blockIdx.z * out_stride;
