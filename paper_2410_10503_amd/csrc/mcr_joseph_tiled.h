@@ -252,9 +252,9 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_sched(Geo<float> g, const An
 //            taps of every ray of the block on band line l lie in window
 //            columns [1, 2^lp - 2] after the shift o_l, BL 2^lp <= kShCap
 // grid (n_pieces, 1, G), block 256
-constexpr int kShCap = 4096;  // staged entries per band
+constexpr int kShCap = 2048;  // staged entries per band
 constexpr int kShPieceLines = 128;  // target lines per block
-constexpr int kShBL = 64;     // lines per band at most
+constexpr int kShBL = 32;     // lines per band at most
 constexpr int kShKA = 16;  // angles per chunk at most
 constexpr int kShJD = 32;  // detector bins per block
 
