@@ -547,15 +547,23 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
       const float na32 = wc.x, pa32 = wc.y, oma = wc.z;
       const long long st = s_step[kc];
       long long u = s_row[kc][ty] + s_col[kc][tx];
+      // the bin pairs of all PX pixels are read before any is used
+      float y0[PX], y1[PX], fl[PX];
 #pragma unroll
       for (int p = 0; p < PX; ++p) {
         const float* q = sy + (int)(u >> 32);
-        const float fl = float((unsigned)u);
-        // hat weights 1 - |a| d and 1 - |a| (1 - d), clamped at 0
-        const float w0 = fmaxf(0.0f, fmaf(na32, fl, 1.0f));
-        const float w1 = fmaxf(0.0f, fmaf(pa32, fl, oma));
-        blk[p] = fmaf(w1, q[1], fmaf(w0, q[0], blk[p]));
+        fl[p] = float((unsigned)u);
+        y0[p] = q[0];
+        y1[p] = q[1];
         u += st;
+      }
+#pragma unroll
+      for (int p = 0; p < PX; ++p) {
+        // hat weights 1 - |a| d and 1 - |a| (1 - d), clamped at 0 (neither
+        // exceeds 1, so a clamp to [0, 1] is the same)
+        const float w0 = __builtin_amdgcn_fmed3f(fmaf(na32, fl[p], 1.0f), 0.0f, 1.0f);
+        const float w1 = __builtin_amdgcn_fmed3f(fmaf(pa32, fl[p], oma), 0.0f, 1.0f);
+        blk[p] = fmaf(w1, y1[p], fmaf(w0, y0[p], blk[p]));
       }
     }
 #pragma unroll
