@@ -56,7 +56,7 @@ mcr_status fail(mcr_status s, const char* fmt, ...) {
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 constexpr int kFwdKA = 8, kFwdJD = 32, kFwdWL = 128;  // tiled forward: angles, bins, LDS row
-constexpr int kMaxShares = 4;                          // tiled adjoint: angle shares
+constexpr int kMaxShares = 8;                          // tiled adjoint: angle shares
 
 
 // Per-precision workspace and tables.
