@@ -52,26 +52,29 @@ def joseph_nnz(n: int, na: int, nd: int) -> int:
 
 
 def measured_traffic(dominant: str, variant: dict):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (profiles/), or None when that summary is for another kernel or
-    the kernel sources have changed since the counters were taken."""
+    """HBM bytes per launch of the dominant kernel class from the committed
+    counter summary (profiles/), or None when that summary holds no line for
+    this class and variant, or the kernel sources have changed since the
+    counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_joseph_fwd_chest512_field16.md")
-    if dominant != "project" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", "traffic_joseph_pair_chest512_field16.md")
+    if not os.path.exists(path):
         return None
-    line = next((ln for ln in open(path) if ln.startswith("traffic: ")), None)
-    if line is None:
-        return None
-    fields = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
-    if fields.get("fwd") != str(variant.get("fwd")):
-        return None
+    want = {"class": dominant, "fwd": str(variant.get("fwd")),
+            "adj": f"{variant.get('adj_px')},{variant.get('adj_shares')}"}
     h = hashlib.sha256()
     for src in ("mcr_joseph_tiled.h", "mcr_kernels.h"):
         with open(os.path.join(ROOT, "paper_2410_10503_amd", "csrc", src), "rb") as f:
             h.update(f.read())
-    if h.hexdigest()[:16] != fields.get("sources_sha256_16"):
-        return None
-    return float(fields["fetch_bytes"]) + float(fields["write_bytes"])
+    for line in open(path):
+        if not line.startswith("traffic: "):
+            continue
+        fields = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
+        if all(fields.get(k) == v for k, v in want.items()):
+            if fields.get("sources_sha256_16") != h.hexdigest()[:16]:
+                return None
+            return float(fields["fetch_bytes"]) + float(fields["write_bytes"])
+    return None
 
 
 def cpu_baseline(wl, x_true, fields_or_params):
@@ -236,6 +239,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64 x 256^2 measurement")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation measurement")
+    ap.add_argument("--variant", default=None,
+                    help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
+                         "(counter runs serialise dispatches, which would change the autotuner's choice)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -281,8 +287,14 @@ def main():
     p = [1.0 / N] * N
     log(f"|A_i|^2 in [{min(norms):.4g}, {max(norms):.4g}], per-epoch rate {rate:.6f}")
 
-    variant = h.autotune(1)
-    log(f"autotuned projector variants: {variant}")
+    if args.variant:
+        f, px, sh = (int(v) for v in args.variant.split(","))
+        h.set_variant(f, px, sh)
+        variant = {"fwd": f, "adj_px": px, "adj_shares": sh}
+        log(f"projector variants (fixed): {variant}")
+    else:
+        variant = h.autotune(1)
+        log(f"autotuned projector variants: {variant}")
     st = h.zero_state()
 
     def epoch(e):

@@ -1769,7 +1769,7 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
         }
       }
       h->tune.fwd = best.fwd;
-      const int cand[][2] = {{0, 1}, {1, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {4, 4}};
+      const int cand[][2] = {{0, 1}, {1, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {4, 4}, {4, 6}, {4, 8}};
       best_ms = 1e30f;
       for (const auto& c : cand) {
         if (st != MCR_OK) break;
