@@ -250,7 +250,7 @@ mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq,
  *           3 = host-scheduled bands whose window shifts line by line with
  *           the chunk's mean ray slope (up to 16 angles x 32 bins, two rays
  *           per thread; the default where it applies);
- * adjoint:  adj_px = 0 one thread per pixel, or 1, 2, 4 pixels per thread with
+ * adjoint:  adj_px = 0 one thread per pixel, or 1, 2, 4, 8 pixels per thread with
  *           LDS-staged sinogram chunks, the angles split into adj_s (1..8)
  *           shares whose partial images are summed in a fixed order.
  * All variants compute the same weights; results differ only by summation

@@ -115,7 +115,7 @@ struct mcr_handle {
   struct Tune {
     int fwd = 3;     // 0 one thread per ray, 1 LDS-tiled (8 angles x 32 bins), 2 the same with a host band
                      // schedule, 3 line-sheared bands (16 angles x 32 bins, two rays per thread)
-    int adj_px = 4;  // 0 one thread per pixel; 1, 2, 4 pixels per thread (LDS-tiled)
+    int adj_px = 4;  // 0 one thread per pixel; 1, 2, 4, 8 pixels per thread (LDS-tiled)
     int adj_s = 4;   // angle shares per pixel tile (LDS-tiled adjoint)
   } tune;
   bool fwd_lds_ok = false;         // every band window of the tiled forward fits in LDS
@@ -739,8 +739,10 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
         ADJ(1);
       else if (px == 2)
         ADJ(2);
-      else
+      else if (px == 4)
         ADJ(4);
+      else
+        ADJ(8);
 #undef ADJ
       LAUNCH_OK();
       if (S > 1) {
@@ -1769,7 +1771,7 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
         }
       }
       h->tune.fwd = best.fwd;
-      const int cand[][2] = {{0, 1}, {1, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {4, 4}, {4, 6}, {4, 8}};
+      const int cand[][2] = {{0, 1}, {1, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {4, 4}, {4, 6}, {4, 8}, {8, 4}, {8, 8}};
       best_ms = 1e30f;
       for (const auto& c : cand) {
         if (st != MCR_OK) break;
@@ -1801,8 +1803,8 @@ mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t a
   if (fwd < 0 || fwd > 3) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1, 2 or 3", fwd);
   if (h->dtype == MCR_F32 && !fwd_variant_ok(h, fwd))
     return fail(MCR_ERR_STATE, "the tiled forward's band windows do not fit this geometry");
-  if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4)
-    return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2 or 4", adj_px);
+  if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4 && adj_px != 8)
+    return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2, 4 or 8", adj_px);
   if (adj_s < 1 || adj_s > kMaxShares) return fail(MCR_ERR_ARG, "angle shares %d must be in [1, %d]", adj_s, kMaxShares);
   h->tune.fwd = fwd;
   h->tune.adj_px = adj_px;

@@ -305,10 +305,15 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const An
       float v = 0.0f, v1 = 0.0f;
       if (l < bd.y) {
         const int o = (int)(((long long)l * Bm) >> 32);
-        const int c = bd.z + o + (ib & ((1 << bd.w) - 1)) + lane;
-        const float* row = img + (long)(bd.x + l) * pitch;
-        v = row[min(max(c, -kPad), n + kPad - 1)];
-        v1 = row[min(max(c + 1, -kPad), n + kPad - 1)];
+        // column + kPad, clamped into the padded row [0, n + 2 kPad - 1]; its
+        // right neighbour is read unclamped: past the row's right halo it is
+        // the next padded row's left halo (or a bottom padding row), zero too
+        const float* row = img - kPad + (long)(bd.x + l) * pitch;
+        const unsigned i =
+            (unsigned)min(max(bd.z + o + (ib & ((1 << bd.w) - 1)) + lane + kPad, 0), n + 2 * kPad - 1);
+        const float* q = row + i;
+        v = q[0];
+        v1 = q[1];
       }
       pre[e] = v;
       prd[e] = v1 - v;
@@ -434,7 +439,14 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 }
 
 constexpr int kAdjKC = 32;  // angles per staged chunk
-constexpr int kAdjW = 64;   // bins staged per angle
+
+// Bins staged per angle: a 32 x 8PX pixel tile projects onto at most
+// sqrt(32^2 + (8PX)^2) bins (< 46 for PX = 4, < 71 for PX = 8), plus the
+// window margins.
+template <int PX>
+constexpr int adj_window() {
+  return PX == 8 ? 80 : 64;
+}
 
 // grid (ceil(n/(8*PX)), ceil(n/32), G*S), block 256. With S > 1 block z
 // handles angle share z % S of gate slot z / S and writes an unpadded partial
@@ -444,6 +456,8 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
                                                         const float* __restrict__ sino, long sino_stride,
                                                         float* __restrict__ out, long out_stride,
                                                         int padded, int S, long part_stride) {
+  constexpr int kAdjW = adj_window<PX>();
+  constexpr int kAdjUnroll = PX >= 8 ? 1 : 2;  // angles per unrolled step (registers)
   __shared__ float sy[kAdjKC * kAdjW];
   __shared__ long long s_row[kAdjKC][32];  // detector coordinate of row offset ty (incl. window base)
   __shared__ long long s_col[kAdjKC][8];   // ... plus column offset tx*PX
@@ -541,7 +555,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
     }
     __syncthreads();
     if (k1 < kend) fetch(k1, kcn1, s_jb[cur ^ 1]);
-#pragma unroll 2
+#pragma unroll kAdjUnroll
     for (int kc = 0; kc < kcn; ++kc) {
       const float4 wc = s_w[kc];
       const float na32 = wc.x, pa32 = wc.y, oma = wc.z;

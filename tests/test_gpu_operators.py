@@ -37,7 +37,7 @@ def test_project_and_backproject(dtype, bar, geom):
 
 # (forward, adjoint pixels per thread, adjoint angle shares)
 VARIANTS = [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 2), (1, 4, 1), (1, 4, 4), (0, 4, 3), (2, 4, 4), (2, 2, 1),
-            (3, 4, 4), (3, 1, 2), (3, 4, 8), (2, 2, 7)]
+            (3, 4, 4), (3, 1, 2), (3, 4, 8), (2, 2, 7), (3, 8, 4), (0, 8, 1)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -64,7 +64,7 @@ def test_autotune_keeps_parity():
     P = Problem(128, 120, 182, 3, "field")
     h = P.handle(torch.float32)
     choice = h.autotune(1)
-    assert choice["fwd"] in (0, 1, 2, 3) and choice["adj_px"] in (0, 1, 2, 4) and 1 <= choice["adj_shares"] <= 8
+    assert choice["fwd"] in (0, 1, 2, 3) and choice["adj_px"] in (0, 1, 2, 4, 8) and 1 <= choice["adj_shares"] <= 8
     assert h.autotune(3) is not None
     x = f32(synth.ellipse_phantom(128, 1))
     y = f32(synth.random_sinograms(1, 120, 182, 2)[0])
