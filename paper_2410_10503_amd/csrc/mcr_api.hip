@@ -670,7 +670,7 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
   Work<T>& w = work<T>(h);
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_WARP);
-  dim3 grid(cdiv(n, 32), cdiv(n, 32), G), block(32, 8);
+  dim3 grid(cdiv(n, 32), cdiv(n, 32), G), block(32, 32);
   hipLaunchKernelGGL(k_warp_fwd<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate0,
                      h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, w.wTP, h->padded, slots);
   LAUNCH_OK();

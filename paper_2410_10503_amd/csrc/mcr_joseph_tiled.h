@@ -319,7 +319,22 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const An
       prd[e] = v1 - v;
     }
   };
-  if (bb.y > 0) fetch(bands[bb.x]);
+  // crossings of both rays on the piece's first line, relative to the first
+  // band's window; the bands of a piece are consecutive lines, so at a band
+  // change only the window start moves
+  unsigned lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+  int s_prev = 0;
+  if (bb.y > 0) {
+    const int4 bd = bands[bb.x];
+    fetch(bd);
+    const unsigned long long p0 = (unsigned long long)(c0j + (long long)bd.x * A0.B - ((long long)bd.z << 32));
+    const unsigned long long p1 = (unsigned long long)(c1j + (long long)bd.x * A1.B - ((long long)bd.z << 32));
+    lo0 = (unsigned)p0;
+    hi0 = (unsigned)(p0 >> 32);
+    lo1 = (unsigned)p1;
+    hi1 = (unsigned)(p1 >> 32);
+    s_prev = bd.z;
+  }
   float acc0 = 0.0f, acc1 = 0.0f;
   for (int b = 0; b < bb.y; ++b) {
     const int4 bd = bands[bb.x + b];
@@ -327,10 +342,9 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const An
     for (int e = 0; e < kPer; ++e) st[256 * e + tid] = make_float2(pre[e], prd[e]);
     __syncthreads();
     if (b + 1 < bb.y) fetch(bands[bb.x + b + 1]);
-    const unsigned long long p0 = (unsigned long long)(c0j + (long long)bd.x * A0.B - ((long long)bd.z << 32));
-    const unsigned long long p1 = (unsigned long long)(c1j + (long long)bd.x * A1.B - ((long long)bd.z << 32));
-    unsigned lo0 = (unsigned)p0, hi0 = (unsigned)(p0 >> 32);
-    unsigned lo1 = (unsigned)p1, hi1 = (unsigned)(p1 >> 32);
+    hi0 += (unsigned)(s_prev - bd.z);
+    hi1 += (unsigned)(s_prev - bd.z);
+    s_prev = bd.z;
     long long om = 0;
     float a0 = 0.0f, f0 = 0.0f, a1 = 0.0f, f1 = 0.0f;
     const char* base = (const char*)st;

@@ -189,13 +189,14 @@ __device__ __forceinline__ void project_epilogue(T s, long idx, T* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // a1: forward warp  w = D_i x  (bilinear pull-back, zero outside the image).
-// One thread per output pixel, 32x32 tiles; the tile is also written
-// transposed (through LDS) so that the projector reads column-stepping
-// angles with unit stride.
-// grid (ceil(n/32), ceil(n/32), G), block (32, 8)
+// One thread per output pixel, 32x32 tiles (1024 threads, so that a 512^2
+// image fills every SIMD with 4 waves); the tile is also written transposed
+// (through LDS) so that the projector reads column-stepping angles with unit
+// stride.
+// grid (ceil(n/32), ceil(n/32), G), block (32, 32)
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_warp_fwd(Geo<T> g, const GateMotion<T>* __restrict__ gm,
+__global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>* __restrict__ gm,
                                                   int gate0, const float* __restrict__ field,
                                                   long field_stride, long plane_stride,
                                                   const T* __restrict__ x, long x_stride,
@@ -213,9 +214,8 @@ __global__ __launch_bounds__(256) void k_warp_fwd(Geo<T> g, const GateMotion<T>*
   T* dst = wP + blockIdx.z * w_stride + origin;
   T* dstT = wTP + blockIdx.z * w_stride + origin;
   const int c = blockIdx.x * 32 + threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int r = blockIdx.y * 32 + threadIdx.y + 8 * i;
+  {
+    const int r = blockIdx.y * 32 + threadIdx.y;
     T v = T(0);
     if (r < n && c < n) {
       if (M.kind == 0) {
@@ -237,16 +237,13 @@ __global__ __launch_bounds__(256) void k_warp_fwd(Geo<T> g, const GateMotion<T>*
       }
       dst[(long)r * pitch + c] = v;
     }
-    tile[threadIdx.y + 8 * i][threadIdx.x] = v;
+    tile[threadIdx.y][threadIdx.x] = v;
   }
   __syncthreads();
-  // transposed store: thread (tx, ty) writes column blockIdx.x*32 + ty + 8i, rows along tx
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int cc = blockIdx.x * 32 + threadIdx.y + 8 * i;
-    const int rr = blockIdx.y * 32 + threadIdx.x;
-    if (cc < n && rr < n) dstT[(long)cc * pitch + rr] = tile[threadIdx.x][threadIdx.y + 8 * i];
-  }
+  // transposed store: thread (tx, ty) writes column blockIdx.x*32 + ty, rows along tx
+  const int cc = blockIdx.x * 32 + threadIdx.y;
+  const int rr = blockIdx.y * 32 + threadIdx.x;
+  if (cc < n && rr < n) dstT[(long)cc * pitch + rr] = tile[threadIdx.x][threadIdx.y];
 }
 
 // ---------------------------------------------------------------------------
