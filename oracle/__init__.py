@@ -24,5 +24,5 @@ Where the paper is silent or garbled, the readings are listed in the design
 notes: step (i) uses the extrapolated z-bar, step (iii) extrapolates from z,
 f_i(u) = |u - d_i|^2 / N and g(x) = alpha |x|^2.
 """
-from . import projector, warp, spdhg, grad  # noqa: F401
+from . import projector, warp, spdhg, grad, subsets  # noqa: F401
 from .operators import GatedOperators  # noqa: F401
