@@ -242,6 +242,46 @@ mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq,
                           double* sigma, double* tau, double* theta, double* rate_per_epoch);
 
 /* ---------------------------------------------------------------------------
+ * Sampling over gates x angle subsets (the next step named in the
+ * Conclusions: sampling over both the gates and subsets of the data).
+ * The angles are cut into M contiguous subsets [k_s, k_{s+1}),
+ * k_s = floor(s n_angles / M). Block b = i M + s (gate i, subset s) has the
+ * operator A_b = R_s A D_i (R_s keeps the rows of subset s) and the data term
+ * f_b(u) = |u - d_{i,s}|^2 / N, so the objective, its minimiser and the dual
+ * solution are those of the gate problem; f_b^* keeps the modulus N/2, so the
+ * dual step of a block is the gate formula (with N, the gate count) on the
+ * block's rows. An epoch is N M block iterations (the operator work of one
+ * PDHG iteration).
+ * ------------------------------------------------------------------------- */
+/* Sets the number of angle subsets (1 <= M <= n_angles; 1 at creation).
+ * Rebuilds the float32 forward projector's work tables so that no work unit
+ * crosses a subset boundary; the full-range operators are unchanged.
+ * Synchronises the stream. Not available on batch handles (MCR_ERR_STATE).  */
+mcr_status mcr_set_subsets(mcr_handle* h, int32_t n_subsets);
+/* |A_b|^2 for block (gate, subset) by FP64 power iteration on A_b^* A_b, as
+ * mcr_power_norm_sq.                                                          */
+mcr_status mcr_block_norm_sq(mcr_handle* h, int32_t gate, int32_t subset, const double* v0,
+                             int32_t max_iter, double rtol, double* out, int32_t* iters);
+/* n_iter iterations of Algorithm 1 over blocks with serial sampling: iteration
+ * k updates block block_seq[k] (host int32, entries in [0, N M)): step (i);
+ * the rows of subset s of y_i become (y + sigma_b (A_b x - d)) / (1 + sigma_b N/2);
+ * z += A_b^*(dy); z-bar = z + (theta / p_b) A_b^*(dy). sigma and p are host
+ * arrays of N M doubles indexed by block; y and d stay per gate (full
+ * [n_angles][n_det] arrays, only the block's rows are read or written).      */
+mcr_status mcr_spdhg_blocks_iterate(mcr_handle* h, const mcr_state* st, const void* const* d,
+                                    double alpha, const double* sigma, double tau, double theta,
+                                    const double* p, const int32_t* block_seq, int32_t n_iter);
+/* Host step sizes for serial uniform sampling over the N M blocks
+ * (p = 1/(N M)): s_b = sqrt(1 + norms_sq[b] / (alpha N)), s = max_b s_b,
+ * rho = 1 - 2p / (1 + s), sigma_b = 2 / (N (s_b - 1)),
+ * tau = p / (2 alpha rho (1 + s)), theta = rho; per-epoch rate rho^(N M) =
+ * l(max_b |A_b|^2 / (alpha N), N M). sigma: host array of N M doubles (out);
+ * tau, theta, rate may be NULL.                                               */
+mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const double* norms_sq,
+                                 double alpha, double* sigma, double* tau, double* theta,
+                                 double* rate_per_epoch);
+
+/* ---------------------------------------------------------------------------
  * Kernel variants of the float32 projector pair (no effect on FP64 handles).
  * forward:  0 = one thread per ray, 1 = LDS-tiled (8 angles x 32 bins share a
  *           staged image band; only where every band window fits in LDS),

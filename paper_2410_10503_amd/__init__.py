@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import McrError  # noqa: F401
 
-__all__ = ["Handle", "BatchHandle", "ReconState", "McrError", "step_sizes"]
+__all__ = ["Handle", "BatchHandle", "ReconState", "McrError", "step_sizes", "step_sizes_blocks"]
 
 _DTYPES = {torch.float32: _lib.MCR_F32, torch.float64: _lib.MCR_F64}
 
@@ -45,6 +45,21 @@ def step_sizes(algo: str, norms_sq: Sequence[float], alpha: float, n_gates: int)
     tau, theta, rate = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
     _lib.check(lib.mcr_step_sizes(a, n_gates, _dbl_array(norms_sq), float(alpha), sig,
                                   ctypes.byref(tau), ctypes.byref(theta), ctypes.byref(rate)))
+    return list(sig), tau.value, theta.value, rate.value
+
+
+def step_sizes_blocks(norms_sq: Sequence[float], alpha: float, n_gates: int, n_subsets: int):
+    """Step sizes for serial uniform sampling over gates x angle subsets
+    (norms_sq: |A_b|^2 per block b = gate * M + subset). Returns
+    (sigma list [N M], tau, theta, rate per epoch)."""
+    lib = _lib.load()
+    nb = n_gates * n_subsets
+    if len(norms_sq) != nb:
+        raise ValueError(f"need {nb} block norms")
+    sig = (ctypes.c_double * nb)()
+    tau, theta, rate = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _lib.check(lib.mcr_step_sizes_blocks(n_gates, n_subsets, _dbl_array(norms_sq), float(alpha), sig,
+                                         ctypes.byref(tau), ctypes.byref(theta), ctypes.byref(rate)))
     return list(sig), tau.value, theta.value, rate.value
 
 
@@ -81,6 +96,7 @@ class Handle:
         self.n, self.n_angles, self.n_det = int(n), int(n_angles), int(n_det)
         self.dtype = dtype
         self.n_gates = len(motion)
+        self.n_subsets = 1
         self._h = ctypes.c_void_p()
         arr = (_lib.Motion * self.n_gates)()
         keep = []
@@ -292,6 +308,35 @@ class Handle:
         _lib.check(self._lib.mcr_power_norm_sq(self._h, int(gate), v0.data_ptr(), int(max_iter), float(rtol),
                                                ctypes.byref(out), ctypes.byref(it)))
         return out.value, it.value
+
+    def set_subsets(self, n_subsets: int):
+        """Cut the angles into n_subsets contiguous subsets (gates x angle-subsets sampling)."""
+        self._sync_stream()
+        _lib.check(self._lib.mcr_set_subsets(self._h, int(n_subsets)))
+        self.n_subsets = int(n_subsets)
+
+    def block_norm_sq(self, gate: int, subset: int, v0, max_iter: int = 500, rtol: float = 1e-12):
+        """|A_b|^2 of block (gate, subset)."""
+        self._sync_stream()
+        if not (v0.dtype == torch.float64 and v0.is_cuda and tuple(v0.shape) == (self.n, self.n)
+                and v0.is_contiguous()):
+            raise ValueError("v0 must be a contiguous float64 device tensor of shape (n, n)")
+        out, it = ctypes.c_double(), ctypes.c_int32()
+        _lib.check(self._lib.mcr_block_norm_sq(self._h, int(gate), int(subset), v0.data_ptr(), int(max_iter),
+                                               float(rtol), ctypes.byref(out), ctypes.byref(it)))
+        return out.value, it.value
+
+    def spdhg_blocks_iterate(self, st: ReconState, d, alpha, sigma, tau, theta, p, block_seq):
+        """Iterations of Algorithm 1 over blocks b = gate * M + subset (sigma, p per block)."""
+        self._sync_stream()
+        nb = self.n_gates * self.n_subsets
+        if len(sigma) != nb or len(p) != nb:
+            raise ValueError(f"sigma and p need {nb} entries (one per block)")
+        seq = [int(b) for b in block_seq]
+        c_seq = (ctypes.c_int32 * max(1, len(seq)))(*seq)
+        _lib.check(self._lib.mcr_spdhg_blocks_iterate(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
+                                                      float(alpha), _dbl_array(sigma), float(tau), float(theta),
+                                                      _dbl_array(p), c_seq, len(seq)))
 
     def objective(self, x, d, alpha) -> float:
         self._sync_stream()

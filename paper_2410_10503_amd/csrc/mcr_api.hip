@@ -82,6 +82,8 @@ struct Work {
   std::vector<char> last;
   std::vector<GateScalars<T>> sc_host;  // last tables handed to upload_params
   std::vector<GatePtrs<T>> pt_host;
+  int sc_base = 0;                      // first scalar entry the launches use (angle subset s: s N)
+  int sc_cap = 0;                       // scalar entries allocated
 };
 
 }  // namespace
@@ -133,6 +135,11 @@ struct mcr_handle {
   float* shear_part = nullptr;     // [slots][part_floats] partial ray sums of multi-piece units
   int* shear_multi = nullptr;      // units cut into several pieces
   int shear_npieces = 0, shear_nmulti = 0;
+  std::vector<int2> shear_sub;        // per angle subset: (first piece, pieces)
+  std::vector<int2> shear_sub_multi;  // per angle subset: (first multi-piece unit entry, entries)
+  // angle subsets (mcr_set_subsets): subset s holds angles [sub_k[s], sub_k[s + 1])
+  int M = 1;
+  std::vector<int> sub_k;
   long shear_part_floats = 0;
   float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
   // batched SPDHG (mcr_batch_create): S independent slices sharing the geometry
@@ -377,6 +384,7 @@ struct Schedule {
   std::vector<int4> units;   // (chunk, detector tile, pieces P, offset of the unit's partial sums)
   std::vector<int> multi;    // units with P > 1
   long part_floats = 0;      // partial sums per gate slot
+  std::vector<int2> sub_pieces, sub_multi;  // per angle subset: (first, count) of pieces / multi entries
 };
 
 // Lines [L_lo, L_hi] on which some ray of angles [k0, k0 + cnt) and bins
@@ -446,12 +454,24 @@ bool shear_tile_bands(int n, int nd, const std::vector<AngleFx>& af, int k0, int
   return true;
 }
 
-// Chunks of up to kShKA angles of one stepping type, halved where a line of
-// some detector tile does not fit the window.
-Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af) {
+// Chunks of up to kShKA angles of one stepping type and one angle subset
+// (bounds: k_0 = 0 < ... < k_M = n_angles), halved where a line of some
+// detector tile does not fit the window.
+Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& bounds) {
   Schedule S;
   const int ntiles = (nd + kShJD - 1) / kShJD;
-  for (const int2& run : angle_chunks(af, INT_MAX)) {
+  std::vector<int2> runs;
+  for (const int2& r : angle_chunks(af, INT_MAX)) {
+    int k = r.x;
+    for (size_t b = 1; b < bounds.size() && k < r.x + r.y; ++b) {
+      const int e = std::min(r.x + r.y, bounds[b]);
+      if (e > k) {
+        runs.push_back(make_int2(k, e - k));
+        k = e;
+      }
+    }
+  }
+  for (const int2& run : runs) {
     for (int k0 = run.x; k0 < run.x + run.y;) {
       int cnt = std::min(kShKA, run.x + run.y - k0);
       std::vector<int2> blocks;
@@ -506,6 +526,24 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af) {
       (void)first_piece;
     }
   }
+  // pieces and multi-piece units come in chunk order, so each subset's are contiguous
+  const int M = (int)bounds.size() - 1;
+  S.sub_pieces.assign(M, make_int2(0, 0));
+  S.sub_multi.assign(M, make_int2(0, 0));
+  auto subset_of = [&](int unit) {
+    const int k0 = S.chunks[S.units[unit].x].x;
+    return (int)(std::upper_bound(bounds.begin(), bounds.end(), k0) - bounds.begin()) - 1;
+  };
+  for (int q = 0; q < (int)S.pieces.size(); ++q) {
+    int2& r = S.sub_pieces[subset_of(S.pieces[q].z)];
+    if (r.y == 0) r.x = q;
+    ++r.y;
+  }
+  for (int q = 0; q < (int)S.multi.size(); ++q) {
+    int2& r = S.sub_multi[subset_of(S.multi[q])];
+    if (r.y == 0) r.x = q;
+    ++r.y;
+  }
   return S;
 }
 
@@ -556,6 +594,66 @@ Schedule build_schedule(int n, int nd, const std::vector<AngleFx>& af, int ka, i
   return S;
 }
 
+void dfree(mcr_handle* h, void* p) {
+  if (!p) return;
+  auto it = std::find(h->allocs.begin(), h->allocs.end(), p);
+  if (it != h->allocs.end()) h->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+// (Re)builds the line-sheared forward's tables for the handle's angle subsets.
+// Synchronises the stream (the previous tables may still be in use).
+mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
+  HIP_OK(hipStreamSynchronize(h->stream));
+  for (void* p : {(void*)h->shear_chunks, (void*)h->shear_pieces, (void*)h->shear_units, (void*)h->shear_bands,
+                  (void*)h->shear_part, (void*)h->shear_multi})
+    dfree(h, p);
+  h->shear_chunks = h->shear_pieces = h->shear_units = h->shear_bands = nullptr;
+  h->shear_part = nullptr;
+  h->shear_multi = nullptr;
+  h->shear_npieces = h->shear_nmulti = 0;
+  h->shear_sub.clear();
+  h->shear_sub_multi.clear();
+  const Schedule ss = build_shear_schedule(h->geo.n, h->geo.n_det, af, h->sub_k);
+  if (!ss.ok) return MCR_OK;  // variant 3 unavailable on this geometry
+  const int ns = h->nslots;
+  h->shear_part_floats = ss.part_floats;
+  STATUS_OK(dmalloc(h, (void**)&h->shear_chunks, sizeof(int4) * ss.chunks.size()));
+  STATUS_OK(dmalloc(h, (void**)&h->shear_pieces, sizeof(int4) * ss.pieces.size()));
+  STATUS_OK(dmalloc(h, (void**)&h->shear_units, sizeof(int4) * ss.units.size()));
+  STATUS_OK(dmalloc(h, (void**)&h->shear_bands, sizeof(int4) * std::max<size_t>(1, ss.bands.size())));
+  STATUS_OK(dmalloc(h, (void**)&h->shear_part, sizeof(float) * std::max<long>(1, ss.part_floats) * ns));
+  STATUS_OK(dmalloc(h, (void**)&h->shear_multi, sizeof(int) * std::max<size_t>(1, ss.multi.size())));
+  HIP_OK(hipMemcpyAsync(h->shear_chunks, ss.chunks.data(), sizeof(int4) * ss.chunks.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  HIP_OK(hipMemcpyAsync(h->shear_pieces, ss.pieces.data(), sizeof(int4) * ss.pieces.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  HIP_OK(hipMemcpyAsync(h->shear_units, ss.units.data(), sizeof(int4) * ss.units.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  if (!ss.bands.empty())
+    HIP_OK(hipMemcpyAsync(h->shear_bands, ss.bands.data(), sizeof(int4) * ss.bands.size(), hipMemcpyHostToDevice,
+                          h->stream));
+  if (!ss.multi.empty())
+    HIP_OK(hipMemcpyAsync(h->shear_multi, ss.multi.data(), sizeof(int) * ss.multi.size(), hipMemcpyHostToDevice,
+                          h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  h->shear_npieces = (int)ss.pieces.size();
+  h->shear_nmulti = (int)ss.multi.size();
+  h->shear_sub = ss.sub_pieces;
+  h->shear_sub_multi = ss.sub_multi;
+  return MCR_OK;
+}
+
+void subset_range(const mcr_handle* h, int subset, int& ka, int& kb) {
+  if (subset < 0) {
+    ka = 0;
+    kb = h->geo.n_angles;
+  } else {
+    ka = h->sub_k[subset];
+    kb = h->sub_k[subset + 1];
+  }
+}
+
 template <typename T>
 mcr_status init_work(mcr_handle* h) {
   Work<T>& w = work<T>(h);
@@ -564,7 +662,8 @@ mcr_status init_work(mcr_handle* h) {
   const long n2 = (long)h->geo.n * h->geo.n;
   STATUS_OK(dmalloc(h, (void**)&w.ang, sizeof(AngleT<T>) * h->geo.n_angles));
   STATUS_OK(dmalloc(h, (void**)&w.motion, sizeof(GateMotion<T>) * (N + 1)));
-  STATUS_OK(dmalloc(h, (void**)&w.scalars, sizeof(GateScalars<T>) * N));
+  w.sc_cap = N * h->M;
+  STATUS_OK(dmalloc(h, (void**)&w.scalars, sizeof(GateScalars<T>) * w.sc_cap));
   STATUS_OK(dmalloc(h, (void**)&w.ptrs, sizeof(GatePtrs<T>) * N));
   const int ns = h->nslots;
   STATUS_OK(dmalloc(h, (void**)&w.wP, sizeof(T) * h->padded * ns));
@@ -573,7 +672,7 @@ mcr_status init_work(mcr_handle* h) {
   STATUS_OK(dmalloc(h, (void**)&w.dy, sizeof(T) * h->sino * ns));
   STATUS_OK(dmalloc(h, (void**)&w.img, sizeof(T) * n2));
   STATUS_OK(dmalloc(h, (void**)&w.img2, sizeof(T) * n2));
-  w.pin_bytes = (sizeof(GateScalars<T>) + sizeof(GatePtrs<T>)) * N;
+  w.pin_bytes = sizeof(GateScalars<T>) * w.sc_cap + sizeof(GatePtrs<T>) * N;
   HIP_OK(hipHostMalloc(&w.pin, w.pin_bytes, hipHostMallocDefault));
   HIP_OK(hipEventCreateWithFlags(&w.pin_ev, hipEventDisableTiming));
   const std::vector<AngleT<T>> at = angle_table<T>(h->geo.n_angles);
@@ -602,31 +701,7 @@ mcr_status init_work(mcr_handle* h) {
       HIP_OK(hipMemcpyAsync(h->sched_bands, sc.bands.data(), sizeof(int4) * sc.bands.size(), hipMemcpyHostToDevice,
                             h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
-    const Schedule ss = build_shear_schedule(h->geo.n, h->geo.n_det, af);
-    if (ss.ok) {
-      h->shear_npieces = (int)ss.pieces.size();
-      h->shear_nmulti = (int)ss.multi.size();
-      h->shear_part_floats = ss.part_floats;
-      STATUS_OK(dmalloc(h, (void**)&h->shear_chunks, sizeof(int4) * ss.chunks.size()));
-      STATUS_OK(dmalloc(h, (void**)&h->shear_pieces, sizeof(int4) * ss.pieces.size()));
-      STATUS_OK(dmalloc(h, (void**)&h->shear_units, sizeof(int4) * ss.units.size()));
-      STATUS_OK(dmalloc(h, (void**)&h->shear_bands, sizeof(int4) * std::max<size_t>(1, ss.bands.size())));
-      STATUS_OK(dmalloc(h, (void**)&h->shear_part, sizeof(float) * std::max<long>(1, ss.part_floats) * ns));
-      STATUS_OK(dmalloc(h, (void**)&h->shear_multi, sizeof(int) * std::max<size_t>(1, ss.multi.size())));
-      if (!ss.multi.empty())
-        HIP_OK(hipMemcpyAsync(h->shear_multi, ss.multi.data(), sizeof(int) * ss.multi.size(), hipMemcpyHostToDevice,
-                              h->stream));
-      HIP_OK(hipMemcpyAsync(h->shear_chunks, ss.chunks.data(), sizeof(int4) * ss.chunks.size(),
-                            hipMemcpyHostToDevice, h->stream));
-      HIP_OK(hipMemcpyAsync(h->shear_pieces, ss.pieces.data(), sizeof(int4) * ss.pieces.size(),
-                            hipMemcpyHostToDevice, h->stream));
-      HIP_OK(hipMemcpyAsync(h->shear_units, ss.units.data(), sizeof(int4) * ss.units.size(),
-                            hipMemcpyHostToDevice, h->stream));
-      if (!ss.bands.empty())
-        HIP_OK(hipMemcpyAsync(h->shear_bands, ss.bands.data(), sizeof(int4) * ss.bands.size(), hipMemcpyHostToDevice,
-                              h->stream));
-      HIP_OK(hipStreamSynchronize(h->stream));
-    }
+    STATUS_OK(upload_shear(h, af));
   }
   HIP_OK(hipStreamSynchronize(h->stream));
   STATUS_OK(upload_motion<T>(h));
@@ -677,51 +752,66 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
   return MCR_OK;
 }
 
+// Angles of subset `subset` (-1: all angles).
+void subset_range(const mcr_handle* h, int subset, int& ka, int& kb);
+
 template <typename T, int MODE>
 mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stride,
-                          const SlotInfo* slots = nullptr) {
+                          const SlotInfo* slots = nullptr, int subset = -1) {
   Work<T>& w = work<T>(h);
   Timed tm(h, MCR_KERNEL_PROJECT);
-  dim3 grid(cdiv(h->geo.n_det, 256), h->geo.n_angles, G), block(256);
+  int ka, kb;
+  subset_range(h, subset, ka, kb);
+  const GateScalars<T>* gs = w.scalars + w.sc_base;
+  dim3 grid(cdiv(h->geo.n_det, 256), kb - ka, G), block(256);
   if constexpr (std::is_same<T, float>::value) {
-    if (h->tune.fwd == 3 && h->shear_npieces > 0) {
-      dim3 gt(h->shear_npieces, 1, G);
-      hipLaunchKernelGGL((k_joseph_fwd_shear<MODE>), gt, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx,
-                         h->shear_chunks, h->shear_pieces, h->shear_units, h->shear_bands, w.wP, w.wTP, h->padded,
-                         out, out_stride, gate0, w.scalars, w.ptrs, slots, h->shear_part, h->shear_part_floats);
-      if (h->shear_nmulti > 0) {
+    // the chunk tables of variants 1 and 2 cover all angles
+    const int fwd = (subset >= 0 && (h->tune.fwd == 1 || h->tune.fwd == 2)) ? (h->shear_npieces > 0 ? 3 : 0)
+                                                                             : h->tune.fwd;
+    if (fwd == 3 && h->shear_npieces > 0) {
+      const int2 pr = subset >= 0 ? h->shear_sub[subset] : make_int2(0, h->shear_npieces);
+      const int2 mr = subset >= 0 ? h->shear_sub_multi[subset] : make_int2(0, h->shear_nmulti);
+      if (pr.y > 0) {
+        hipLaunchKernelGGL((k_joseph_fwd_shear<MODE>), dim3(pr.y, 1, G), dim3(256), 0, h->stream, geo_of<T>(h),
+                           w.angfx, h->shear_chunks, h->shear_pieces, h->shear_units, h->shear_bands, w.wP, w.wTP,
+                           h->padded, out, out_stride, gate0, gs, w.ptrs, slots, h->shear_part, h->shear_part_floats,
+                           pr.x);
         LAUNCH_OK();
-        hipLaunchKernelGGL((k_joseph_fwd_shear_finish<MODE>), dim3(h->shear_nmulti, 1, G), dim3(256), 0, h->stream,
-                           geo_of<T>(h), w.angfx, h->shear_chunks, h->shear_units, h->shear_multi, h->shear_part,
-                           h->shear_part_floats, out, out_stride, gate0, w.scalars, w.ptrs, slots);
       }
-    } else if (h->tune.fwd == 2 && h->sched_ok) {
+      if (mr.y > 0) {
+        hipLaunchKernelGGL((k_joseph_fwd_shear_finish<MODE>), dim3(mr.y, 1, G), dim3(256), 0, h->stream,
+                           geo_of<T>(h), w.angfx, h->shear_chunks, h->shear_units, h->shear_multi, h->shear_part,
+                           h->shear_part_floats, out, out_stride, gate0, gs, w.ptrs, slots, mr.x);
+      }
+    } else if (fwd == 2 && h->sched_ok) {
       dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->sched_nchunks, G);
       hipLaunchKernelGGL((k_joseph_fwd_sched<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
                          geo_of<T>(h), w.angfx, h->sched_chunks, h->sched_blocks, h->sched_bands, w.wP, w.wTP,
-                         h->padded, out, out_stride, gate0, w.scalars, w.ptrs, slots);
-    } else if (h->tune.fwd == 1 && h->fwd_lds_ok) {
+                         h->padded, out, out_stride, gate0, gs, w.ptrs, slots);
+    } else if (fwd == 1 && h->fwd_lds_ok) {
       dim3 gt(cdiv(h->geo.n_det, kFwdJD), h->nchunks, G);
       hipLaunchKernelGGL((k_joseph_fwd_lds<kFwdKA, kFwdJD, kFwdWL, MODE>), gt, dim3(256), 0, h->stream,
-                         geo_of<T>(h), w.angfx, h->chunks, w.wP, w.wTP, h->padded, out, out_stride, gate0,
-                         w.scalars, w.ptrs, slots);
+                         geo_of<T>(h), w.angfx, h->chunks, w.wP, w.wTP, h->padded, out, out_stride, gate0, gs,
+                         w.ptrs, slots);
     } else {
       hipLaunchKernelGGL((k_joseph_fwd_fx<MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.angfx, w.wP,
-                         w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs, slots);
+                         w.wTP, h->padded, out, out_stride, gate0, gs, w.ptrs, slots, ka);
     }
   } else
     hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.ang, w.wP,
-                       w.wTP, h->padded, out, out_stride, gate0, w.scalars, w.ptrs, slots);
+                       w.wTP, h->padded, out, out_stride, gate0, gs, w.ptrs, slots, ka);
   LAUNCH_OK();
   return MCR_OK;
 }
 
 template <typename T>
 mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_stride, T* out,
-                              long out_stride, int padded) {
+                              long out_stride, int padded, int subset = -1) {
   Work<T>& w = work<T>(h);
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_BACKPROJECT);
+  int ka, kb;
+  subset_range(h, subset, ka, kb);
   dim3 grid(cdiv(n, 16), cdiv(n, 16), G), block(16, 16);
   if constexpr (std::is_same<T, float>::value) {
     const int px = h->tune.adj_px, S = px > 0 ? h->tune.adj_s : 1;
@@ -734,7 +824,7 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
       dim3 gt(cdiv(n, 8 * px), cdiv(n, 32), G * S);
 #define ADJ(PX)                                                                                           \
   hipLaunchKernelGGL(k_joseph_adj_lds<PX>, gt, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx, sino, \
-                     sino_stride, dst, dst_stride, padded, S, part_stride)
+                     sino_stride, dst, dst_stride, padded, S, part_stride, ka, kb)
       if (px == 1)
         ADJ(1);
       else if (px == 2)
@@ -751,11 +841,11 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
       }
     } else {
       hipLaunchKernelGGL(k_joseph_adj_fx, grid, block, 0, h->stream, geo_of<T>(h), w.angfx, sino,
-                         sino_stride, out, out_stride, padded);
+                         sino_stride, out, out_stride, padded, ka, kb);
     }
   } else
     hipLaunchKernelGGL(k_joseph_adj<T>, grid, block, 0, h->stream, geo_of<T>(h), w.ang, sino,
-                       sino_stride, out, out_stride, padded);
+                       sino_stride, out, out_stride, padded, ka, kb);
   LAUNCH_OK();
   return MCR_OK;
 }
@@ -771,7 +861,7 @@ mcr_status launch_twarp(mcr_handle* h, int gate0, int G, T* out, UpdateArgs<T> u
   const Geo<T> g = geo_of<T>(h);
 #define TW(RR)                                                                                   \
   hipLaunchKernelGGL((k_twarp<T, MODE, RR>), grid, block, 0, h->stream, g, w.motion, gate0, G,   \
-                     w.scalars, h->fieldP, 2 * h->padded, h->padded, h->centres, w.bP, h->padded, \
+                     w.scalars + w.sc_base, h->fieldP, 2 * h->padded, h->padded, h->centres, w.bP, h->padded, \
                      out, ua, slots, (long)n * n, slice_tc)
   if (R <= 1)
     TW(1);
@@ -871,17 +961,78 @@ mcr_status check_alg(const mcr_handle* h, const mcr_state* st, const void* const
 // ---------------------------------------------------------------------------
 // Algorithm 1 driver: one iteration over the gates gate0 .. gate0+G-1.
 // ---------------------------------------------------------------------------
+// subset >= 0: the block (gate, subset) of the gates x angle-subsets
+// sampling; its scalars are entry subset * N + gate.
 template <typename T>
 mcr_status iteration(mcr_handle* h, const mcr_state* st, int gate0, int G, bool xstep_first,
-                     bool xstep_after, T tau, T cx) {
+                     bool xstep_after, T tau, T cx, int subset = -1) {
   Work<T>& w = work<T>(h);
   T* x = (T*)st->x;
   if (xstep_first) STATUS_OK(launch_xstep<T>(h, x, (const T*)st->zbar, tau, cx));
-  STATUS_OK(launch_warp<T>(h, gate0, G, x));
-  STATUS_OK((launch_project<T, 1>(h, gate0, G, w.dy, h->sino)));
-  STATUS_OK(launch_backproject<T>(h, G, w.dy, h->sino, w.bP, h->padded, 1));
+  w.sc_base = subset > 0 ? subset * h->N : 0;
+  mcr_status rc = launch_warp<T>(h, gate0, G, x);
+  if (rc == MCR_OK) rc = launch_project<T, 1>(h, gate0, G, w.dy, h->sino, nullptr, subset);
+  if (rc == MCR_OK) rc = launch_backproject<T>(h, G, w.dy, h->sino, w.bP, h->padded, 1, subset);
   UpdateArgs<T> ua{x, (T*)st->z, (T*)st->zbar, tau, cx, xstep_after ? 1 : 0};
-  STATUS_OK((launch_twarp<T, 2>(h, gate0, G, nullptr, ua)));
+  if (rc == MCR_OK) rc = launch_twarp<T, 2>(h, gate0, G, nullptr, ua);
+  w.sc_base = 0;
+  return rc;
+}
+
+// Scalar tables for N M blocks (grown when the subset count grows).
+template <typename T>
+mcr_status ensure_scalars(mcr_handle* h) {
+  Work<T>& w = work<T>(h);
+  if (!w.ready || w.sc_cap >= h->N * h->M) return MCR_OK;
+  HIP_OK(hipStreamSynchronize(h->stream));
+  if (w.pin_recorded) HIP_OK(hipEventSynchronize(w.pin_ev));
+  dfree(h, w.scalars);
+  w.scalars = nullptr;
+  w.sc_cap = h->N * h->M;
+  STATUS_OK(dmalloc(h, (void**)&w.scalars, sizeof(GateScalars<T>) * w.sc_cap));
+  HIP_OK(hipHostFree(w.pin));
+  w.pin = nullptr;
+  w.pin_bytes = sizeof(GateScalars<T>) * w.sc_cap + sizeof(GatePtrs<T>) * h->N;
+  HIP_OK(hipHostMalloc(&w.pin, w.pin_bytes, hipHostMallocDefault));
+  w.pin_recorded = false;
+  w.last.clear();
+  return MCR_OK;
+}
+
+// Block b = gate * M + subset has sigma[b], p[b]; its scalars go to entry
+// subset * N + gate, where the launches of an iteration on that subset look.
+template <typename T>
+mcr_status set_params_blocks(mcr_handle* h, const mcr_state* st, const void* const* d, const double* sigma,
+                             double theta, const double* p) {
+  const int N = h->N, M = h->M;
+  std::vector<GateScalars<T>> sc(N * M);
+  std::vector<GatePtrs<T>> pt(N);
+  for (int i = 0; i < N; ++i) {
+    for (int s = 0; s < M; ++s) {
+      const int b = i * M + s;
+      GateScalars<T>& e = sc[s * N + i];
+      e.sigma = T(sigma[b]);
+      e.cy = T(1.0 / (1.0 + sigma[b] * N / 2.0));
+      e.coef = T(theta / p[b]);
+      e.pad_ = T(0);
+    }
+    pt[i].y = (T*)st->y[i];
+    pt[i].d = (const T*)d[i];
+  }
+  Work<T>& w = work<T>(h);
+  w.sc_host = sc;
+  w.pt_host = pt;
+  return upload_params<T>(h, sc, pt);
+}
+
+template <typename T>
+mcr_status spdhg_blocks_impl(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                             const double* sigma, double tau, double theta, const double* p, const int32_t* seq,
+                             int n_iter) {
+  STATUS_OK(set_params_blocks<T>(h, st, d, sigma, theta, p));
+  const T t = T(tau), cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
+  for (int k = 0; k < n_iter; ++k)
+    STATUS_OK(iteration<T>(h, st, seq[k] / h->M, 1, k == 0, k + 1 < n_iter, t, cx, seq[k] % h->M));
   return MCR_OK;
 }
 
@@ -1064,11 +1215,11 @@ mcr_status warp_adjoint_impl(mcr_handle* h, int gate, const void* b, void* out) 
 // FP64 diagnostics (always on the double workspace)
 // ---------------------------------------------------------------------------
 // out = sum over gates in [gate0, gate0+G) of A_g^* A_g v  (v unpadded double)
-mcr_status normal_op64(mcr_handle* h, int gate0, int G, const double* v, double* out) {
+mcr_status normal_op64(mcr_handle* h, int gate0, int G, const double* v, double* out, int subset = -1) {
   Work<double>& w = h->wd;
   STATUS_OK(launch_warp<double>(h, gate0, G, v));
-  STATUS_OK((launch_project<double, 0>(h, gate0, G, w.dy, h->sino)));
-  STATUS_OK(launch_backproject<double>(h, G, w.dy, h->sino, w.bP, h->padded, 1));
+  STATUS_OK((launch_project<double, 0>(h, gate0, G, w.dy, h->sino, nullptr, subset)));
+  STATUS_OK(launch_backproject<double>(h, G, w.dy, h->sino, w.bP, h->padded, 1, subset));
   return launch_twarp<double, 0>(h, gate0, G, out, UpdateArgs<double>{});
 }
 
@@ -1337,6 +1488,7 @@ mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_moti
   h->sino = (long)geom->n_angles * geom->n_det;
   h->motion.assign(motion, motion + n_gates);
   h->radius.assign(n_gates, 1);
+  h->sub_k = {0, geom->n_angles};
   for (auto& m : h->motion) {
     if (m.kind == MCR_MOTION_FIELD) h->any_field = true;
   }
@@ -1656,12 +1808,11 @@ mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, co
   return DISPATCH(motion_grad_impl, h, gate, img, v, grad_motion);
 }
 
-mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int32_t max_iter, double rtol,
-                             double* out, int32_t* iters) {
-  STATUS_OK(check_handle(h));
-  if (gate != -1) STATUS_OK(check_gate(h, gate));
-  if (gate == -1 && h->nslots < h->N)
-    return fail(MCR_ERR_STATE, "the stacked norm over all gates is not available on a batch handle");
+}  // extern "C"
+
+namespace {
+mcr_status power_norm_impl(mcr_handle* h, int32_t gate, int subset, const double* v0, int32_t max_iter,
+                           double rtol, double* out, int32_t* iters) {
   STATUS_OK(check_ptr(v0, "v0"));
   STATUS_OK(check_ptr(out, "out"));
   if (max_iter < 1) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 1", max_iter);
@@ -1682,7 +1833,7 @@ mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int3
   for (it = 1; it <= max_iter; ++it) {
     hipLaunchKernelGGL(k_scale<double>, dim3(cdiv(n2, 256)), dim3(256), 0, h->stream, n2, v, scale);
     LAUNCH_OK();
-    STATUS_OK(normal_op64(h, gate0, G, v, av));
+    STATUS_OK(normal_op64(h, gate0, G, v, av, subset));
     STATUS_OK((launch_reduce<double, double, 1>(h, n2, v, av, 0)));
     STATUS_OK((launch_reduce<double, double, 0>(h, n2, av, av, 1)));
     STATUS_OK(read_results(h, 2));
@@ -1702,6 +1853,68 @@ mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int3
   *out = lam;
   if (iters) *iters = std::min(it, max_iter);
   return MCR_OK;
+}
+}  // namespace
+
+extern "C" {
+
+mcr_status mcr_power_norm_sq(mcr_handle* h, int32_t gate, const double* v0, int32_t max_iter, double rtol,
+                             double* out, int32_t* iters) {
+  STATUS_OK(check_handle(h));
+  if (gate != -1) STATUS_OK(check_gate(h, gate));
+  if (gate == -1 && h->nslots < h->N)
+    return fail(MCR_ERR_STATE, "the stacked norm over all gates is not available on a batch handle");
+  return power_norm_impl(h, gate, -1, v0, max_iter, rtol, out, iters);
+}
+
+mcr_status mcr_block_norm_sq(mcr_handle* h, int32_t gate, int32_t subset, const double* v0, int32_t max_iter,
+                             double rtol, double* out, int32_t* iters) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  if (subset < 0 || subset >= h->M) return fail(MCR_ERR_ARG, "subset = %d must be in [0, %d)", subset, h->M);
+  return power_norm_impl(h, gate, subset, v0, max_iter, rtol, out, iters);
+}
+
+mcr_status mcr_set_subsets(mcr_handle* h, int32_t n_subsets) {
+  STATUS_OK(check_handle(h));
+  if (n_subsets < 1 || n_subsets > h->geo.n_angles)
+    return fail(MCR_ERR_ARG, "n_subsets = %d must be in [1, %d]", n_subsets, h->geo.n_angles);
+  if (h->nslots < h->N) return fail(MCR_ERR_STATE, "angle subsets are not available on a batch handle");
+  if (n_subsets == h->M) return MCR_OK;
+  HIP_OK(hipStreamSynchronize(h->stream));
+  h->M = n_subsets;
+  h->sub_k.resize(n_subsets + 1);
+  for (int s = 0; s <= n_subsets; ++s) h->sub_k[s] = (int)((long)s * h->geo.n_angles / n_subsets);
+  STATUS_OK(ensure_scalars<float>(h));
+  STATUS_OK(ensure_scalars<double>(h));
+  if (h->wf.ready)
+    STATUS_OK(upload_shear(h, angle_table_fx(h->geo.n, h->geo.n_angles, h->geo.n_det)));
+  return MCR_OK;
+}
+
+mcr_status mcr_spdhg_blocks_iterate(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
+                                    const double* sigma, double tau, double theta, const double* p,
+                                    const int32_t* block_seq, int32_t n_iter) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_alg(h, st, d, alpha, sigma, tau, theta, nullptr));
+  STATUS_OK(check_ptr(p, "p"));
+  STATUS_OK(check_ptr(block_seq, "block_seq"));
+  const int nb = h->N * h->M;
+  for (int b = 0; b < nb; ++b) {
+    if (!(sigma[b] > 0) || !std::isfinite(sigma[b]))
+      return fail(MCR_ERR_ARG, "sigma[%d] = %g must be finite and > 0", b, sigma[b]);
+    if (!(p[b] > 0) || !(p[b] <= 1)) return fail(MCR_ERR_ARG, "p[%d] = %g must be in (0, 1]", b, p[b]);
+  }
+  if (n_iter < 0) return fail(MCR_ERR_ARG, "n_iter = %d must be >= 0", n_iter);
+  for (int k = 0; k < n_iter; ++k)
+    if (block_seq[k] < 0 || block_seq[k] >= nb)
+      return fail(MCR_ERR_ARG, "block_seq[%d] = %d must be in [0, %d)", k, block_seq[k], nb);
+  if (n_iter == 0) return MCR_OK;
+  if (h->dtype == MCR_F32) STATUS_OK(init_work<float>(h));
+  else STATUS_OK(init_work<double>(h));
+  STATUS_OK(ensure_scalars<float>(h));
+  STATUS_OK(ensure_scalars<double>(h));
+  return DISPATCH(spdhg_blocks_impl, h, st, d, alpha, sigma, tau, theta, p, block_seq, n_iter);
 }
 
 mcr_status mcr_objective(mcr_handle* h, const void* x, const void* const* d, double alpha, double* out) {
@@ -1952,6 +2165,31 @@ mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq,
     if (theta) *theta = (s - 1.0) / (s + 1.0);
     if (rate_per_epoch) *rate_per_epoch = (s - 1.0) / (s + 1.0);
   }
+  return MCR_OK;
+}
+
+mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const double* norms_sq, double alpha,
+                                 double* sigma, double* tau, double* theta, double* rate_per_epoch) {
+  if (n_gates < 1) return fail(MCR_ERR_ARG, "n_gates = %d must be >= 1", n_gates);
+  if (n_subsets < 1) return fail(MCR_ERR_ARG, "n_subsets = %d must be >= 1", n_subsets);
+  STATUS_OK(check_ptr(norms_sq, "norms_sq"));
+  STATUS_OK(check_ptr(sigma, "sigma"));
+  if (!(alpha > 0) || !std::isfinite(alpha)) return fail(MCR_ERR_ARG, "alpha must be finite and > 0");
+  const int nb = n_gates * n_subsets;
+  for (int b = 0; b < nb; ++b)
+    if (!(norms_sq[b] > 0) || !std::isfinite(norms_sq[b]))
+      return fail(MCR_ERR_ARG, "norms_sq[%d] = %g must be finite and > 0", b, norms_sq[b]);
+  const double N = n_gates, pr = 1.0 / nb;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) {
+    const double sb = std::sqrt(1.0 + norms_sq[b] / (alpha * N));
+    s = std::max(s, sb);
+    sigma[b] = 2.0 / (N * (sb - 1.0));
+  }
+  const double rho = 1.0 - 2.0 * pr / (1.0 + s);
+  if (tau) *tau = pr / (2.0 * alpha * rho * (1.0 + s));
+  if (theta) *theta = rho;
+  if (rate_per_epoch) *rate_per_epoch = std::pow(rho, nb);
   return MCR_OK;
 }
 

@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_sched(Geo<float> g, const An
 //   bands  : (first line L0, lines BL, window start S0, log2 pitch lp); the
 //            taps of every ray of the block on band line l lie in window
 //            columns [1, 2^lp - 2] after the shift o_l, BL 2^lp <= kShCap
-// grid (n_pieces, 1, G), block 256
+// grid (pieces, 1, G), block 256; piece piece0 + blockIdx.x
 constexpr int kShCap = 2048;  // staged entries per band
 constexpr int kShPieceLines = 128;  // target lines per block
 constexpr int kShBL = 32;     // lines per band at most
@@ -270,13 +270,13 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const An
                                                           const GateScalars<float>* __restrict__ gs,
                                                           const GatePtrs<float>* __restrict__ gp,
                                                           const SlotInfo* __restrict__ slots,
-                                                          float* __restrict__ part, long part_stride) {
+                                                          float* __restrict__ part, long part_stride, int piece0) {
   constexpr int kPer = kShCap / 256;  // staged entries per thread
   __shared__ float2 st[kShCap];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int4 pc = pieces[blockIdx.x];
+  const int4 pc = pieces[piece0 + blockIdx.x];
   const int4 un = units[pc.z];
   const int4 ch = chunks[un.x];
   const long long Bm = (long long)(((unsigned long long)(unsigned)ch.w << 32) | (unsigned)ch.z);
@@ -409,8 +409,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear(Geo<float> g, const An
 }
 
 // Sum of the partial sums of the multi-piece units in piece order, then the
-// projection epilogue. grid (n_multi, 1, G), block 256; multi lists the units
-// with P > 1.
+// projection epilogue. grid (count, 1, G), block 256; multi lists the units
+// with P > 1, this launch handles entries multi0 .. multi0 + count - 1.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, const AngleFx* __restrict__ ang,
                                                                  const int4* __restrict__ chunks,
@@ -420,9 +420,9 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
                                                                  float* __restrict__ out, long out_stride, int gate0,
                                                                  const GateScalars<float>* __restrict__ gs,
                                                                  const GatePtrs<float>* __restrict__ gp,
-                                                                 const SlotInfo* __restrict__ slots) {
+                                                                 const SlotInfo* __restrict__ slots, int multi0) {
   const int tid = threadIdx.x;
-  const int4 un = units[multi[blockIdx.x]];
+  const int4 un = units[multi[multi0 + blockIdx.x]];
   const int4 ch = chunks[un.x];
   const int kk = tid >> 5;
   const int j = un.y * kShJD + (tid & 31);
@@ -462,14 +462,14 @@ constexpr int adj_window() {
   return PX == 8 ? 80 : 64;
 }
 
-// grid (ceil(n/(8*PX)), ceil(n/32), G*S), block 256. With S > 1 block z
+// grid (ceil(n/(8*PX)), ceil(n/32), G*S), block 256; angles [ka, kb). With S > 1 block z
 // handles angle share z % S of gate slot z / S and writes an unpadded partial
 // image to out + (z % S) * part_stride + (z / S) * out_stride (summed later).
 template <int PX>
 __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const AngleFx* __restrict__ ang,
                                                         const float* __restrict__ sino, long sino_stride,
                                                         float* __restrict__ out, long out_stride,
-                                                        int padded, int S, long part_stride) {
+                                                        int padded, int S, long part_stride, int ka, int kb) {
   constexpr int kAdjW = adj_window<PX>();
   constexpr int kAdjUnroll = PX >= 8 ? 1 : 2;  // angles per unrolled step (registers)
   __shared__ float sy[kAdjKC * kAdjW];
@@ -483,7 +483,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
   const int tx = tid & 7, ty = tid >> 3;
   const int R0 = blockIdx.y * 32, C0 = blockIdx.x * (8 * PX);
   const int share = blockIdx.z % S, slot = blockIdx.z / S;
-  const int kbeg = (int)((long)g.na * share / S), kend = (int)((long)g.na * (share + 1) / S);
+  const int kbeg = ka + (int)((long)(kb - ka) * share / S), kend = ka + (int)((long)(kb - ka) * (share + 1) / S);
   const float* s = sino + slot * sino_stride;
   const int nd = g.nd;
   float acc[PX], blk[PX];

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
 // transposed) padded image. Mode 0 writes the sinogram; mode 1 fuses the
 // dual step of Algorithm 1 (ii):
 //   y' = (y + sigma (A_i x - d)) / (1 + sigma N / 2),  dy = y' - y
-// grid (ceil(n_det/256), n_angles, G), block 256
+// grid (ceil(n_det/256), angles, G), block 256; angle k0 + blockIdx.y
 // ---------------------------------------------------------------------------
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_joseph_fwd(Geo<T> g, const AngleT<T>* __restrict__ ang,
@@ -262,9 +262,9 @@ __global__ __launch_bounds__(256) void k_joseph_fwd(Geo<T> g, const AngleT<T>* _
                                                     T* __restrict__ out, long out_stride,
                                                     int gate0, const GateScalars<T>* __restrict__ gs,
                                                     const GatePtrs<T>* __restrict__ gp,
-                                                    const SlotInfo* __restrict__ slots) {
+                                                    const SlotInfo* __restrict__ slots, int k0) {
   __shared__ int s_lo, s_hi;
-  const int k = blockIdx.y;
+  const int k = k0 + blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
   const AngleT<T> A = ang[k];
   const int n = g.n, pitch = g.pitch;
@@ -337,7 +337,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* __restrict__ ang,
                                                     const T* __restrict__ sino, long sino_stride,
                                                     T* __restrict__ out, long out_stride,
-                                                    int padded) {
+                                                    int padded, int ka, int kb) {
   const int c = blockIdx.x * 16 + threadIdx.x;
   const int r = blockIdx.y * 16 + threadIdx.y;
   if (c >= g.n || r >= g.n) return;
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* _
   const T fc = T(c), fr = T(r);
   const int nd = g.nd;
   T acc = T(0), blk = T(0);
-  for (int k = 0; k < g.na; ++k) {
+  for (int k = ka; k < kb; ++k) {
     if ((k & (kLineBlock - 1)) == 0) {  // two-level sum over angles
       acc += blk;
       blk = T(0);
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* _
 // One thread per ray; the lanes of a wave are adjacent bins of one angle and
 // walk the lines together, so the two taps of each line are read along a
 // contiguous run of the padded image (its transpose for column stepping).
-// Modes as in k_joseph_fwd.  grid (ceil(n_det/256), n_angles, G), block 256
+// Modes as in k_joseph_fwd.  grid (ceil(n_det/256), angles, G), block 256; angle k0 + blockIdx.y
 // ---------------------------------------------------------------------------
 template <int MODE>
 __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const AngleFx* __restrict__ ang,
@@ -392,9 +392,9 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const Angle
                                                        float* __restrict__ out, long out_stride, int gate0,
                                                        const GateScalars<float>* __restrict__ gs,
                                                        const GatePtrs<float>* __restrict__ gp,
-                                                       const SlotInfo* __restrict__ slots) {
+                                                       const SlotInfo* __restrict__ slots, int k0) {
   __shared__ int s_lo, s_hi;
-  const int k = blockIdx.y;
+  const int k = k0 + blockIdx.y;
   const int j = blockIdx.x * 256 + threadIdx.x;
   const AngleFx A = ang[k];
   const int n = g.n, pitch = g.pitch;
@@ -490,14 +490,15 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const Angle
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_joseph_adj_fx(Geo<float> g, const AngleFx* __restrict__ ang,
                                                        const float* __restrict__ sino, long sino_stride,
-                                                       float* __restrict__ out, long out_stride, int padded) {
+                                                       float* __restrict__ out, long out_stride, int padded,
+                                                       int ka, int kb) {
   const int c = blockIdx.x * 16 + threadIdx.x;
   const int r = blockIdx.y * 16 + threadIdx.y;
   if (c >= g.n || r >= g.n) return;
   const float* s = sino + blockIdx.z * sino_stride;
   const int nd = g.nd;
   float acc = 0.0f, blk = 0.0f;
-  for (int k = 0; k < g.na; ++k) {
+  for (int k = ka; k < kb; ++k) {
     if ((k & (kLineBlock - 1)) == 0) {
       acc += blk;
       blk = 0.0f;

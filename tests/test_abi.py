@@ -103,3 +103,27 @@ def test_step_sizes_reject_bad_arguments(lib, algo, N, norms, alpha):
     sig = (ctypes.c_double * max(N, 1))()
     assert lib.mcr_step_sizes(algo, N, (ctypes.c_double * len(norms))(*norms), alpha, sig, None, None,
                               None) == _lib.MCR_ERR_ARG
+
+
+@pytest.mark.parametrize("N,M,alpha", [(1, 1, 1e-3), (4, 3, 0.5), (16, 4, 1e-3)])
+def test_block_step_sizes_match_oracle(lib, N, M, alpha):
+    from oracle import subsets
+    rng = np.random.default_rng(N * 10 + M)
+    norms = list(3.7e5 / M * (1 + 0.05 * rng.random(N * M)))
+    nb = N * M
+    sig = (ctypes.c_double * nb)()
+    tau, th, rate = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _lib.check(lib.mcr_step_sizes_blocks(N, M, (ctypes.c_double * nb)(*norms), alpha, sig, ctypes.byref(tau),
+                                         ctypes.byref(th), ctypes.byref(rate)))
+    s_o, t_o, th_o, rho = subsets.step_sizes(norms, alpha, N)
+    np.testing.assert_allclose(list(sig), s_o, rtol=1e-14)
+    assert math.isclose(tau.value, t_o, rel_tol=1e-14) and math.isclose(th.value, th_o, rel_tol=1e-14)
+    assert math.isclose(rate.value, subsets.epoch_rate(norms, alpha, N), rel_tol=1e-12)
+    bad = (ctypes.c_double * nb)(*([0.0] + norms[1:]))
+    assert lib.mcr_step_sizes_blocks(N, M, bad, alpha, sig, None, None, None) == _lib.MCR_ERR_ARG
+    assert lib.mcr_step_sizes_blocks(N, 0, (ctypes.c_double * nb)(*norms), alpha, sig, None, None,
+                                     None) == _lib.MCR_ERR_ARG
+
+
+def test_set_subsets_rejects_null_handle(lib):
+    assert lib.mcr_set_subsets(None, 2) == _lib.MCR_ERR_ARG

@@ -1,0 +1,172 @@
+"""GPU parity of SPDHG over gates x angle subsets (blocks b = gate * M + subset)
+against the FP64 oracle (oracle/subsets.py), through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import F32_OP, Problem, dev, f32, host, need_gpu, rel
+import synth
+from oracle import spdhg as osp, subsets as osub
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _blocks_setup(P, M, norm=None):
+    bops = osub.BlockOperators(P.ops, M)
+    nb = bops.n_blocks
+    norms = [norm or 2.0 * P.na * P.n / M] * nb
+    sig, tau, th, _ = osub.step_sizes(norms, P.alpha, P.N)
+    return bops, sig, tau, th, [1.0 / nb] * nb
+
+
+def _run_gpu(P, M, dtype, sig, tau, th, p, seqs, variant=None):
+    h = P.handle(dtype)
+    if variant is not None:
+        h.set_variant(*variant)
+    h.set_subsets(M)
+    d = [dev(v, dtype) for v in P.d]
+    st = h.zero_state()
+    for sq in seqs:
+        h.spdhg_blocks_iterate(st, d, P.alpha, sig, tau, th, p, sq)
+    return st
+
+
+def _compare(st, ref, bar):
+    assert rel(host(st.x), ref.x) < bar
+    assert rel(host(st.zbar), ref.zbar) < bar
+    yg = np.concatenate([host(v).ravel() for v in st.y])
+    assert rel(yg, np.concatenate([v.ravel() for v in ref.y])) < bar
+
+
+@pytest.mark.parametrize("kind,M", [("rigid", 3), ("field", 4)])
+def test_fp64_block_iterations_match_oracle(kind, M):
+    P = Problem(64, 96, 92, 3, kind, alpha=1e-3)
+    bops, sig, tau, th, p = _blocks_setup(P, M)
+    nb = bops.n_blocks
+    seqs = [synth.gate_sequence(nb, 3, e) for e in range(2)]
+    ref = osp.State.zeros(64, P.N, 96, 92)
+    for sq in seqs:
+        ref = osub.spdhg_blocks(bops, ref, P.d, P.alpha, sig, tau, th, p, sq)
+    st = _run_gpu(P, M, torch.float64, sig, tau, th, p, seqs)
+    _compare(st, ref, 1e-11)
+
+
+# (forward variant, adjoint pixels per thread, angle shares)
+@pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1)])
+def test_fp32_block_iterations_match_oracle(variant):
+    P = Problem(64, 96, 92, 4, "field", alpha=1e-3)
+    M = 3
+    bops, sig, tau, th, p = _blocks_setup(P, M)
+    nb = bops.n_blocks
+    seqs = [synth.gate_sequence(nb, 5, e) for e in range(4)]
+    ref = osp.State.zeros(64, P.N, 96, 92)
+    for sq in seqs:
+        ref = osub.spdhg_blocks(bops, ref, P.d, P.alpha, sig, tau, th, p, sq)
+    try:
+        st = _run_gpu(P, M, torch.float32, sig, tau, th, p, seqs, variant)
+    except Exception as e:  # a variant whose tables do not fit this geometry
+        assert "do not fit" in str(e)
+        return
+    _compare(st, ref, 1e-4)
+
+
+def test_one_subset_block_iterations_equal_gate_iterations():
+    P = Problem(64, 96, 92, 3, "rigid", alpha=1e-3)
+    sig, tau, th, _ = osp.step_sizes_spdhg([2.0 * 96 * 64] * 3, P.alpha, 3)
+    p = [1.0 / 3] * 3
+    seq = [int(g) for g in synth.gate_sequence(3, 1, 0, length=7)]
+    for dtype in (torch.float32, torch.float64):
+        h = P.handle(dtype)
+        d = [dev(v, dtype) for v in P.d]
+        a, b = h.zero_state(), h.zero_state()
+        h.spdhg_iterate(a, d, P.alpha, sig, tau, th, p, seq)
+        h.spdhg_blocks_iterate(b, d, P.alpha, sig, tau, th, p, seq)
+        for u, v in [(a.x, b.x), (a.z, b.z), (a.zbar, b.zbar)] + list(zip(a.y, b.y)):
+            assert torch.equal(u, v)
+
+
+def test_block_norms_match_oracle():
+    P = Problem(48, 60, 70, 2, "field", alpha=1e-3)
+    M = 3
+    bops = osub.BlockOperators(P.ops, M)
+    v0 = f32(synth.random_image(48, 9))
+    h = P.handle(torch.float64)
+    h.set_subsets(M)
+    for b in range(bops.n_blocks):
+        g, s = divmod(b, M)
+        lam, _ = h.block_norm_sq(g, s, dev(v0, torch.float64), max_iter=400, rtol=1e-13)
+        lam_o, _ = osub.block_norm_sq(bops, b, v0, rtol=1e-13, max_iter=400)
+        assert abs(lam - lam_o) <= 1e-9 * lam_o
+
+
+@pytest.mark.parametrize("M", [2, 5])
+def test_full_range_operators_unchanged_by_subsets(M):
+    # the forward's work tables are rebuilt with subset boundaries; the full
+    # operators stay within the parity bar
+    P = Problem(75, 40, 300, 2, "rigid")
+    x = f32(synth.ellipse_phantom(75, 3))
+    y = f32(synth.random_sinograms(1, 40, 300, 5)[0])
+    h = P.handle(torch.float32)
+    h.set_subsets(M)
+    assert rel(host(h.apply_Ai(1, dev(x, torch.float32))), P.ops.A(1, x)) < F32_OP
+    assert rel(host(h.apply_Ai_adjoint(1, dev(y, torch.float32))), P.ops.At(1, y)) < F32_OP
+
+
+def test_subset_arguments():
+    from paper_2410_10503_amd import McrError
+    P = Problem(32, 20, 46, 2, "rigid")
+    h = P.handle(torch.float32)
+    with pytest.raises(McrError):
+        h.set_subsets(0)
+    with pytest.raises(McrError):
+        h.set_subsets(21)
+    h.set_subsets(4)
+    with pytest.raises(McrError):
+        h.block_norm_sq(0, 4, torch.ones(32, 32, dtype=torch.float64, device="cuda"))
+    d = [dev(v, torch.float32) for v in P.d]
+    st = h.zero_state()
+    with pytest.raises(McrError):
+        h.spdhg_blocks_iterate(st, d, P.alpha, [1.0] * 8, 1.0, 1.0, [0.125] * 8, [8])
+    with pytest.raises(ValueError):
+        h.spdhg_blocks_iterate(st, d, P.alpha, [1.0] * 2, 1.0, 1.0, [0.5] * 2, [0])
+
+
+def test_full_size_block_iteration_sampled():
+    # 512^2, 720 x 730, 16 field gates, 4 angle subsets: one block iteration per
+    # subset from zero; the dual rows of the block against the oracle, and the
+    # rows of the other subsets untouched (still zero)
+    wl = synth.WORKLOADS["chest512_field16"]
+    P = Problem(512, 720, 730, 16, "field", phantom="chest", alpha=wl.alpha)
+    M = 4
+    nb = 16 * M
+    norms = [3.7e5 / M] * nb
+    sig, tau, th, _ = osub.step_sizes(norms, P.alpha, 16)
+    p = [1.0 / nb] * nb
+    dn = 50.0 * np.abs(synth.random_sinograms(2, 720, 730, 13, dtype=np.float64))
+    h = P.handle(torch.float32)
+    h.set_subsets(M)
+    bops = osub.BlockOperators(P.ops, M)
+    for b in [5, 3 * M + 2]:
+        g, s = divmod(b, M)
+        d = [dev(f32(dn[k % 2]), torch.float32) for k in range(16)]
+        st = h.zero_state()
+        h.spdhg_blocks_iterate(st, d, P.alpha, sig, tau, th, p, [b])
+        yg = host(st.y[g])
+        rows = bops.rows(s)
+        # from zero state: x = 0, y_b = -sigma d / (1 + sigma N / 2), the other rows stay 0
+        want = -sig[b] * f32(dn[g % 2])[rows] / (1 + sig[b] * 16 / 2)
+        assert rel(yg[rows], want) < 1e-6
+        mask = np.ones(720, bool)
+        mask[rows] = False
+        assert not yg[mask].any()
+        for k in range(16):
+            if k != g:
+                assert not host(st.y[k]).any()
+        # z = A_b^* dy against the oracle's block adjoint
+        dz = bops.At(b, np.where(mask[:, None], 0.0, yg))
+        assert rel(host(st.z), dz) < 1e-5
