@@ -229,6 +229,51 @@ def autograd_measurement(reps: int = 3):
     return out
 
 
+def subsets_measurement(h, d, wl, gate_norms, v0, M: int = 4, epochs: int = 3):
+    """Sampling over gates x angle subsets (the next step named in the
+    Conclusions) on the same handle and data: M contiguous angle subsets,
+    N M blocks, an epoch of N M block iterations (the operator work of one
+    PDHG iteration). Reports epochs/s and the theoretical per-epoch rates
+    l(kappa, N M) against the gate-only l(kappa, N), at the workload's alpha
+    and in the paper's regime (kappa = |A|^2 / alpha = 70)."""
+    import torch
+    import synth
+    from paper_2410_10503_amd import step_sizes_blocks
+    N = h.n_gates
+    h.set_subsets(M)
+    nb = N * M
+    bnorms = [h.block_norm_sq(b // M, b % M, v0, max_iter=15, rtol=1e-5)[0] for b in range(nb)]
+    sig, tau, th, rate_b = step_sizes_blocks(bnorms, wl.alpha, N, M)
+    p = [1.0 / nb] * nb
+    st = h.zero_state()
+
+    def epoch(e):
+        h.spdhg_blocks_iterate(st, d, wl.alpha, sig, tau, th, p, synth.gate_sequence(nb, wl.gate_seed, e))
+
+    epoch(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(epochs):
+        epoch(1 + e)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h.set_subsets(1)
+
+    def l(kappa, n):
+        return (1.0 - 2.0 / (n * (1.0 + math.sqrt(1.0 + kappa)))) ** n
+
+    a70 = max(gate_norms) / 70.0
+    return {
+        "workload": f"{wl.name} with {M} contiguous angle subsets ({nb} blocks), epoch = {nb} block iterations",
+        "epochs_per_s": epochs / el,
+        "block_iterations_per_s": epochs * nb / el,
+        "block_norm_sq_range": [min(bnorms), max(bnorms)],
+        "rate_per_epoch": {"gates": l(max(gate_norms) / (wl.alpha * N), N), "gates_x_subsets": rate_b},
+        "rate_per_epoch_kappa70": {"gates": l(max(gate_norms) / (a70 * N), N),
+                                   "gates_x_subsets": l(max(bnorms) / (a70 * N), nb)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -239,6 +284,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64 x 256^2 measurement")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation measurement")
+    ap.add_argument("--no-subsets", action="store_true", help="skip the gates x angle-subsets measurement")
     ap.add_argument("--variant", default=None,
                     help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
                          "(counter runs serialise dispatches, which would change the autotuner's choice)")
@@ -401,6 +447,10 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = a.numel() * 4
         del a, bcopy
+    if not args.no_subsets:
+        log("gates x angle subsets ...")
+        out["subsets"] = subsets_measurement(h, d, wl, norms, v0)
+        log(f"subsets: {out['subsets']}")
     if not args.no_batch:
         log("batched workload: 64 slices of 256^2 ...")
         out["batched"] = batched_measurement(max(2, args.steps // 3))
