@@ -481,8 +481,13 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
   __shared__ float s_ds[2][kAdjKC];
   const int tid = threadIdx.x;
   const int tx = tid & 7, ty = tid >> 3;
-  const int R0 = blockIdx.y * 32, C0 = blockIdx.x * (8 * PX);
-  const int share = blockIdx.z % S, slot = blockIdx.z / S;
+  // consecutive workgroups go to the 8 XCDs in turn: making the share the
+  // fastest-varying index keeps each share (angle range) on one XCD's L2
+  // when S is 8 (or a divisor of it)
+  const int L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int share = L % S, rest = L / S;
+  const int tiles = gridDim.x * gridDim.y, tile = rest % tiles, slot = rest / tiles;
+  const int R0 = (tile / gridDim.x) * 32, C0 = (tile % gridDim.x) * (8 * PX);
   const int kbeg = ka + (int)((long)(kb - ka) * share / S), kend = ka + (int)((long)(kb - ka) * (share + 1) / S);
   const float* s = sino + slot * sino_stride;
   const int nd = g.nd;
