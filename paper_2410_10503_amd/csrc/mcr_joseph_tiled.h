@@ -1,13 +1,15 @@
 // LDS-tiled float32 Joseph projector pair (gfx950). Same fixed-point geometry
 // as k_joseph_fwd_fx / k_joseph_adj_fx (AngleFx), different work split:
 //
-//  forward  - a block owns KA consecutive angles of one stepping type times JD
-//             detector bins and walks the lines in bands. Each band of the
-//             padded image is staged once in LDS as a sheared window (window
-//             start moves by an integer slope m per line) and read by all
-//             KA x JD rays; the LDS index of a tap is the integer part of the
-//             ray's fixed-point crossing, so a sample costs one 64-bit add, one
-//             conversion, one paired LDS read and two FMAs.
+//  forward  - a block owns consecutive angles of one stepping type times a
+//             tile of detector bins and walks the lines in bands. Each band of
+//             the padded image is staged once in LDS as a window that follows
+//             the rays' slope (k_joseph_fwd_lds / _sched: integer shear per
+//             line; k_joseph_fwd_shear: per-line shift from the chunk's mean
+//             fixed-point slope, host-scheduled pieces) and read by all the
+//             block's rays; the LDS index of a tap is the integer part of the
+//             ray's fixed-point crossing, so a sample costs a 64-bit add, one
+//             conversion, one LDS read and two FMAs.
 //  adjoint  - a block owns a 32-row x 8*PX-column pixel tile and a share of
 //             the angles (S shares in total). Chunks of KC angles of the
 //             sinogram are staged in LDS (bin window per angle, pre-scaled by

@@ -196,6 +196,7 @@ class Workload:
     motion_seed: int = 1
     noise_seed: int = 2
     gate_seed: int = 3
+    kappa: float = 0.0     # > 0: alpha = |A|^2 / kappa (the paper's regime), computed by the caller
 
     def image(self) -> np.ndarray:
         if self.phantom == "chest":
@@ -220,4 +221,10 @@ WORKLOADS = {
     "ellipses512_rigid16": Workload("ellipses512_rigid16", 512, 720, 730, 16, "rigid", 1e-3, 8.0, 10.0),
     # one slice shape of the batched case
     "ellipses256_slice": Workload("ellipses256_slice", 256, 360, 366, 8, "rigid", 1e-3, 8.0, 10.0),
+    # the paper's regime (Section III: kappa = |A|^2 / alpha ~ 70): 20 rigid gates
+    # (stand-in for the walnut) and 10 dilatation gates (stand-in for the chest)
+    "ellipses128_rigid20_k70": Workload("ellipses128_rigid20_k70", 128, 120, 182, 20, "rigid", 0.0, 5.0, 4.0,
+                                        kappa=70.0),
+    "chest128_field10_k70": Workload("chest128_field10_k70", 128, 120, 182, 10, "field", 0.0, phantom="chest",
+                                     kappa=70.0),
 }
