@@ -296,6 +296,7 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  * All variants compute the same weights; results differ only by summation
  * order. mcr_autotune times the variants on this geometry with
  * gates_per_launch gates per launch (1 for SPDHG, N for PDHG), keeps the
+ * first variant, in a fixed order of preference, that is within 3% of the
  * fastest (remembered per geometry for the life of the process) and returns
  * the choice (output pointers may be NULL). Synchronises the stream.
  * ------------------------------------------------------------------------- */

@@ -1972,31 +1972,43 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       Work<float>& w = h->wf;
       const int G = gates_per_launch;
       mcr_handle::Tune best = h->tune;
-      float best_ms = 1e30f, ms = 0.0f;
       mcr_status st = MCR_OK;
-      for (int f = 0; f <= 3 && st == MCR_OK; ++f) {
+      // each variant is timed; the first one (in the order below) within 3%
+      // of the fastest is kept, so that near-ties resolve the same way run to run
+      auto pick = [](const std::vector<float>& t) {
+        const float lo = *std::min_element(t.begin(), t.end());
+        for (size_t i = 0; i < t.size(); ++i)
+          if (t[i] <= 1.03f * lo) return (int)i;
+        return 0;
+      };
+      std::vector<int> fv;
+      std::vector<float> ft;
+      for (int f = 3; f >= 0 && st == MCR_OK; --f) {  // preferred: the newest kernel
         if (!fwd_variant_ok(h, f)) continue;
         h->tune.fwd = f;
+        float ms = 0.0f;
         st = time_launches(h, [&] { return launch_project<float, 0>(h, 0, G, w.dy, h->sino); }, 5, &ms);
-        if (st == MCR_OK && ms < best_ms) {
-          best_ms = ms;
-          best.fwd = f;
-        }
+        fv.push_back(f);
+        ft.push_back(st == MCR_OK ? ms : 1e30f);
       }
+      if (st == MCR_OK && !fv.empty()) best.fwd = fv[pick(ft)];
       h->tune.fwd = best.fwd;
-      const int cand[][2] = {{0, 1}, {1, 1}, {2, 1}, {2, 2}, {4, 1}, {4, 2}, {4, 4}, {4, 6}, {4, 8}, {8, 4}, {8, 8}};
-      best_ms = 1e30f;
+      const int cand[][2] = {{8, 6}, {8, 8}, {8, 4}, {4, 4}, {4, 6}, {4, 8}, {4, 2}, {4, 1},
+                             {2, 2}, {2, 1}, {1, 1}, {0, 1}};
+      std::vector<float> at;
       for (const auto& c : cand) {
         if (st != MCR_OK) break;
         h->tune.adj_px = c[0];
         h->tune.adj_s = c[1];
+        float ms = 0.0f;
         st = time_launches(h, [&] { return launch_backproject<float>(h, G, w.dy, h->sino, w.bP, h->padded, 1); }, 5,
                            &ms);
-        if (st == MCR_OK && ms < best_ms) {
-          best_ms = ms;
-          best.adj_px = c[0];
-          best.adj_s = c[1];
-        }
+        at.push_back(st == MCR_OK ? ms : 1e30f);
+      }
+      if (st == MCR_OK) {
+        const int a = pick(at);
+        best.adj_px = cand[a][0];
+        best.adj_s = cand[a][1];
       }
       h->prof = prof;
       h->tune = best;
