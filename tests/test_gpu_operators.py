@@ -209,3 +209,35 @@ def test_argument_errors():
         h.spdhg_iterate(st, d, 1.0, [float("nan"), 1.0], 1.0, 0.5, [0.5, 0.5], [0])
     with pytest.raises(McrError, match="alpha"):
         h.pdhg_epoch(st, d, -1.0, [1.0, 1.0], 1.0, 0.5)
+
+
+@pytest.mark.parametrize("geom", [(1024, 1440, 1450), (300, 97, 120), (257, 512, 700)])
+def test_large_and_odd_geometries_sampled(geom):
+    # a 1024^2 image with 1440 angles (four times the headline's pixels), a
+    # detector narrower than the image with an odd angle count (no 45/135
+    # degree ties), and a wide detector on an odd image size: sampled rays of
+    # A x and sampled pixels of A^T y against the oracle, one by one, for every
+    # float32 forward variant that fits and the default adjoint
+    from paper_2410_10503_amd import McrError
+    n, na, nd = geom
+    P = Problem(n, na, nd, 1, "identity")
+    h = P.handle(torch.float32)
+    x = f32(synth.ellipse_phantom(n, 3))
+    y = f32(synth.random_sinograms(1, na, nd, 5)[0])
+    rng = np.random.default_rng(n)
+    rays = [(int(rng.integers(na)), int(rng.integers(nd))) for _ in range(16)]
+    pix = [(int(rng.integers(n)), int(rng.integers(n))) for _ in range(2)]
+    refs = [projector.ray_sum(x, na, nd, k, j) for k, j in rays]
+    b = host(h.backproject(dev(y, torch.float32)))
+    for r, c in pix:
+        ref = projector.backproject_pixel(y, n, r, c)
+        assert abs(b[r, c] - ref) <= 1e-5 * np.abs(b).max()
+    for fwd in (0, 1, 2, 3):
+        try:
+            h.set_variant(fwd, 8, 6)
+        except McrError as e:
+            assert "do not fit" in str(e)
+            continue
+        s = host(h.project(dev(x, torch.float32)))
+        for (k, j), ref in zip(rays, refs):
+            assert abs(s[k, j] - ref) <= 1e-5 * np.abs(s).max(), (fwd, k, j, s[k, j], ref)
