@@ -508,6 +508,30 @@ def main():
     pair_s = (time.perf_counter() - t0) / args.pairs
     log(f"pairs: {1e6 * pair_s:.1f} us per A_i + A_i^* pair")
 
+    # the same epochs through the batched path with one slice: the epoch's
+    # launch sequence captured once as a HIP graph and replayed, and plain
+    from paper_2410_10503_amd import BatchHandle
+    bh = BatchHandle(n, na, nd, [N], motion, dtype=torch.float32, device=dev)
+    bh.set_variant(variant["fwd"], variant["adj_px"], variant["adj_shares"])
+    db = torch.stack(d)
+    graph_eps = {}
+    for use_graph in (True, False):
+        stb = bh.zero_batch_state()
+        run = lambda e: bh.batch_spdhg_epoch(stb, db, [wl.alpha], sigma, [tau], [theta], p,  # noqa: E731
+                                             [int(g) for g in synth.gate_sequence(N, wl.gate_seed, e)],
+                                             use_graph=use_graph)
+        for e in range(args.warmup):
+            run(e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in range(args.steps):
+            run(args.warmup + e)
+        torch.cuda.synchronize()
+        graph_eps["graph" if use_graph else "plain"] = args.steps / (time.perf_counter() - t0)
+    bh.close()
+    del db
+    log(f"one-slice batched path: {graph_eps}")
+
     # roofline of the dominant kernel (per launch)
     nnz = joseph_nnz(n, na, nd)
     img_b, sino_b = 4 * n * n, 4 * na * nd
@@ -552,6 +576,7 @@ def main():
         "ms_per_step_with_kernel_events": prof_ms,
         "kernels_us_per_launch": {k: (v[0] * 1e3 / v[1] if v[1] else None) for k, v in kstats.items()},
         "projector_variant": variant,
+        "epochs_per_s_one_slice_batched": graph_eps,
         "roofline": roof,
         "cpu_baseline": None,
     }
