@@ -550,6 +550,10 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": bytes_ / avg_s / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
+    if roof["bound"] == "alu":
+        # the library is built without packed FP32 (one FMA per lane per cycle)
+        roof["peak_without_packed_fp32"] = PEAK_FP32_TFLOPS / 2
+        roof["frac_without_packed_fp32"] = roof["achieved"] / (PEAK_FP32_TFLOPS / 2)
     roof["traffic"] = measured_traffic(dom, variant)
     roof["kernel"] = dom
     roof["avg_launch_us"] = avg_s * 1e6
