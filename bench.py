@@ -559,6 +559,8 @@ def main():
     roof["avg_launch_us"] = avg_s * 1e6
     roof["hbm_gbs_algorithmic"] = bytes_ / avg_s / 1e9
     roof["nnz_per_launch"] = nnz
+    if dom in ("project", "backproject"):
+        roof["weights_per_s"] = nnz / avg_s   # interpolation weights applied per second
 
     out = {
         "metric": METRIC,
