@@ -90,10 +90,17 @@ def cpu_baseline(wl, x_true, fields_or_params):
     t0 = time.perf_counter()
     spdhg.iterate(ops, st, d, wl.alpha, [1e-3] * N, 1.0, 0.9, [1.0 / N] * N, [N - 1])
     dt = time.perf_counter() - t0
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": 1.0 / (N * dt), "unit": "SPDHG epochs/s", "cores": 1, "kind": "oracle",
             "sample": f"one SPDHG iteration (gate {N - 1}: warp, projection, dual step, backprojection, "
                       f"transposed warp, updates) at {wl.n}^2, {wl.n_angles}x{wl.n_det}, FP64 NumPy, "
-                      f"{dt:.1f} s, scaled by 1/N"}
+                      f"{dt:.1f} s, scaled by 1/N",
+            "host_cpus": os.cpu_count(), "cpu_model": cpu}
 
 
 def batched_measurement(steps: int, seed: int = 4):
@@ -499,14 +506,18 @@ def main():
         h.apply_Ai(i, xs, s)
         h.apply_Ai_adjoint(i, s, b)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.pairs):
-        i = k % N
-        h.apply_Ai(i, xs, s)
-        h.apply_Ai_adjoint(i, s, b)
-    torch.cuda.synchronize()
-    pair_s = (time.perf_counter() - t0) / args.pairs
-    log(f"pairs: {1e6 * pair_s:.1f} us per A_i + A_i^* pair")
+    runs = []
+    for _ in range(5):   # median of 5 runs of `pairs` pairs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.pairs):
+            i = k % N
+            h.apply_Ai(i, xs, s)
+            h.apply_Ai_adjoint(i, s, b)
+        torch.cuda.synchronize()
+        runs.append((time.perf_counter() - t0) / args.pairs)
+    pair_s = float(np.median(runs))
+    log(f"pairs: {1e6 * pair_s:.1f} us per A_i + A_i^* pair (median of 5 runs of {args.pairs})")
 
     # the same epochs through the batched path with one slice: the epoch's
     # launch sequence captured once as a HIP graph and replayed, and plain
