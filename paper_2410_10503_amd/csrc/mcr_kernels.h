@@ -122,6 +122,19 @@ struct Tap {
   T fx, fy;
 };
 
+// The bilinear tap of the sample taken for pixel (r, c) at displacement (dx, dy).
+template <typename T>
+__device__ __forceinline__ Tap<T> tap_from_displacement(T dx, T dy, int r, int c) {
+  const T fdx = floor(dx), fdy = floor(dy);
+  Tap<T> t;
+  t.fx = dx - fdx;
+  t.fy = dy - fdy;
+  // far-away samples only need to stay far away; clamp keeps the int cast finite
+  t.c0 = c + (int)fmax(fmin(fdx, T(16384)), T(-16384));
+  t.r0 = r + (int)fmax(fmin(fdy, T(16384)), T(-16384));
+  return t;
+}
+
 template <typename T>
 __device__ __forceinline__ Tap<T> motion_tap(const GateMotion<T>& M, const float* __restrict__ ux,
                                              const float* __restrict__ uy, int pitch, T hc, int r,
@@ -136,14 +149,7 @@ __device__ __forceinline__ Tap<T> motion_tap(const GateMotion<T>& M, const float
     dx = T(ux[o]);
     dy = T(uy[o]);
   }
-  const T fdx = floor(dx), fdy = floor(dy);
-  Tap<T> t;
-  t.fx = dx - fdx;
-  t.fy = dy - fdy;
-  // far-away samples only need to stay far away; clamp keeps the int cast finite
-  t.c0 = c + (int)fmax(fmin(fdx, T(16384)), T(-16384));
-  t.r0 = r + (int)fmax(fmin(fdy, T(16384)), T(-16384));
-  return t;
+  return tap_from_displacement<T>(dx, dy, r, c);
 }
 
 // Centre of the gather window of output pixel (qr, qc) for the transposed
@@ -228,11 +234,16 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
         const T w10 = (T(1) - fx) * fy, w11 = fx * fy;
         const bool cin0 = (unsigned)c0 < (unsigned)n, cin1 = (unsigned)(c0 + 1) < (unsigned)n;
         const bool rin0 = (unsigned)r0 < (unsigned)n, rin1 = (unsigned)(r0 + 1) < (unsigned)n;
+        // the four loads are unconditional (indices clamped into the image) so
+        // that they are in flight together; taps outside the image weigh 0
+        const long ra = (long)min(max(r0, 0), n - 1) * n, rb = (long)min(max(r0 + 1, 0), n - 1) * n;
+        const int ca = min(max(c0, 0), n - 1), cb = min(max(c0 + 1, 0), n - 1);
+        const T v00 = src[ra + ca], v01 = src[ra + cb], v10 = src[rb + ca], v11 = src[rb + cb];
         T acc = T(0);
-        if (rin0 && cin0) acc = fmaT(w00, src[(long)r0 * n + c0], acc);
-        if (rin0 && cin1) acc = fmaT(w01, src[(long)r0 * n + c0 + 1], acc);
-        if (rin1 && cin0) acc = fmaT(w10, src[(long)(r0 + 1) * n + c0], acc);
-        if (rin1 && cin1) acc = fmaT(w11, src[(long)(r0 + 1) * n + c0 + 1], acc);
+        acc = fmaT((rin0 && cin0) ? w00 : T(0), v00, acc);
+        acc = fmaT((rin0 && cin1) ? w01 : T(0), v01, acc);
+        acc = fmaT((rin1 && cin0) ? w10 : T(0), v10, acc);
+        acc = fmaT((rin1 && cin1) ? w11 : T(0), v11, acc);
         v = acc;
       }
       dst[(long)r * pitch + c] = v;
@@ -587,20 +598,38 @@ __global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __
     if (M.kind == 0) {
       part = b[(long)qr * pitch + qc];
     } else {
-      const float* ux = field + gate * field_stride + origin;
-      const float* uy = ux + plane_stride;
+      // every load of the window is issued before any is used: the values of
+      // b, and for a field the displacements, of the (2R+1)^2 candidates
+      constexpr int K = (2 * R + 1) * (2 * R + 1);
       int cr, cc;
       window_centre(M, centres, gate, n, g.hc, qr, qc, cr, cc);
+      const long o0 = (long)cr * pitch + cc;
+      T bv[K], dxv[K], dyv[K];
 #pragma unroll
-      for (int ddy = -R; ddy <= R; ++ddy) {
+      for (int t = 0; t < K; ++t) bv[t] = b[o0 + (long)(t / (2 * R + 1) - R) * pitch + (t % (2 * R + 1) - R)];
+      if (M.kind == 2) {
+        const float* ux = field + gate * field_stride + origin;
+        const float* uy = ux + plane_stride;
 #pragma unroll
-        for (int ddx = -R; ddx <= R; ++ddx) {
-          const int pr = cr + ddy, pc = cc + ddx;
-          const Tap<T> tp = motion_tap(M, ux, uy, pitch, g.hc, pr, pc);
-          const T wx = (qc == tp.c0) ? (T(1) - tp.fx) : ((qc == tp.c0 + 1) ? tp.fx : T(0));
-          const T wy = (qr == tp.r0) ? (T(1) - tp.fy) : ((qr == tp.r0 + 1) ? tp.fy : T(0));
-          part = fmaT(wx * wy, b[(long)pr * pitch + pc], part);
+        for (int t = 0; t < K; ++t) {
+          const long o = o0 + (long)(t / (2 * R + 1) - R) * pitch + (t % (2 * R + 1) - R);
+          dxv[t] = T(ux[o]);
+          dyv[t] = T(uy[o]);
         }
+      } else {
+#pragma unroll
+        for (int t = 0; t < K; ++t) {
+          const T xc = T(cc + t % (2 * R + 1) - R) - g.hc, yc = T(cr + t / (2 * R + 1) - R) - g.hc;
+          dxv[t] = fmaT(M.cm1, xc, fmaT(-M.sn, yc, M.tx));
+          dyv[t] = fmaT(M.sn, xc, fmaT(M.cm1, yc, M.ty));
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < K; ++t) {
+        const Tap<T> tp = tap_from_displacement<T>(dxv[t], dyv[t], cr + t / (2 * R + 1) - R, cc + t % (2 * R + 1) - R);
+        const T wx = (qc == tp.c0) ? (T(1) - tp.fx) : ((qc == tp.c0 + 1) ? tp.fx : T(0));
+        const T wy = (qr == tp.r0) ? (T(1) - tp.fy) : ((qr == tp.r0 + 1) ? tp.fy : T(0));
+        part = fmaT(wx * wy, bv[t], part);
       }
     }
     dz += part;
