@@ -633,8 +633,13 @@ __global__ __launch_bounds__(256) void k_sum_parts(int n, int pitch, int S, cons
   if (c >= n || r >= n) return;
   const long q = (long)r * n + c;
   const float* src = parts + blockIdx.z * slot_stride;
+  // all S loads in flight together (S <= 8), then the sum in share order
+  float a[8];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) a[s] = s < S ? src[s * part_stride + q] : 0.0f;
   float v = 0.0f;
-  for (int s = 0; s < S; ++s) v += src[s * part_stride + q];
+#pragma unroll
+  for (int s = 0; s < 8; ++s) v += a[s];
   if (padded)
     out[blockIdx.z * out_stride + (long)(r + kPad) * pitch + c + kPad] = v;
   else
