@@ -509,7 +509,6 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
     for (int t = 0; t < ntiles; ++t) {
       const int u = c * ntiles + t;
       const int2 bl = S.blocks[u];
-      const int first_piece = (int)S.pieces.size();
       int b0 = bl.x, lines = 0, pc = 0;
       for (int b = bl.x; b < bl.x + bl.y; ++b) {
         if (b > b0 && lines + S.bands[b].y > kShPieceLines) {
@@ -523,7 +522,6 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
       if (pc > 1) S.multi.push_back((int)S.units.size());
       S.units.push_back(make_int4(c, t, pc, (int)S.part_floats));
       if (pc > 1) S.part_floats += (long)pc * 512;
-      (void)first_piece;
     }
   }
   // pieces and multi-piece units come in chunk order, so each subset's are contiguous
