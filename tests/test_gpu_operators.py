@@ -241,3 +241,29 @@ def test_large_and_odd_geometries_sampled(geom):
         s = host(h.project(dev(x, torch.float32)))
         for (k, j), ref in zip(rays, refs):
             assert abs(s[k, j] - ref) <= 1e-5 * np.abs(s).max(), (fwd, k, j, s[k, j], ref)
+
+
+@pytest.mark.parametrize("geom", [(1, 1, 1), (2, 3, 1), (3, 1, 5), (5, 4, 2), (2, 8, 7), (7, 2, 40)])
+def test_degenerate_geometries(geom):
+    # one pixel, one angle, one detector bin, and detectors far wider or
+    # narrower than the image: every variant against the oracle
+    from paper_2410_10503_amd import McrError
+    n, na, nd = geom
+    x = np.arange(n * n, dtype=np.float64).reshape(n, n) + 1.0
+    y = np.arange(na * nd, dtype=np.float64).reshape(na, nd) + 0.5
+    s_ref, b_ref = projector.forward(x, na, nd), projector.adjoint(y, n)
+    for dtype, bar in DT:
+        P = Problem(n, na, nd, 1, "identity")
+        h = P.handle(dtype)
+        variants = [None] if dtype == torch.float64 else [(0, 0, 1), (1, 1, 1), (2, 2, 2), (3, 4, 1), (3, 8, 3)]
+        for v in variants:
+            if v is not None:
+                try:
+                    h.set_variant(*v)
+                except McrError as e:
+                    assert "do not fit" in str(e)
+                    continue
+            s = host(h.project(dev(x, dtype)))
+            b = host(h.backproject(dev(y, dtype)))
+            assert np.abs(s - s_ref).max() <= bar * max(np.abs(s_ref).max(), 1.0), (v, s, s_ref)
+            assert np.abs(b - b_ref).max() <= bar * max(np.abs(b_ref).max(), 1.0), (v, b, b_ref)
