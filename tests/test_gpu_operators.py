@@ -267,3 +267,22 @@ def test_degenerate_geometries(geom):
             b = host(h.backproject(dev(y, dtype)))
             assert np.abs(s - s_ref).max() <= bar * max(np.abs(s_ref).max(), 1.0), (v, s, s_ref)
             assert np.abs(b - b_ref).max() <= bar * max(np.abs(b_ref).max(), 1.0), (v, b, b_ref)
+
+
+def test_maximum_image_size_sampled():
+    # n = 4096, the largest image the library accepts (few angles keep it
+    # cheap): sampled rays of A x and one pixel of A^T y against the oracle
+    n, na, nd = 4096, 48, 5800
+    P = Problem(n, na, nd, 1, "identity")
+    h = P.handle(torch.float32)
+    x = f32(synth.ellipse_phantom(n, 3))
+    y = f32(synth.random_sinograms(1, na, nd, 5)[0])
+    s = host(h.project(dev(x, torch.float32)))
+    rng = np.random.default_rng(4096)
+    for _ in range(8):
+        k, j = int(rng.integers(na)), int(rng.integers(nd))
+        ref = projector.ray_sum(x, na, nd, k, j)
+        assert abs(s[k, j] - ref) <= 1e-5 * np.abs(s).max(), (k, j, s[k, j], ref)
+    b = host(h.backproject(dev(y, torch.float32)))
+    ref = projector.backproject_pixel(y, n, 1000, 2000)
+    assert abs(b[1000, 2000] - ref) <= 1e-5 * np.abs(b).max()
