@@ -291,8 +291,13 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           the chunk's mean ray slope (up to 16 angles x 32 bins, two rays
  *           per thread; the default where it applies);
  * adjoint:  adj_px = 0 one thread per pixel, or 1, 2, 4, 8 pixels per thread with
- *           LDS-staged sinogram chunks, the angles split into adj_s (1..8)
- *           shares whose partial images are summed in a fixed order.
+ *           LDS-staged sinogram chunks, the angles split into adj_s (1..16)
+ *           shares whose partial images are summed in a fixed order;
+ *           adj_px = -2, -4, -8: the quarter-turn kernel with 2, 4, 8 pixels
+ *           per thread (one detector coordinate serves a pixel of the top-left
+ *           quadrant at angle k and its three quarter turns at angles k and
+ *           k +- n_angles/2; needs an even n and n_angles and a launch over
+ *           all angles, else the tiled kernel with -adj_px pixels runs).
  * All variants compute the same weights; results differ only by summation
  * order. mcr_autotune times the variants on this geometry with
  * gates_per_launch gates per launch (1 for SPDHG, N for PDHG), keeps the

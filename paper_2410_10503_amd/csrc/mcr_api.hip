@@ -56,7 +56,7 @@ mcr_status fail(mcr_status s, const char* fmt, ...) {
 inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 constexpr int kFwdKA = 8, kFwdJD = 32, kFwdWL = 128;  // tiled forward: angles, bins, LDS row
-constexpr int kMaxShares = 8;                          // tiled adjoint: angle shares
+constexpr int kMaxShares = 16;                          // tiled adjoint: angle shares
 
 
 // Per-precision workspace and tables.
@@ -642,6 +642,13 @@ mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
   return MCR_OK;
 }
 
+// The quarter-turn adjoint pairs angle k with angle k +- n_angles/2 and a
+// pixel with its quarter turns: it needs an even image size, an even number
+// of angles, and all of them in the launch.
+bool quad_ok(const mcr_handle* h, int ka, int kb) {
+  return h->geo.n % 2 == 0 && h->geo.n_angles % 2 == 0 && ka == 0 && kb == h->geo.n_angles;
+}
+
 void subset_range(const mcr_handle* h, int subset, int& ka, int& kb) {
   if (subset < 0) {
     ka = 0;
@@ -752,6 +759,7 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
 
 // Angles of subset `subset` (-1: all angles).
 void subset_range(const mcr_handle* h, int subset, int& ka, int& kb);
+bool quad_ok(const mcr_handle* h, int ka, int kb);
 
 template <typename T, int MODE>
 mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stride,
@@ -812,8 +820,32 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
   subset_range(h, subset, ka, kb);
   dim3 grid(cdiv(n, 16), cdiv(n, 16), G), block(16, 16);
   if constexpr (std::is_same<T, float>::value) {
-    const int px = h->tune.adj_px, S = px > 0 ? h->tune.adj_s : 1;
-    if (px > 0) {
+    // adj_px < 0: the quarter-turn kernel where the geometry allows it (even
+    // n and n_angles, all angles), else the tiled kernel with -adj_px pixels
+    const bool quad = h->tune.adj_px < 0 && quad_ok(h, ka, kb);
+    const int px = std::abs(h->tune.adj_px), S = px > 0 ? h->tune.adj_s : 1;
+    if (quad) {
+      const long n2 = (long)n * n;
+      float* dst = S > 1 ? h->parts : out;
+      const long dst_stride = S > 1 ? n2 : out_stride;
+      const long part_stride = n2 * h->nslots;
+      dim3 gq(cdiv(n / 2, 8 * px), cdiv(n / 2, 32), G * S);
+#define ADJQ(PX)                                                                                           \
+  hipLaunchKernelGGL(k_joseph_adj_quad<PX>, gq, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx, sino, \
+                     sino_stride, dst, dst_stride, padded, S, part_stride)
+      if (px == 2)
+        ADJQ(2);
+      else if (px == 4)
+        ADJQ(4);
+      else
+        ADJQ(8);
+#undef ADJQ
+      LAUNCH_OK();
+      if (S > 1) {
+        hipLaunchKernelGGL(k_sum_parts, grid, block, 0, h->stream, n, h->pitch, S, h->parts, part_stride, n2,
+                           out, out_stride, padded);
+      }
+    } else if (px > 0) {
       const long n2 = (long)n * n;
       // S > 1: partial images per angle share, then a fixed-order sum
       float* dst = S > 1 ? h->parts : out;
@@ -1991,8 +2023,10 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       }
       if (st == MCR_OK && !fv.empty()) best.fwd = fv[pick(ft)];
       h->tune.fwd = best.fwd;
-      const int cand[][2] = {{8, 6}, {8, 8}, {8, 4}, {4, 4}, {4, 6}, {4, 8}, {4, 2}, {4, 1},
-                             {2, 2}, {2, 1}, {1, 1}, {0, 1}};
+      // quarter-turn kernels first (tiled ones where the geometry has no
+      // quarter-turn symmetry: they then run as their tiled counterparts)
+      const int cand[][2] = {{-4, 8}, {-4, 12}, {-4, 16}, {-8, 16}, {-2, 8}, {8, 6}, {8, 8}, {8, 4}, {4, 4},
+                             {4, 6}, {4, 8}, {4, 2}, {4, 1}, {2, 2}, {2, 1}, {1, 1}, {0, 1}};
       std::vector<float> at;
       for (const auto& c : cand) {
         if (st != MCR_OK) break;
@@ -2026,8 +2060,9 @@ mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t a
   if (fwd < 0 || fwd > 3) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1, 2 or 3", fwd);
   if (h->dtype == MCR_F32 && !fwd_variant_ok(h, fwd))
     return fail(MCR_ERR_STATE, "the tiled forward's band windows do not fit this geometry");
-  if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4 && adj_px != 8)
-    return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2, 4 or 8", adj_px);
+  if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4 && adj_px != 8 && adj_px != -2 && adj_px != -4 &&
+      adj_px != -8)
+    return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2, 4, 8, -2, -4 or -8", adj_px);
   if (adj_s < 1 || adj_s > kMaxShares) return fail(MCR_ERR_ARG, "angle shares %d must be in [1, %d]", adj_s, kMaxShares);
   h->tune.fwd = fwd;
   h->tune.adj_px = adj_px;

@@ -623,6 +623,212 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
   }
 }
 
+// Quarter-turn backprojection. With x = c - hc, y = r - hc and an even number
+// of angles spread over [0, pi), angle k + na/2 is angle k turned by pi/2, and
+// the quarter turn of the image R: (r, c) -> (c, n - 1 - r) keeps the detector
+// coordinate: U(R p, theta + pi/2) = U(p, theta). A half turn of the angle
+// (theta + pi, outside [0, pi)) is angle theta with the detector reversed,
+// U -> (n_det - 1) - U. The hat weights depend on |a| only, which is the same
+// for angle k and angle k +- na/2. So for a pixel p of the top-left quadrant
+// (n even) and any angle k, one detector coordinate and one pair of weights
+// serve four (pixel, angle) pairs:
+//   p      at k                                (bins as they are)
+//   R p    at k + na/2, or k - na/2 reversed
+//   R^2 p  at k, reversed
+//   R^3 p  at k + na/2 reversed, or k - na/2
+// and the four quadrants' pixels get every angle exactly once. The four rows
+// of angle k's chunk entry are staged interleaved (one float4 per bin), the
+// reversed ones read backwards from the mirrored window, so that the bin index
+// and the weights are shared. Per four pairs: a 64-bit add, one conversion,
+// two clamped FMAs for the weights, two 16-byte LDS reads and eight FMAs.
+//
+// A thread accumulates PX pixels of a row 8 columns apart (columns C0 + tx +
+// 8p), so that the eight lanes of a row read neighbouring 16-byte entries
+// (distinct LDS banks) rather than entries PX bins apart.
+// grid (ceil(n/2/(8*PX)), ceil(n/2/32), G*S), block 256; all angles. S > 1:
+// partial images as in k_joseph_adj_lds.
+constexpr int kQuadKC = 16;  // angles per staged chunk
+
+// Bins staged per angle: a 32 x 8PX tile projects onto at most
+// sqrt(31^2 + (8PX - 1)^2) bins (< 44 for PX = 4), and the window needs 3 more.
+template <int PX>
+constexpr int quad_window() {
+  return PX == 8 ? 80 : 48;
+}
+
+template <int PX>
+__global__ __launch_bounds__(256) void k_joseph_adj_quad(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                         const float* __restrict__ sino, long sino_stride,
+                                                         float* __restrict__ out, long out_stride, int padded,
+                                                         int S, long part_stride) {
+  constexpr int kW = quad_window<PX>();
+  constexpr int KC = kQuadKC;
+  constexpr int kPer = KC * kW / 256;  // staged entries per thread
+  static_assert(KC * kW % 256 == 0, "whole entries per thread");
+  __shared__ float4 sy[KC * kW];
+  __shared__ long long s_row[KC][32];
+  __shared__ long long s_col[KC][8];
+  __shared__ long long s_step[KC];
+  __shared__ float4 s_w[KC];
+  __shared__ int s_jb[2][KC];
+  __shared__ float s_ds[2][KC];
+  const int tid = threadIdx.x;
+  const int tx = tid & 7, ty = tid >> 3;
+  const int L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const int share = L % S, rest = L / S;
+  const int tiles = gridDim.x * gridDim.y, tile = rest % tiles, slot = rest / tiles;
+  const int R0 = (tile / gridDim.x) * 32, C0 = (tile % gridDim.x) * (8 * PX);
+  const int na = g.na, H = na >> 1, nd = g.nd;
+  const int kbeg = (int)((long)na * share / S), kend = (int)((long)na * (share + 1) / S);
+  const float* s = sino + slot * sino_stride;
+  float acc[4][PX], blk[4][PX];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int p = 0; p < PX; ++p) acc[m][p] = blk[m][p] = 0.0f;
+  auto window = [&](int k0, int kcn, int& jb, float& ds) {
+    if (tid < kcn) {
+      const AngleFx A = ang[k0 + tid];
+      const int pmin = A.rows ? C0 : R0, lmin = A.rows ? R0 : C0;
+      const int pext = A.rows ? 8 * PX - 1 : 31, lext = A.rows ? 31 : 8 * PX - 1;
+      const long long u00 = A.U0 + (long long)pmin * A.P + (long long)lmin * A.Q;
+      const long long up = (long long)pext * A.P, ul = (long long)lext * A.Q;
+      const long long umin = min(min(u00, u00 + up), min(u00 + ul, u00 + up + ul));
+      jb = (int)(umin >> 32) - 1;
+      ds = A.ds;
+    }
+  };
+  // the four rows of a chunk's entries: angle k forwards and backwards, angle
+  // k +- na/2 forwards and backwards (zero off the detector)
+  float4 pre[kPer];
+  auto fetch = [&](int k0, int kcn, const int* jbs) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int i = tid + e * 256;
+      const int kc = i / kW, q = i % kW;
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (kc < kcn) {
+        const int k = k0 + kc;
+        const int k2 = k < H ? k + H : k - H;
+        const int ju = jbs[kc] + q, jr = nd - 1 - ju;
+        if ((unsigned)ju < (unsigned)nd) {
+          const float* r1 = s + (long)k * nd;
+          const float* r2 = s + (long)k2 * nd;
+          const float f2 = r2[ju], b2 = r2[jr];
+          v.x = r1[ju];
+          v.z = r1[jr];
+          v.y = k < H ? f2 : b2;
+          v.w = k < H ? b2 : f2;
+        }
+      }
+      pre[e] = v;
+    }
+  };
+  int jb = 0;
+  float ds = 0.0f;
+  window(kbeg, min(KC, kend - kbeg), jb, ds);
+  if (tid < KC) {
+    s_jb[0][tid] = jb;
+    s_ds[0][tid] = ds;
+  }
+  __syncthreads();
+  if (kbeg < kend) fetch(kbeg, min(KC, kend - kbeg), s_jb[0]);
+  int cur = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += KC, cur ^= 1) {
+    const int kcn = min(KC, kend - k0);
+    const int k1 = k0 + KC;
+    const int kcn1 = min(KC, kend - k1);
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int i = tid + e * 256;
+      const int kc = i / kW;
+      const float sc = kc < kcn ? s_ds[cur][kc] : 0.0f;
+      sy[i] = make_float4(pre[e].x * sc, pre[e].y * sc, pre[e].z * sc, pre[e].w * sc);
+    }
+    for (int i = tid; i < kcn * 40; i += 256) {
+      const int kc = i / 40, e = i % 40;
+      const AngleFx A = ang[k0 + kc];
+      const long long sc = A.rows ? A.P : A.Q;  // along a row (column step)
+      const long long sr = A.rows ? A.Q : A.P;  // along a column (row step)
+      if (e < 32) {
+        const int pmin = A.rows ? C0 : R0, lmin = A.rows ? R0 : C0;
+        const long long base = A.U0 + (long long)pmin * A.P + (long long)lmin * A.Q -
+                               ((long long)s_jb[cur][kc] << 32) + ((long long)(kc * kW) << 32);
+        s_row[kc][e] = base + (long long)e * sr;
+      } else {
+        s_col[kc][e - 32] = (long long)(e - 32) * sc;
+        if (e == 32) {
+          s_step[kc] = 8 * sc;
+          s_w[kc] = make_float4(A.na32, A.pa32, A.oma, 0.0f);
+        }
+      }
+    }
+    if (k1 < kend) {
+      window(k1, kcn1, jb, ds);
+      if (tid < KC) {
+        s_jb[cur ^ 1][tid] = jb;
+        s_ds[cur ^ 1][tid] = ds;
+      }
+    }
+    __syncthreads();
+    if (k1 < kend) fetch(k1, kcn1, s_jb[cur ^ 1]);
+#pragma unroll 2
+    for (int kc = 0; kc < kcn; ++kc) {
+      const float4 wc = s_w[kc];
+      const float na32 = wc.x, pa32 = wc.y, oma = wc.z;
+      const long long st = s_step[kc];
+      long long u = s_row[kc][ty] + s_col[kc][tx];
+      float4 y0[PX], y1[PX];
+      float fl[PX];
+#pragma unroll
+      for (int p = 0; p < PX; ++p) {
+        const float4* q = sy + (int)(u >> 32);
+        fl[p] = float((unsigned)u);
+        y0[p] = q[0];
+        y1[p] = q[1];
+        u += st;
+      }
+#pragma unroll
+      for (int p = 0; p < PX; ++p) {
+        const float w0 = __builtin_amdgcn_fmed3f(fmaf(na32, fl[p], 1.0f), 0.0f, 1.0f);
+        const float w1 = __builtin_amdgcn_fmed3f(fmaf(pa32, fl[p], oma), 0.0f, 1.0f);
+        blk[0][p] = fmaf(w1, y1[p].x, fmaf(w0, y0[p].x, blk[0][p]));
+        blk[1][p] = fmaf(w1, y1[p].y, fmaf(w0, y0[p].y, blk[1][p]));
+        blk[2][p] = fmaf(w1, y1[p].z, fmaf(w0, y0[p].z, blk[2][p]));
+        blk[3][p] = fmaf(w1, y1[p].w, fmaf(w0, y0[p].w, blk[3][p]));
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int p = 0; p < PX; ++p) {
+        acc[m][p] += blk[m][p];
+        blk[m][p] = 0.0f;
+      }
+    __syncthreads();
+  }
+  const int n = g.n, h = n >> 1;
+  const int r = R0 + ty;
+  if (r >= h) return;
+#pragma unroll
+  for (int p = 0; p < PX; ++p) {
+    const int c = C0 + tx + 8 * p;
+    if (c >= h) continue;
+    // p, R p, R^2 p, R^3 p
+    const int rr[4] = {r, c, n - 1 - r, n - 1 - c};
+    const int cc[4] = {c, n - 1 - r, n - 1 - c, r};
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      if (S > 1)
+        out[share * part_stride + slot * out_stride + (long)rr[m] * n + cc[m]] = acc[m][p];
+      else if (padded)
+        out[slot * out_stride + (long)(rr[m] + kPad) * g.pitch + (cc[m] + kPad)] = acc[m][p];
+      else
+        out[slot * out_stride + (long)rr[m] * n + cc[m]] = acc[m][p];
+    }
+  }
+}
+
 // Sum of S partial images (fixed order) into the padded or unpadded output.
 // grid (ceil(n/16), ceil(n/16), G), block (16, 16)
 __global__ __launch_bounds__(256) void k_sum_parts(int n, int pitch, int S, const float* __restrict__ parts,
@@ -633,13 +839,13 @@ __global__ __launch_bounds__(256) void k_sum_parts(int n, int pitch, int S, cons
   if (c >= n || r >= n) return;
   const long q = (long)r * n + c;
   const float* src = parts + blockIdx.z * slot_stride;
-  // all S loads in flight together (S <= 8), then the sum in share order
-  float a[8];
+  // all S loads in flight together (S <= 16), then the sum in share order
+  float a[16];
 #pragma unroll
-  for (int s = 0; s < 8; ++s) a[s] = s < S ? src[s * part_stride + q] : 0.0f;
+  for (int s = 0; s < 16; ++s) a[s] = s < S ? src[s * part_stride + q] : 0.0f;
   float v = 0.0f;
 #pragma unroll
-  for (int s = 0; s < 8; ++s) v += a[s];
+  for (int s = 0; s < 16; ++s) v += a[s];
   if (padded)
     out[blockIdx.z * out_stride + (long)(r + kPad) * pitch + c + kPad] = v;
   else

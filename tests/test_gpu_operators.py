@@ -37,7 +37,9 @@ def test_project_and_backproject(dtype, bar, geom):
 
 # (forward, adjoint pixels per thread, adjoint angle shares)
 VARIANTS = [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 2), (1, 4, 1), (1, 4, 4), (0, 4, 3), (2, 4, 4), (2, 2, 1),
-            (3, 4, 4), (3, 1, 2), (3, 4, 8), (2, 2, 7), (3, 8, 4), (0, 8, 1)]
+            (3, 4, 4), (3, 1, 2), (3, 4, 8), (2, 2, 7), (3, 8, 4), (0, 8, 1),
+            # quarter-turn adjoint (falls back to the tiled one on odd sizes)
+            (3, -4, 6), (3, -2, 1), (3, -8, 8), (0, -4, 3), (2, -2, 5)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -64,7 +66,8 @@ def test_autotune_keeps_parity():
     P = Problem(128, 120, 182, 3, "field")
     h = P.handle(torch.float32)
     choice = h.autotune(1)
-    assert choice["fwd"] in (0, 1, 2, 3) and choice["adj_px"] in (0, 1, 2, 4, 8) and 1 <= choice["adj_shares"] <= 8
+    assert choice["fwd"] in (0, 1, 2, 3) and choice["adj_px"] in (0, 1, 2, 4, 8, -2, -4, -8)
+    assert 1 <= choice["adj_shares"] <= 16
     assert h.autotune(3) is not None
     x = f32(synth.ellipse_phantom(128, 1))
     y = f32(synth.random_sinograms(1, 120, 182, 2)[0])
@@ -228,10 +231,12 @@ def test_large_and_odd_geometries_sampled(geom):
     rays = [(int(rng.integers(na)), int(rng.integers(nd))) for _ in range(16)]
     pix = [(int(rng.integers(n)), int(rng.integers(n))) for _ in range(2)]
     refs = [projector.ray_sum(x, na, nd, k, j) for k, j in rays]
-    b = host(h.backproject(dev(y, torch.float32)))
-    for r, c in pix:
-        ref = projector.backproject_pixel(y, n, r, c)
-        assert abs(b[r, c] - ref) <= 1e-5 * np.abs(b).max()
+    prefs = [projector.backproject_pixel(y, n, r, c) for r, c in pix]
+    for adj in ((8, 6), (-4, 6)):
+        h.set_variant(0, *adj)
+        b = host(h.backproject(dev(y, torch.float32)))
+        for (r, c), ref in zip(pix, prefs):
+            assert abs(b[r, c] - ref) <= 1e-5 * np.abs(b).max(), (adj, r, c, b[r, c], ref)
     for fwd in (0, 1, 2, 3):
         try:
             h.set_variant(fwd, 8, 6)
@@ -255,7 +260,8 @@ def test_degenerate_geometries(geom):
     for dtype, bar in DT:
         P = Problem(n, na, nd, 1, "identity")
         h = P.handle(dtype)
-        variants = [None] if dtype == torch.float64 else [(0, 0, 1), (1, 1, 1), (2, 2, 2), (3, 4, 1), (3, 8, 3)]
+        variants = [None] if dtype == torch.float64 else [(0, 0, 1), (1, 1, 1), (2, 2, 2), (3, 4, 1), (3, 8, 3),
+                                                          (3, -4, 1), (3, -2, 3), (3, -8, 8)]
         for v in variants:
             if v is not None:
                 try:
