@@ -70,6 +70,7 @@ struct Work {
   GatePtrs<T>* ptrs = nullptr;       // [N]
   T* wP = nullptr;                   // [N][padded]
   T* wTP = nullptr;                  // [N][padded]
+  T* wQ = nullptr;                   // [N][3][padded] quarter-turn planes P_1..P_3 (float, even n and n_angles)
   T* bP = nullptr;                   // [N][padded]
   T* dy = nullptr;                   // [N][sino]
   T* img = nullptr;                  // [n*n] scratch
@@ -116,7 +117,8 @@ struct mcr_handle {
   // float32 projector pair: kernel variants (chosen by mcr_autotune)
   struct Tune {
     int fwd = 3;     // 0 one thread per ray, 1 LDS-tiled (8 angles x 32 bins), 2 the same with a host band
-                     // schedule, 3 line-sheared bands (16 angles x 32 bins, two rays per thread)
+                     // schedule, 3 line-sheared bands (16 angles x 32 bins, two rays per thread), 4 the
+                     // line-sheared quarter-turn forward (four rays per crossing)
     int adj_px = 4;  // 0 one thread per pixel; 1, 2, 4, 8 pixels per thread (LDS-tiled)
     int adj_s = 4;   // angle shares per pixel tile (LDS-tiled adjoint)
   } tune;
@@ -137,6 +139,15 @@ struct mcr_handle {
   int shear_npieces = 0, shear_nmulti = 0;
   std::vector<int2> shear_sub;        // per angle subset: (first piece, pieces)
   std::vector<int2> shear_sub_multi;  // per angle subset: (first multi-piece unit entry, entries)
+  // quarter-turn forward (variant 4): the same table format over the primary angles
+  int4* quad_chunks = nullptr;
+  int4* quad_pieces = nullptr;
+  int4* quad_units = nullptr;
+  int4* quad_bands = nullptr;
+  float* quad_part = nullptr;      // [slots][quad_part_floats]
+  int* quad_multi = nullptr;
+  int quad_npieces = 0, quad_nmulti = 0;
+  long quad_part_floats = 0;
   // angle subsets (mcr_set_subsets): subset s holds angles [sub_k[s], sub_k[s + 1])
   int M = 1;
   std::vector<int> sub_k;
@@ -421,7 +432,7 @@ void block_lines(int n, int nd, const std::vector<AngleFx>& af, int k0, int cnt,
 // entries; bands start at kShBL lines and are shortened until they fit.
 // Returns false if a single line does not fit.
 bool shear_tile_bands(int n, int nd, const std::vector<AngleFx>& af, int k0, int cnt, long long Bm, int jf, int jl,
-                      std::vector<int4>& bands) {
+                      int cap, std::vector<int4>& bands) {
   int L_lo, L_hi;
   block_lines(n, nd, af, k0, cnt, jf, jl, L_lo, L_hi);
   for (int L0 = L_lo; L0 <= L_hi;) {
@@ -444,9 +455,9 @@ bool shear_tile_bands(int n, int nd, const std::vector<AngleFx>& af, int k0, int
       const long long W = vmax - vmin + 3;
       lp = 6;
       while ((1LL << lp) < W) ++lp;
-      if ((long long)bl << lp <= kShCap) break;
+      if ((long long)bl << lp <= cap) break;
       if (bl == 1) return false;
-      bl = std::max(1, (int)(kShCap >> lp));
+      bl = std::max(1, (int)(cap >> lp));
     }
     bands.push_back(make_int4(L0, bl, S0, lp));
     L0 += bl;
@@ -454,23 +465,15 @@ bool shear_tile_bands(int n, int nd, const std::vector<AngleFx>& af, int k0, int
   return true;
 }
 
-// Chunks of up to kShKA angles of one stepping type and one angle subset
-// (bounds: k_0 = 0 < ... < k_M = n_angles), halved where a line of some
-// detector tile does not fit the window.
-Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& bounds) {
+// Chunks of up to kShKA consecutive angles of each run (runs: consecutive
+// angles of one stepping type and one angle subset, bounds: k_0 = 0 < ... <
+// k_M = n_angles), halved where a line of some detector tile does not fit the
+// window; detector tiles of kShJD bins cover bins [0, nbins); cap: staged
+// entries per band; ppp: partial sums per piece.
+Schedule build_shear_units(int n, int nd, int nbins, const std::vector<AngleFx>& af, const std::vector<int2>& runs,
+                           const std::vector<int>& bounds, int cap, int ppp, int piece_lines) {
   Schedule S;
-  const int ntiles = (nd + kShJD - 1) / kShJD;
-  std::vector<int2> runs;
-  for (const int2& r : angle_chunks(af, INT_MAX)) {
-    int k = r.x;
-    for (size_t b = 1; b < bounds.size() && k < r.x + r.y; ++b) {
-      const int e = std::min(r.x + r.y, bounds[b]);
-      if (e > k) {
-        runs.push_back(make_int2(k, e - k));
-        k = e;
-      }
-    }
-  }
+  const int ntiles = (nbins + kShJD - 1) / kShJD;
   for (const int2& run : runs) {
     for (int k0 = run.x; k0 < run.x + run.y;) {
       int cnt = std::min(kShKA, run.x + run.y - k0);
@@ -482,9 +485,9 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
         bands.clear();
         bool fit = true;
         for (int t = 0; t < ntiles && fit; ++t) {
-          const int jf = t * kShJD, jl = std::min(jf + kShJD - 1, nd - 1);
+          const int jf = t * kShJD, jl = std::min(jf + kShJD - 1, nbins - 1);
           const int first = (int)(S.bands.size() + bands.size());
-          fit = shear_tile_bands(n, nd, af, k0, cnt, Bm, jf, jl, bands);
+          fit = shear_tile_bands(n, nd, af, k0, cnt, Bm, jf, jl, cap, bands);
           blocks.push_back(make_int2(first, (int)(S.bands.size() + bands.size()) - first));
         }
         if (fit) {
@@ -502,7 +505,7 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
       k0 += cnt;
     }
   }
-  // cut every (chunk, tile) unit into pieces of about kShPieceLines lines so
+  // cut every (chunk, tile) unit into pieces of about piece_lines lines so
   // that the blocks carry similar work; pieces of one unit are numbered in
   // line order and their partial sums are added in that order
   for (int c = 0; c < (int)S.chunks.size(); ++c) {
@@ -511,7 +514,7 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
       const int2 bl = S.blocks[u];
       int b0 = bl.x, lines = 0, pc = 0;
       for (int b = bl.x; b < bl.x + bl.y; ++b) {
-        if (b > b0 && lines + S.bands[b].y > kShPieceLines) {
+        if (b > b0 && lines + S.bands[b].y > piece_lines) {
           S.pieces.push_back(make_int4(b0, b - b0, u, pc++));
           b0 = b;
           lines = 0;
@@ -521,7 +524,7 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
       S.pieces.push_back(make_int4(b0, bl.x + bl.y - b0, u, pc++));
       if (pc > 1) S.multi.push_back((int)S.units.size());
       S.units.push_back(make_int4(c, t, pc, (int)S.part_floats));
-      if (pc > 1) S.part_floats += (long)pc * 512;
+      if (pc > 1) S.part_floats += (long)pc * ppp;
     }
   }
   // pieces and multi-piece units come in chunk order, so each subset's are contiguous
@@ -543,6 +546,37 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
     ++r.y;
   }
   return S;
+}
+
+// Line-sheared forward over all angles: runs of one stepping type, cut at
+// the subset bounds.
+Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& bounds) {
+  std::vector<int2> runs;
+  for (const int2& r : angle_chunks(af, INT_MAX)) {
+    int k = r.x;
+    for (size_t b = 1; b < bounds.size() && k < r.x + r.y; ++b) {
+      const int e = std::min(r.x + r.y, bounds[b]);
+      if (e > k) {
+        runs.push_back(make_int2(k, e - k));
+        k = e;
+      }
+    }
+  }
+  return build_shear_units(n, nd, nd, af, runs, bounds, kShCap, 2 * 256, kShPieceLines);
+}
+
+// Quarter-turn forward: the primary angles are the row-stepping ones
+// (4k <= n_angles or 4k >= 3 n_angles), without k = 3 n_angles / 4 (the
+// partner of k = n_angles / 4); with n_angles even each pair {k, k +- n_angles/2}
+// holds exactly one primary angle. Bins [0, ceil(n_det / 2)).
+Schedule build_quad_schedule(int n, int nd, const std::vector<AngleFx>& af) {
+  const int na = (int)af.size();
+  std::vector<int2> runs;
+  const int a_end = na / 4 + 1;                  // k <= floor(na / 4)
+  const int b_beg = (3 * na + 3) / 4 + (na % 4 == 0 ? 1 : 0);
+  if (a_end > 0) runs.push_back(make_int2(0, std::min(a_end, na)));
+  if (b_beg < na) runs.push_back(make_int2(b_beg, na - b_beg));
+  return build_shear_units(n, nd, (nd + 1) / 2, af, runs, {0, na}, kQuCap, 8 * 256, kQuPieceLines);
 }
 
 Schedule build_schedule(int n, int nd, const std::vector<AngleFx>& af, int ka, int jd, int wl) {
@@ -642,6 +676,38 @@ mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
   return MCR_OK;
 }
 
+// Tables of the quarter-turn forward (float handles with even n and n_angles).
+mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
+  if (h->geo.n % 2 || h->geo.n_angles % 2) return MCR_OK;
+  const Schedule qs = build_quad_schedule(h->geo.n, h->geo.n_det, af);
+  if (!qs.ok || qs.pieces.empty()) return MCR_OK;  // variant 4 unavailable on this geometry
+  const int ns = h->nslots;
+  STATUS_OK(dmalloc(h, (void**)&h->wf.wQ, sizeof(float) * 3 * h->padded * ns));
+  h->quad_part_floats = qs.part_floats;
+  STATUS_OK(dmalloc(h, (void**)&h->quad_chunks, sizeof(int4) * qs.chunks.size()));
+  STATUS_OK(dmalloc(h, (void**)&h->quad_pieces, sizeof(int4) * qs.pieces.size()));
+  STATUS_OK(dmalloc(h, (void**)&h->quad_units, sizeof(int4) * qs.units.size()));
+  STATUS_OK(dmalloc(h, (void**)&h->quad_bands, sizeof(int4) * std::max<size_t>(1, qs.bands.size())));
+  STATUS_OK(dmalloc(h, (void**)&h->quad_part, sizeof(float) * std::max<long>(1, qs.part_floats) * ns));
+  STATUS_OK(dmalloc(h, (void**)&h->quad_multi, sizeof(int) * std::max<size_t>(1, qs.multi.size())));
+  HIP_OK(hipMemcpyAsync(h->quad_chunks, qs.chunks.data(), sizeof(int4) * qs.chunks.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  HIP_OK(hipMemcpyAsync(h->quad_pieces, qs.pieces.data(), sizeof(int4) * qs.pieces.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  HIP_OK(hipMemcpyAsync(h->quad_units, qs.units.data(), sizeof(int4) * qs.units.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  if (!qs.bands.empty())
+    HIP_OK(hipMemcpyAsync(h->quad_bands, qs.bands.data(), sizeof(int4) * qs.bands.size(), hipMemcpyHostToDevice,
+                          h->stream));
+  if (!qs.multi.empty())
+    HIP_OK(hipMemcpyAsync(h->quad_multi, qs.multi.data(), sizeof(int) * qs.multi.size(), hipMemcpyHostToDevice,
+                          h->stream));
+  HIP_OK(hipStreamSynchronize(h->stream));
+  h->quad_npieces = (int)qs.pieces.size();
+  h->quad_nmulti = (int)qs.multi.size();
+  return MCR_OK;
+}
+
 // The quarter-turn adjoint pairs angle k with angle k +- n_angles/2 and a
 // pixel with its quarter turns: it needs an even image size, an even number
 // of angles, and all of them in the launch.
@@ -707,6 +773,7 @@ mcr_status init_work(mcr_handle* h) {
                             h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
     STATUS_OK(upload_shear(h, af));
+    STATUS_OK(upload_quad(h, af));
   }
   HIP_OK(hipStreamSynchronize(h->stream));
   STATUS_OK(upload_motion<T>(h));
@@ -751,8 +818,11 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_WARP);
   dim3 grid(cdiv(n, 32), cdiv(n, 32), G), block(32, 32);
+  // the quarter-turn planes only when the forward that reads them is selected
+  T* wQ = (std::is_same<T, float>::value && h->tune.fwd == 4 && h->quad_npieces > 0) ? w.wQ : nullptr;
   hipLaunchKernelGGL(k_warp_fwd<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate0,
-                     h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, w.wTP, h->padded, slots);
+                     h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, w.wTP, h->padded, slots, wQ,
+                     3 * h->padded, h->padded);
   LAUNCH_OK();
   return MCR_OK;
 }
@@ -771,10 +841,22 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   const GateScalars<T>* gs = w.scalars + w.sc_base;
   dim3 grid(cdiv(h->geo.n_det, 256), kb - ka, G), block(256);
   if constexpr (std::is_same<T, float>::value) {
-    // the chunk tables of variants 1 and 2 cover all angles
-    const int fwd = (subset >= 0 && (h->tune.fwd == 1 || h->tune.fwd == 2)) ? (h->shear_npieces > 0 ? 3 : 0)
-                                                                             : h->tune.fwd;
-    if (fwd == 3 && h->shear_npieces > 0) {
+    // the chunk tables of variants 1, 2 and 4 cover all angles
+    const int fwd = (subset >= 0 && h->tune.fwd != 0 && h->tune.fwd != 3) ? (h->shear_npieces > 0 ? 3 : 0)
+                                                                          : h->tune.fwd;
+    if (fwd == 4 && h->quad_npieces > 0) {
+      const long qp = h->quad_part_floats;
+      hipLaunchKernelGGL((k_joseph_fwd_quad<MODE>), dim3(h->quad_npieces, 1, G), dim3(256), 0, h->stream,
+                         geo_of<T>(h), w.angfx, h->quad_chunks, h->quad_pieces, h->quad_units, h->quad_bands, w.wP,
+                         w.wQ, h->padded, 3 * h->padded, h->padded, out, out_stride, gate0, gs, w.ptrs, slots,
+                         h->quad_part, qp, 0);
+      LAUNCH_OK();
+      if (h->quad_nmulti > 0) {
+        hipLaunchKernelGGL((k_joseph_fwd_quad_finish<MODE>), dim3(h->quad_nmulti, 1, G), dim3(256), 0, h->stream,
+                           geo_of<T>(h), w.angfx, h->quad_chunks, h->quad_units, h->quad_multi, h->quad_part, qp,
+                           out, out_stride, gate0, gs, w.ptrs, slots, 0);
+      }
+    } else if (fwd == 3 && h->shear_npieces > 0) {
       const int2 pr = subset >= 0 ? h->shear_sub[subset] : make_int2(0, h->shear_npieces);
       const int2 mr = subset >= 0 ? h->shear_sub_multi[subset] : make_int2(0, h->shear_nmulti);
       if (pr.y > 0) {
@@ -1976,7 +2058,8 @@ mcr_status mcr_duality_gap(mcr_handle* h, const mcr_state* st, const void* const
 
 namespace {
 bool fwd_variant_ok(const mcr_handle* h, int f) {
-  return f == 0 || (f == 1 && h->fwd_lds_ok) || (f == 2 && h->sched_ok) || (f == 3 && h->shear_npieces > 0);
+  return f == 0 || (f == 1 && h->fwd_lds_ok) || (f == 2 && h->sched_ok) || (f == 3 && h->shear_npieces > 0) ||
+         (f == 4 && h->quad_npieces > 0);
 }
 }  // namespace
 
@@ -2013,7 +2096,7 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       };
       std::vector<int> fv;
       std::vector<float> ft;
-      for (int f = 3; f >= 0 && st == MCR_OK; --f) {  // preferred: the newest kernel
+      for (int f = 4; f >= 0 && st == MCR_OK; --f) {  // preferred: the newest kernel
         if (!fwd_variant_ok(h, f)) continue;
         h->tune.fwd = f;
         float ms = 0.0f;
@@ -2057,7 +2140,10 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
 
 mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t adj_s) {
   STATUS_OK(check_handle(h));
-  if (fwd < 0 || fwd > 3) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1, 2 or 3", fwd);
+  if (fwd < 0 || fwd > 4) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1, 2, 3 or 4", fwd);
+  if (h->dtype == MCR_F32 && fwd == 4 && (h->geo.n % 2 || h->geo.n_angles % 2))
+    return fail(MCR_ERR_STATE, "the quarter-turn forward needs an even n and n_angles: its tables do not fit this "
+                               "geometry");
   if (h->dtype == MCR_F32 && !fwd_variant_ok(h, fwd))
     return fail(MCR_ERR_STATE, "the tiled forward's band windows do not fit this geometry");
   if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4 && adj_px != 8 && adj_px != -2 && adj_px != -4 &&

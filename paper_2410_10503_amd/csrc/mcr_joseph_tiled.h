@@ -454,6 +454,262 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
     project_epilogue<float, MODE>(ang[ch.x + kk + 8].ds * acc1, (long)(ch.x + kk + 8) * g.nd + j, o, gate, gs, gp);
 }
 
+// Quarter-turn forward. For a row-stepping (primary) angle k, with k2 = k +
+// n_angles/2 (k < n_angles/2) or k - n_angles/2 (then reversed), the Joseph
+// rays of angle k through the quarter turns of the image give the other
+// rays: with the planes P_m[q] = x[R^m q], R (r, c) -> (c, n - 1 - r),
+//   ray j of P_0 -> ray (k, j)          ray j of P_2 -> ray (k, n_det - 1 - j)
+//   ray j of P_1 -> ray (k2, j)         ray j of P_3 -> ray (k2, n_det - 1 - j)
+// (k2's bins reversed when k >= n_angles/2). So each staged entry holds the
+// four planes' values at one pixel (a float4) and one crossing, one
+// conversion and one pair of weights serve four rays; the bins run over
+// [0, ceil(n_det/2)) only. The work split is the line-sheared one of
+// k_joseph_fwd_shear (same schedule format, kQuCap entries per band); a tap
+// reads the entries at the crossing's column and the next one and
+// interpolates. Multi-piece units write 8 partial sums per thread (planes x
+// two rays), added by k_joseph_fwd_quad_finish.
+// grid (pieces, 1, G), block 256; piece piece0 + blockIdx.x. wQ holds the
+// planes P_1, P_2, P_3 (plane_stride apart) of each slot, wP is P_0.
+constexpr int kQuCap = 1024;       // staged float4 entries per band
+constexpr int kQuPieceLines = 64;  // target lines per block
+
+// The four outputs of the rays (k, j) of the planes; the reversed bin of
+// the centre bin of an odd detector is the bin itself, written once.
+template <int MODE>
+__device__ __forceinline__ void quad_epilogue(const float (&v)[4], int k, int j, int na, int nd, float* o, int gate,
+                                              const GateScalars<float>* gs, const GatePtrs<float>* gp) {
+  const int H = na >> 1;
+  const int k2 = k < H ? k + H : k - H;
+  const int jr = nd - 1 - j;
+  const bool rev = k >= H;
+  project_epilogue<float, MODE>(v[0], (long)k * nd + j, o, gate, gs, gp);
+  project_epilogue<float, MODE>(v[1], (long)k2 * nd + (rev ? jr : j), o, gate, gs, gp);
+  if (jr != j) {
+    project_epilogue<float, MODE>(v[2], (long)k * nd + jr, o, gate, gs, gp);
+    project_epilogue<float, MODE>(v[3], (long)k2 * nd + (rev ? j : jr), o, gate, gs, gp);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                         const int4* __restrict__ chunks,
+                                                         const int4* __restrict__ pieces,
+                                                         const int4* __restrict__ units,
+                                                         const int4* __restrict__ bands,
+                                                         const float* __restrict__ wP,
+                                                         const float* __restrict__ wQ, long w_stride,
+                                                         long q_stride, long plane_stride,
+                                                         float* __restrict__ out, long out_stride, int gate0,
+                                                         const GateScalars<float>* __restrict__ gs,
+                                                         const GatePtrs<float>* __restrict__ gp,
+                                                         const SlotInfo* __restrict__ slots,
+                                                         float* __restrict__ part, long part_stride, int piece0) {
+  constexpr int kPer = kQuCap / 256;  // staged entries per thread
+  __shared__ float4 st[kQuCap];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int4 pc = pieces[piece0 + blockIdx.x];
+  const int4 un = units[pc.z];
+  const int4 ch = chunks[un.x];
+  const long long Bm = (long long)(((unsigned long long)(unsigned)ch.w << 32) | (unsigned)ch.z);
+  const int2 bb = make_int2(pc.x, pc.y);
+  const int kk = tid >> 5;
+  const int nb = (g.nd + 1) >> 1;
+  const int j = un.y * kShJD + (tid & 31);
+  const int jc = min(j, nb - 1);
+  const AngleFx& A0 = ang[ch.x + min(kk, ch.y - 1)];
+  const AngleFx& A1 = ang[ch.x + min(kk + 8, ch.y - 1)];
+  const unsigned long long S0 = (unsigned long long)A0.B;
+  const unsigned long long S1 = (unsigned long long)A1.B;
+  const unsigned s0lo = (unsigned)S0, s0hi = (unsigned)(S0 >> 32);
+  const unsigned s1lo = (unsigned)S1, s1hi = (unsigned)(S1 >> 32);
+  const long long c0j = A0.C0 + (long long)jc * A0.A;
+  const long long c1j = A1.C0 + (long long)jc * A1.A;
+  const int n = g.n, pitch = g.pitch;
+  const long origin = (long)kPad * pitch + kPad;
+  const float* p0 = wP + blockIdx.z * w_stride + origin;
+  const float* p1 = wQ + blockIdx.z * q_stride + origin;
+  const float* p2 = p1 + plane_stride;
+  const float* p3 = p2 + plane_stride;
+  float4 pre[kPer];
+  // entry i = l * pitch + q of a band; a wave's 64 entries share one line
+  auto fetch = [&](const int4 bd) {
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) {
+      const int ib = 256 * e + 64 * wv;
+      const int l = ib >> bd.w;
+      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (l < bd.y) {
+        const int o = (int)(((long long)l * Bm) >> 32);
+        // column clamped into the padded row [-kPad, n + kPad - 1] (zero halo)
+        const int c = min(max(bd.z + o + (ib & ((1 << bd.w) - 1)) + lane, -kPad), n + kPad - 1);
+        const long q = (long)(bd.x + l) * pitch + c;
+        v = make_float4(p0[q], p1[q], p2[q], p3[q]);
+      }
+      pre[e] = v;
+    }
+  };
+  unsigned lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+  int s_prev = 0;
+  if (bb.y > 0) {
+    const int4 bd = bands[bb.x];
+    fetch(bd);
+    const unsigned long long q0 = (unsigned long long)(c0j + (long long)bd.x * A0.B - ((long long)bd.z << 32));
+    const unsigned long long q1 = (unsigned long long)(c1j + (long long)bd.x * A1.B - ((long long)bd.z << 32));
+    lo0 = (unsigned)q0;
+    hi0 = (unsigned)(q0 >> 32);
+    lo1 = (unsigned)q1;
+    hi1 = (unsigned)(q1 >> 32);
+    s_prev = bd.z;
+  }
+  float acc0[4] = {0.0f, 0.0f, 0.0f, 0.0f}, acc1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int b = 0; b < bb.y; ++b) {
+    const int4 bd = bands[bb.x + b];
+#pragma unroll
+    for (int e = 0; e < kPer; ++e) st[256 * e + tid] = pre[e];
+    __syncthreads();
+    if (b + 1 < bb.y) fetch(bands[bb.x + b + 1]);
+    hi0 += (unsigned)(s_prev - bd.z);
+    hi1 += (unsigned)(s_prev - bd.z);
+    s_prev = bd.z;
+    long long om = 0;
+    float b0[4] = {0.0f, 0.0f, 0.0f, 0.0f}, b1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    const char* base = (const char*)st;
+    // the taps of both rays on line l: the entries at the crossing's column
+    // and the next one; so = 16 (l pitch - o_l) is the byte offset of line
+    // l's window (uniform)
+    auto tap = [&](int so, float4& x0, float4& y0, float& f0, float4& x1, float4& y1, float& f1) {
+      const char* q0 = base + ((hi0 << 4) + (unsigned)so);
+      const char* q1 = base + ((hi1 << 4) + (unsigned)so);
+      x0 = *(const float4*)q0;
+      y0 = *(const float4*)(q0 + 16);
+      x1 = *(const float4*)q1;
+      y1 = *(const float4*)(q1 + 16);
+      f0 = float(lo0);
+      f1 = float(lo1);
+      unsigned c0, c1;
+      lo0 = __builtin_addc(lo0, s0lo, 0u, &c0);
+      hi0 = __builtin_addc(hi0, s0hi, c0, &c0);
+      lo1 = __builtin_addc(lo1, s1lo, 0u, &c1);
+      hi1 = __builtin_addc(hi1, s1hi, c1, &c1);
+    };
+    auto mix = [&](const float4& x, const float4& y, float f, float (&a)[4]) {
+      const float w1 = f * kFix, w0 = fmaf(f, -kFix, 1.0f);
+      a[0] = fmaf(w1, y.x, fmaf(w0, x.x, a[0]));
+      a[1] = fmaf(w1, y.y, fmaf(w0, x.y, a[1]));
+      a[2] = fmaf(w1, y.z, fmaf(w0, x.z, a[2]));
+      a[3] = fmaf(w1, y.w, fmaf(w0, x.w, a[3]));
+    };
+    int l = 0;
+    for (; l + 2 <= bd.y; l += 2) {
+      float4 x0[2], y0[2], x1[2], y1[2];
+      float f0[2], f1[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int so = 16 * (((l + t) << bd.w) - (int)(om >> 32));
+        om += Bm;
+        tap(so, x0[t], y0[t], f0[t], x1[t], y1[t], f1[t]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        mix(x0[t], y0[t], f0[t], b0);
+        mix(x1[t], y1[t], f1[t], b1);
+      }
+    }
+    if (l < bd.y) {
+      float4 x0, y0, x1, y1;
+      float f0, f1;
+      const int so = 16 * ((l << bd.w) - (int)(om >> 32));
+      om += Bm;
+      tap(so, x0, y0, f0, x1, y1, f1);
+      mix(x0, y0, f0, b0);
+      mix(x1, y1, f1, b1);
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      acc0[m] += b0[m];
+      acc1[m] += b1[m];
+    }
+    __syncthreads();
+  }
+  if (un.z > 1) {  // partial sums; k_joseph_fwd_quad_finish adds them
+    float* pu = part + blockIdx.z * part_stride + un.w + pc.w * 2048;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      pu[m * 512 + tid] = acc0[m];
+      pu[m * 512 + 256 + tid] = acc1[m];
+    }
+    return;
+  }
+  if (j >= nb) return;
+  const int gate = slot_gate(slots, gate0);
+  float* o = out + blockIdx.z * out_stride;
+  if (kk < ch.y) {
+    const float v[4] = {A0.ds * acc0[0], A0.ds * acc0[1], A0.ds * acc0[2], A0.ds * acc0[3]};
+    quad_epilogue<MODE>(v, ch.x + kk, j, g.na, g.nd, o, gate, gs, gp);
+  }
+  if (kk + 8 < ch.y) {
+    const float v[4] = {A1.ds * acc1[0], A1.ds * acc1[1], A1.ds * acc1[2], A1.ds * acc1[3]};
+    quad_epilogue<MODE>(v, ch.x + kk + 8, j, g.na, g.nd, o, gate, gs, gp);
+  }
+}
+
+// Sum of the partial sums of the multi-piece units of k_joseph_fwd_quad in
+// piece order, then the four outputs. grid (count, 1, G), block 256.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_joseph_fwd_quad_finish(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                                const int4* __restrict__ chunks,
+                                                                const int4* __restrict__ units,
+                                                                const int* __restrict__ multi,
+                                                                const float* __restrict__ part, long part_stride,
+                                                                float* __restrict__ out, long out_stride, int gate0,
+                                                                const GateScalars<float>* __restrict__ gs,
+                                                                const GatePtrs<float>* __restrict__ gp,
+                                                                const SlotInfo* __restrict__ slots, int multi0) {
+  const int tid = threadIdx.x;
+  const int4 un = units[multi[multi0 + blockIdx.x]];
+  const int4 ch = chunks[un.x];
+  const int kk = tid >> 5;
+  const int nb = (g.nd + 1) >> 1;
+  const int j = un.y * kShJD + (tid & 31);
+  if (j >= nb) return;
+  const float* pu = part + blockIdx.z * part_stride + un.w;
+  float a0[4] = {0.0f, 0.0f, 0.0f, 0.0f}, a1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // loads of up to 4 pieces in flight, then their sum in piece order
+  for (int q0 = 0; q0 < un.z; q0 += 4) {
+    float va[4][4], vb[4][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const bool in = q0 + q < un.z;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        va[q][m] = in ? pu[(q0 + q) * 2048 + m * 512 + tid] : 0.0f;
+        vb[q][m] = in ? pu[(q0 + q) * 2048 + m * 512 + 256 + tid] : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        a0[m] += va[q][m];
+        a1[m] += vb[q][m];
+      }
+  }
+  const int gate = slot_gate(slots, gate0);
+  float* o = out + blockIdx.z * out_stride;
+  if (kk < ch.y) {
+    const float ds = ang[ch.x + kk].ds;
+    const float v[4] = {ds * a0[0], ds * a0[1], ds * a0[2], ds * a0[3]};
+    quad_epilogue<MODE>(v, ch.x + kk, j, g.na, g.nd, o, gate, gs, gp);
+  }
+  if (kk + 8 < ch.y) {
+    const float ds = ang[ch.x + kk + 8].ds;
+    const float v[4] = {ds * a1[0], ds * a1[1], ds * a1[2], ds * a1[3]};
+    quad_epilogue<MODE>(v, ch.x + kk + 8, j, g.na, g.nd, o, gate, gs, gp);
+  }
+}
+
 constexpr int kAdjKC = 32;  // angles per staged chunk
 
 // Bins staged per angle: a 32 x 8PX pixel tile projects onto at most

@@ -207,7 +207,8 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
                                                   long field_stride, long plane_stride,
                                                   const T* __restrict__ x, long x_stride,
                                                   T* __restrict__ wP, T* __restrict__ wTP,
-                                                  long w_stride, const SlotInfo* __restrict__ slots) {
+                                                  long w_stride, const SlotInfo* __restrict__ slots,
+                                                  T* __restrict__ wQ, long q_stride, long q_plane) {
   __shared__ T tile[32][33];
   const int gate = slot_gate(slots, gate0);
   const int slice = slots ? slots[blockIdx.z].slice : (int)blockIdx.z;
@@ -247,6 +248,9 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
         v = acc;
       }
       dst[(long)r * pitch + c] = v;
+      // quarter-turn planes P_m[q] = w[R^m q], R (r, c) -> (c, n - 1 - r):
+      // P_2 takes w(r, c) at (n - 1 - r, n - 1 - c)
+      if (wQ) wQ[blockIdx.z * q_stride + origin + q_plane + (long)(n - 1 - r) * pitch + (n - 1 - c)] = v;
     }
     tile[threadIdx.y][threadIdx.x] = v;
   }
@@ -254,7 +258,15 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
   // transposed store: thread (tx, ty) writes column blockIdx.x*32 + ty, rows along tx
   const int cc = blockIdx.x * 32 + threadIdx.y;
   const int rr = blockIdx.y * 32 + threadIdx.x;
-  if (cc < n && rr < n) dstT[(long)cc * pitch + rr] = tile[threadIdx.x][threadIdx.y];
+  if (cc < n && rr < n) {
+    const T v = tile[threadIdx.x][threadIdx.y];  // w(rr, cc)
+    dstT[(long)cc * pitch + rr] = v;
+    if (wQ) {  // P_1 takes it at (n - 1 - cc, rr), P_3 at (cc, n - 1 - rr)
+      T* q = wQ + blockIdx.z * q_stride + origin;
+      q[(long)(n - 1 - cc) * pitch + rr] = v;
+      q[2 * q_plane + (long)cc * pitch + (n - 1 - rr)] = v;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------

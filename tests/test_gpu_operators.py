@@ -39,7 +39,9 @@ def test_project_and_backproject(dtype, bar, geom):
 VARIANTS = [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 2), (1, 4, 1), (1, 4, 4), (0, 4, 3), (2, 4, 4), (2, 2, 1),
             (3, 4, 4), (3, 1, 2), (3, 4, 8), (2, 2, 7), (3, 8, 4), (0, 8, 1),
             # quarter-turn adjoint (falls back to the tiled one on odd sizes)
-            (3, -4, 6), (3, -2, 1), (3, -8, 8), (0, -4, 3), (2, -2, 5)]
+            (3, -4, 6), (3, -2, 1), (3, -8, 8), (0, -4, 3), (2, -2, 5),
+            # quarter-turn forward (unavailable on odd sizes)
+            (4, -4, 8), (4, 4, 4), (4, 8, 6), (4, -2, 16)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -66,7 +68,7 @@ def test_autotune_keeps_parity():
     P = Problem(128, 120, 182, 3, "field")
     h = P.handle(torch.float32)
     choice = h.autotune(1)
-    assert choice["fwd"] in (0, 1, 2, 3) and choice["adj_px"] in (0, 1, 2, 4, 8, -2, -4, -8)
+    assert choice["fwd"] in (0, 1, 2, 3, 4) and choice["adj_px"] in (0, 1, 2, 4, 8, -2, -4, -8)
     assert 1 <= choice["adj_shares"] <= 16
     assert h.autotune(3) is not None
     x = f32(synth.ellipse_phantom(128, 1))
@@ -237,7 +239,7 @@ def test_large_and_odd_geometries_sampled(geom):
         b = host(h.backproject(dev(y, torch.float32)))
         for (r, c), ref in zip(pix, prefs):
             assert abs(b[r, c] - ref) <= 1e-5 * np.abs(b).max(), (adj, r, c, b[r, c], ref)
-    for fwd in (0, 1, 2, 3):
+    for fwd in (0, 1, 2, 3, 4):
         try:
             h.set_variant(fwd, 8, 6)
         except McrError as e:
@@ -261,7 +263,8 @@ def test_degenerate_geometries(geom):
         P = Problem(n, na, nd, 1, "identity")
         h = P.handle(dtype)
         variants = [None] if dtype == torch.float64 else [(0, 0, 1), (1, 1, 1), (2, 2, 2), (3, 4, 1), (3, 8, 3),
-                                                          (3, -4, 1), (3, -2, 3), (3, -8, 8)]
+                                                          (3, -4, 1), (3, -2, 3), (3, -8, 8), (4, -4, 1),
+                                                          (4, 8, 2)]
         for v in variants:
             if v is not None:
                 try:

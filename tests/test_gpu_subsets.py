@@ -57,7 +57,7 @@ def test_fp64_block_iterations_match_oracle(kind, M):
 
 
 # (forward variant, adjoint pixels per thread, angle shares)
-@pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1)])
+@pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1), (4, -4, 8)])
 def test_fp32_block_iterations_match_oracle(variant):
     P = Problem(64, 96, 92, 4, "field", alpha=1e-3)
     M = 3
