@@ -289,7 +289,12 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           band prefetched while the current one is computed,
  *           3 = host-scheduled bands whose window shifts line by line with
  *           the chunk's mean ray slope (up to 16 angles x 32 bins, two rays
- *           per thread; the default where it applies);
+ *           per thread; the default where it applies),
+ *           4 = the same over the row-stepping angles and half the bins, the
+ *           warp also writing the image's three quarter turns: one crossing
+ *           serves rays of angle k and k +- n_angles/2, bins j and
+ *           n_det - 1 - j (even n and n_angles only; angle-subset launches
+ *           run variant 3);
  * adjoint:  adj_px = 0 one thread per pixel, or 1, 2, 4, 8 pixels per thread with
  *           LDS-staged sinogram chunks, the angles split into adj_s (1..16)
  *           shares whose partial images are summed in a fixed order;
