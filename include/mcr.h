@@ -299,10 +299,13 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           LDS-staged sinogram chunks, the angles split into adj_s (1..16)
  *           shares whose partial images are summed in a fixed order;
  *           adj_px = -2, -4, -8: the quarter-turn kernel with 2, 4, 8 pixels
- *           per thread (one detector coordinate serves a pixel of the top-left
+ *           per thread on 32 x 16, 32 x 32, 32 x 64 pixel tiles, -16: 4 pixels
+ *           per thread on 32 x 64 tiles, -32: 4 pixels per thread on 64 x 64
+ *           tiles (one detector coordinate serves a pixel of the top-left
  *           quadrant at angle k and its three quarter turns at angles k and
  *           k +- n_angles/2; needs an even n and n_angles and a launch over
- *           all angles, else the tiled kernel with -adj_px pixels runs).
+ *           all angles, else the tiled kernel runs with 2, 4, 8, 8, 8
+ *           pixels per thread).
  * All variants compute the same weights; results differ only by summation
  * order. mcr_autotune times the variants on this geometry with
  * gates_per_launch gates per launch (1 for SPDHG, N for PDHG), keeps the

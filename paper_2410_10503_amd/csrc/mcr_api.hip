@@ -708,6 +708,13 @@ mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
   return MCR_OK;
 }
 
+// Quarter-turn adjoint codes (adj_px < 0): -2, -4, -8 = 2, 4, 8 pixels per
+// thread on 32 x 8PX tiles (256 threads), -16 = 4 pixels on 32 x 64 tiles
+// (512 threads), -32 = 4 pixels on 64 x 64 tiles (1024 threads). Where the
+// geometry has no quarter-turn symmetry the tiled kernel runs with the
+// pixels per thread returned here.
+int quad_tiled_px(int code) { return code >= -8 ? -code : 8; }
+
 // The quarter-turn adjoint pairs angle k with angle k +- n_angles/2 and a
 // pixel with its quarter turns: it needs an even image size, an even number
 // of angles, and all of them in the launch.
@@ -818,10 +825,14 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_WARP);
   dim3 grid(cdiv(n, 32), cdiv(n, 32), G), block(32, 32);
-  // the quarter-turn planes only when the forward that reads them is selected
-  T* wQ = (std::is_same<T, float>::value && h->tune.fwd == 4 && h->quad_npieces > 0) ? w.wQ : nullptr;
+  // the quarter-turn planes only when the forward that reads them is
+  // selected; the transposed image only when some launch may use another
+  // forward (angle subsets of less than all angles)
+  const bool quad = std::is_same<T, float>::value && h->tune.fwd == 4 && h->quad_npieces > 0;
+  T* wQ = quad ? w.wQ : nullptr;
+  T* wT = quad && h->M == 1 ? nullptr : w.wTP;
   hipLaunchKernelGGL(k_warp_fwd<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate0,
-                     h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, w.wTP, h->padded, slots, wQ,
+                     h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, wT, h->padded, slots, wQ,
                      3 * h->padded, h->padded);
   LAUNCH_OK();
   return MCR_OK;
@@ -830,6 +841,7 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
 // Angles of subset `subset` (-1: all angles).
 void subset_range(const mcr_handle* h, int subset, int& ka, int& kb);
 bool quad_ok(const mcr_handle* h, int ka, int kb);
+int quad_tiled_px(int code);
 
 template <typename T, int MODE>
 mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stride,
@@ -842,8 +854,8 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   dim3 grid(cdiv(h->geo.n_det, 256), kb - ka, G), block(256);
   if constexpr (std::is_same<T, float>::value) {
     // the chunk tables of variants 1, 2 and 4 cover all angles
-    const int fwd = (subset >= 0 && h->tune.fwd != 0 && h->tune.fwd != 3) ? (h->shear_npieces > 0 ? 3 : 0)
-                                                                          : h->tune.fwd;
+    const bool part = ka > 0 || kb < h->geo.n_angles;
+    const int fwd = (part && h->tune.fwd != 0 && h->tune.fwd != 3) ? (h->shear_npieces > 0 ? 3 : 0) : h->tune.fwd;
     if (fwd == 4 && h->quad_npieces > 0) {
       const long qp = h->quad_part_floats;
       hipLaunchKernelGGL((k_joseph_fwd_quad<MODE>), dim3(h->quad_npieces, 1, G), dim3(256), 0, h->stream,
@@ -852,7 +864,7 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
                          h->quad_part, qp, 0);
       LAUNCH_OK();
       if (h->quad_nmulti > 0) {
-        hipLaunchKernelGGL((k_joseph_fwd_quad_finish<MODE>), dim3(h->quad_nmulti, 1, G), dim3(256), 0, h->stream,
+        hipLaunchKernelGGL((k_joseph_fwd_quad_finish<MODE>), dim3(h->quad_nmulti, 4, G), dim3(256), 0, h->stream,
                            geo_of<T>(h), w.angfx, h->quad_chunks, h->quad_units, h->quad_multi, h->quad_part, qp,
                            out, out_stride, gate0, gs, w.ptrs, slots, 0);
       }
@@ -892,6 +904,19 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   return MCR_OK;
 }
 
+// Fixed-order sum of the S partial backprojections of G slots; four pixels
+// per thread where rows and the output are 16-byte aligned.
+void launch_sum_parts(mcr_handle* h, int G, int S, long part_stride, float* out, long out_stride, int padded) {
+  const int n = h->geo.n;
+  const long n2 = (long)n * n;
+  if (n % 4 == 0 && (uintptr_t)out % 16 == 0 && out_stride % 4 == 0)
+    hipLaunchKernelGGL(k_sum_parts4, dim3(cdiv(n, 64), cdiv(n, 16), G), dim3(16, 16), 0, h->stream, n, h->pitch, S,
+                       h->parts, part_stride, n2, out, out_stride, padded);
+  else
+    hipLaunchKernelGGL(k_sum_parts, dim3(cdiv(n, 16), cdiv(n, 16), G), dim3(16, 16), 0, h->stream, n, h->pitch, S,
+                       h->parts, part_stride, n2, out, out_stride, padded);
+}
+
 template <typename T>
 mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_stride, T* out,
                               long out_stride, int padded, int subset = -1) {
@@ -903,29 +928,33 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
   dim3 grid(cdiv(n, 16), cdiv(n, 16), G), block(16, 16);
   if constexpr (std::is_same<T, float>::value) {
     // adj_px < 0: the quarter-turn kernel where the geometry allows it (even
-    // n and n_angles, all angles), else the tiled kernel with -adj_px pixels
-    const bool quad = h->tune.adj_px < 0 && quad_ok(h, ka, kb);
-    const int px = std::abs(h->tune.adj_px), S = px > 0 ? h->tune.adj_s : 1;
+    // n and n_angles, all angles), else the tiled kernel (quad_tiled_px)
+    const int code = h->tune.adj_px;
+    const bool quad = code < 0 && quad_ok(h, ka, kb);
+    const int px = code < 0 ? quad_tiled_px(code) : code, S = px > 0 ? h->tune.adj_s : 1;
     if (quad) {
       const long n2 = (long)n * n;
       float* dst = S > 1 ? h->parts : out;
       const long dst_stride = S > 1 ? n2 : out_stride;
       const long part_stride = n2 * h->nslots;
-      dim3 gq(cdiv(n / 2, 8 * px), cdiv(n / 2, 32), G * S);
-#define ADJQ(PX)                                                                                           \
-  hipLaunchKernelGGL(k_joseph_adj_quad<PX>, gq, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx, sino, \
-                     sino_stride, dst, dst_stride, padded, S, part_stride)
-      if (px == 2)
-        ADJQ(2);
-      else if (px == 4)
-        ADJQ(4);
+#define ADJQ(PX, TX, TY)                                                                                          \
+  hipLaunchKernelGGL((k_joseph_adj_quad<PX, TX, TY>), dim3(cdiv(n / 2, TX * PX), cdiv(n / 2, TY), G * S),         \
+                     dim3(TX * TY), 0, h->stream, geo_of<T>(h), w.angfx, sino, sino_stride, dst, dst_stride, padded, \
+                     S, part_stride)
+      if (code == -2)
+        ADJQ(2, 8, 32);
+      else if (code == -4)
+        ADJQ(4, 8, 32);
+      else if (code == -8)
+        ADJQ(8, 8, 32);
+      else if (code == -16)
+        ADJQ(4, 16, 32);
       else
-        ADJQ(8);
+        ADJQ(4, 16, 64);
 #undef ADJQ
       LAUNCH_OK();
       if (S > 1) {
-        hipLaunchKernelGGL(k_sum_parts, grid, block, 0, h->stream, n, h->pitch, S, h->parts, part_stride, n2,
-                           out, out_stride, padded);
+        launch_sum_parts(h, G, S, part_stride, out, out_stride, padded);
       }
     } else if (px > 0) {
       const long n2 = (long)n * n;
@@ -948,8 +977,7 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
 #undef ADJ
       LAUNCH_OK();
       if (S > 1) {
-        hipLaunchKernelGGL(k_sum_parts, grid, block, 0, h->stream, n, h->pitch, S, h->parts, part_stride, n2,
-                           out, out_stride, padded);
+        launch_sum_parts(h, G, S, part_stride, out, out_stride, padded);
       }
     } else {
       hipLaunchKernelGGL(k_joseph_adj_fx, grid, block, 0, h->stream, geo_of<T>(h), w.angfx, sino,
@@ -2108,8 +2136,9 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       h->tune.fwd = best.fwd;
       // quarter-turn kernels first (tiled ones where the geometry has no
       // quarter-turn symmetry: they then run as their tiled counterparts)
-      const int cand[][2] = {{-4, 8}, {-4, 12}, {-4, 16}, {-8, 16}, {-2, 8}, {8, 6}, {8, 8}, {8, 4}, {4, 4},
-                             {4, 6}, {4, 8}, {4, 2}, {4, 1}, {2, 2}, {2, 1}, {1, 1}, {0, 1}};
+      const int cand[][2] = {{-4, 8}, {-4, 12}, {-4, 16}, {-16, 8}, {-16, 16}, {-32, 16}, {-8, 16}, {-2, 8},
+                             {8, 6}, {8, 8}, {8, 4}, {4, 4}, {4, 6}, {4, 8}, {4, 2}, {4, 1}, {2, 2}, {2, 1}, {1, 1},
+                             {0, 1}};
       std::vector<float> at;
       for (const auto& c : cand) {
         if (st != MCR_OK) break;
@@ -2147,8 +2176,8 @@ mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t a
   if (h->dtype == MCR_F32 && !fwd_variant_ok(h, fwd))
     return fail(MCR_ERR_STATE, "the tiled forward's band windows do not fit this geometry");
   if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4 && adj_px != 8 && adj_px != -2 && adj_px != -4 &&
-      adj_px != -8)
-    return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2, 4, 8, -2, -4 or -8", adj_px);
+      adj_px != -8 && adj_px != -16 && adj_px != -32)
+    return fail(MCR_ERR_ARG, "pixels per thread %d must be 0, 1, 2, 4, 8, -2, -4, -8, -16 or -32", adj_px);
   if (adj_s < 1 || adj_s > kMaxShares) return fail(MCR_ERR_ARG, "angle shares %d must be in [1, %d]", adj_s, kMaxShares);
   h->tune.fwd = fwd;
   h->tune.adj_px = adj_px;

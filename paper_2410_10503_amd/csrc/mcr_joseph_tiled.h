@@ -473,22 +473,36 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 constexpr int kQuCap = 1024;       // staged float4 entries per band
 constexpr int kQuPieceLines = 64;  // target lines per block
 
-// The four outputs of the rays (k, j) of the planes; the reversed bin of
-// the centre bin of an odd detector is the bin itself, written once.
-template <int MODE>
-__device__ __forceinline__ void quad_epilogue(const float (&v)[4], int k, int j, int na, int nd, float* o, int gate,
-                                              const GateScalars<float>* gs, const GatePtrs<float>* gp) {
+// Sinogram index of the output of plane m for the ray (k, j), or -1 where
+// it repeats plane m - 2's (the centre bin of an odd detector is its own
+// reversal, written once).
+__device__ __forceinline__ long quad_index(int m, int k, int j, int na, int nd) {
   const int H = na >> 1;
   const int k2 = k < H ? k + H : k - H;
   const int jr = nd - 1 - j;
   const bool rev = k >= H;
-  project_epilogue<float, MODE>(v[0], (long)k * nd + j, o, gate, gs, gp);
-  project_epilogue<float, MODE>(v[1], (long)k2 * nd + (rev ? jr : j), o, gate, gs, gp);
-  if (jr != j) {
-    project_epilogue<float, MODE>(v[2], (long)k * nd + jr, o, gate, gs, gp);
-    project_epilogue<float, MODE>(v[3], (long)k2 * nd + (rev ? j : jr), o, gate, gs, gp);
+  if (m == 0) return (long)k * nd + j;
+  if (m == 1) return (long)k2 * nd + (rev ? jr : j);
+  if (jr == j) return -1;
+  return m == 2 ? (long)k * nd + jr : (long)k2 * nd + (rev ? j : jr);
+}
+
+template <int MODE>
+__device__ __forceinline__ void quad_epilogue(const float (&v)[4], int k, int j, int na, int nd, float* o, int gate,
+                                              const GateScalars<float>* gs, const GatePtrs<float>* gp) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const long idx = quad_index(m, k, j, na, nd);
+    if (idx >= 0) project_epilogue<float, MODE>(v[m], idx, o, gate, gs, gp);
   }
 }
+
+// Thread -> (angle slot kk of 8, bin of 32) of k_joseph_fwd_quad: each group
+// of 16 lanes holds 8 bins of two neighbouring angles, so its 16-byte LDS
+// reads stay within about 12 consecutive entries (no bank conflicts); each
+// wave still holds two angle slots times the 32 bins.
+__device__ __forceinline__ int quad_bin(int tid) { return (tid & 7) | (((tid >> 4) & 3) << 3); }
+__device__ __forceinline__ int quad_slot(int tid) { return ((tid >> 3) & 1) | ((tid >> 6) << 1); }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const AngleFx* __restrict__ ang,
@@ -514,9 +528,9 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
   const int4 ch = chunks[un.x];
   const long long Bm = (long long)(((unsigned long long)(unsigned)ch.w << 32) | (unsigned)ch.z);
   const int2 bb = make_int2(pc.x, pc.y);
-  const int kk = tid >> 5;
+  const int kk = quad_slot(tid);
   const int nb = (g.nd + 1) >> 1;
-  const int j = un.y * kShJD + (tid & 31);
+  const int j = un.y * kShJD + quad_bin(tid);
   const int jc = min(j, nb - 1);
   const AngleFx& A0 = ang[ch.x + min(kk, ch.y - 1)];
   const AngleFx& A1 = ang[ch.x + min(kk + 8, ch.y - 1)];
@@ -656,7 +670,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
 }
 
 // Sum of the partial sums of the multi-piece units of k_joseph_fwd_quad in
-// piece order, then the four outputs. grid (count, 1, G), block 256.
+// piece order, then the outputs; block y handles plane y (four times the
+// blocks of one launch per unit, for latency). grid (count, 4, G), block 256.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_joseph_fwd_quad_finish(Geo<float> g, const AngleFx* __restrict__ ang,
                                                                 const int4* __restrict__ chunks,
@@ -670,43 +685,37 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad_finish(Geo<float> g, co
   const int tid = threadIdx.x;
   const int4 un = units[multi[multi0 + blockIdx.x]];
   const int4 ch = chunks[un.x];
-  const int kk = tid >> 5;
+  const int kk = quad_slot(tid);
   const int nb = (g.nd + 1) >> 1;
-  const int j = un.y * kShJD + (tid & 31);
+  const int j = un.y * kShJD + quad_bin(tid);
   if (j >= nb) return;
-  const float* pu = part + blockIdx.z * part_stride + un.w;
-  float a0[4] = {0.0f, 0.0f, 0.0f, 0.0f}, a1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  // loads of up to 4 pieces in flight, then their sum in piece order
-  for (int q0 = 0; q0 < un.z; q0 += 4) {
-    float va[4][4], vb[4][4];
+  const int m = blockIdx.y;
+  const float* pu = part + blockIdx.z * part_stride + un.w + m * 512;
+  float a0 = 0.0f, a1 = 0.0f;
+  // loads of up to 8 pieces in flight, then their sum in piece order
+  for (int q0 = 0; q0 < un.z; q0 += 8) {
+    float va[8], vb[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       const bool in = q0 + q < un.z;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        va[q][m] = in ? pu[(q0 + q) * 2048 + m * 512 + tid] : 0.0f;
-        vb[q][m] = in ? pu[(q0 + q) * 2048 + m * 512 + 256 + tid] : 0.0f;
-      }
+      va[q] = in ? pu[(q0 + q) * 2048 + tid] : 0.0f;
+      vb[q] = in ? pu[(q0 + q) * 2048 + 256 + tid] : 0.0f;
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        a0[m] += va[q][m];
-        a1[m] += vb[q][m];
-      }
+    for (int q = 0; q < 8; ++q) {
+      a0 += va[q];
+      a1 += vb[q];
+    }
   }
   const int gate = slot_gate(slots, gate0);
   float* o = out + blockIdx.z * out_stride;
   if (kk < ch.y) {
-    const float ds = ang[ch.x + kk].ds;
-    const float v[4] = {ds * a0[0], ds * a0[1], ds * a0[2], ds * a0[3]};
-    quad_epilogue<MODE>(v, ch.x + kk, j, g.na, g.nd, o, gate, gs, gp);
+    const long idx = quad_index(m, ch.x + kk, j, g.na, g.nd);
+    if (idx >= 0) project_epilogue<float, MODE>(ang[ch.x + kk].ds * a0, idx, o, gate, gs, gp);
   }
   if (kk + 8 < ch.y) {
-    const float ds = ang[ch.x + kk + 8].ds;
-    const float v[4] = {ds * a1[0], ds * a1[1], ds * a1[2], ds * a1[3]};
-    quad_epilogue<MODE>(v, ch.x + kk + 8, j, g.na, g.nd, o, gate, gs, gp);
+    const long idx = quad_index(m, ch.x + kk + 8, j, g.na, g.nd);
+    if (idx >= 0) project_epilogue<float, MODE>(ang[ch.x + kk + 8].ds * a1, idx, o, gate, gs, gp);
   }
 }
 
@@ -898,42 +907,48 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
 // and the weights are shared. Per four pairs: a 64-bit add, one conversion,
 // two clamped FMAs for the weights, two 16-byte LDS reads and eight FMAs.
 //
-// A thread accumulates PX pixels of a row 8 columns apart (columns C0 + tx +
-// 8p), so that the eight lanes of a row read neighbouring 16-byte entries
-// (distinct LDS banks) rather than entries PX bins apart.
-// grid (ceil(n/2/(8*PX)), ceil(n/2/32), G*S), block 256; all angles. S > 1:
-// partial images as in k_joseph_adj_lds.
+// A block owns a TY x TX*PX tile of the quadrant; a thread accumulates PX
+// pixels of a row TX columns apart (columns C0 + tx + TX p), so that the TX
+// lanes of a row read neighbouring 16-byte entries (distinct LDS banks)
+// rather than entries PX bins apart.
+// grid (ceil(n/2/(TX*PX)), ceil(n/2/TY), G*S), block TX*TY; all angles.
+// S > 1: partial images as in k_joseph_adj_lds.
 constexpr int kQuadKC = 16;  // angles per staged chunk
 
-// Bins staged per angle: a 32 x 8PX tile projects onto at most
-// sqrt(31^2 + (8PX - 1)^2) bins (< 44 for PX = 4), and the window needs 3 more.
-template <int PX>
+// Bins staged per angle for a TY x TX*PX tile: its pixels project onto at most
+// sqrt((TY - 1)^2 + (TX PX - 1)^2) bins, and the window needs 3 more (the
+// bin below the lowest, the second bin of the highest, rounding); rounded up
+// to a multiple of 16.
+template <int PX, int TX, int TY>
 constexpr int quad_window() {
-  return PX == 8 ? 80 : 48;
+  int span = 0;
+  while (span * span < (TY - 1) * (TY - 1) + (TX * PX - 1) * (TX * PX - 1)) ++span;
+  return (span + 3 + 15) / 16 * 16;
 }
 
-template <int PX>
-__global__ __launch_bounds__(256) void k_joseph_adj_quad(Geo<float> g, const AngleFx* __restrict__ ang,
-                                                         const float* __restrict__ sino, long sino_stride,
-                                                         float* __restrict__ out, long out_stride, int padded,
-                                                         int S, long part_stride) {
-  constexpr int kW = quad_window<PX>();
+template <int PX, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const AngleFx* __restrict__ ang,
+                                                             const float* __restrict__ sino, long sino_stride,
+                                                             float* __restrict__ out, long out_stride, int padded,
+                                                             int S, long part_stride) {
+  constexpr int NT = TX * TY;
+  constexpr int kW = quad_window<PX, TX, TY>();
   constexpr int KC = kQuadKC;
-  constexpr int kPer = KC * kW / 256;  // staged entries per thread
-  static_assert(KC * kW % 256 == 0, "whole entries per thread");
+  constexpr int kPer = (KC * kW + NT - 1) / NT;  // staged entries per thread
+  constexpr int kTab = TY + TX;                  // table entries per angle
   __shared__ float4 sy[KC * kW];
-  __shared__ long long s_row[KC][32];
-  __shared__ long long s_col[KC][8];
+  __shared__ long long s_row[KC][TY];
+  __shared__ long long s_col[KC][TX];
   __shared__ long long s_step[KC];
   __shared__ float4 s_w[KC];
   __shared__ int s_jb[2][KC];
   __shared__ float s_ds[2][KC];
   const int tid = threadIdx.x;
-  const int tx = tid & 7, ty = tid >> 3;
+  const int tx = tid % TX, ty = tid / TX;
   const int L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const int share = L % S, rest = L / S;
   const int tiles = gridDim.x * gridDim.y, tile = rest % tiles, slot = rest / tiles;
-  const int R0 = (tile / gridDim.x) * 32, C0 = (tile % gridDim.x) * (8 * PX);
+  const int R0 = (tile / gridDim.x) * TY, C0 = (tile % gridDim.x) * (TX * PX);
   const int na = g.na, H = na >> 1, nd = g.nd;
   const int kbeg = (int)((long)na * share / S), kend = (int)((long)na * (share + 1) / S);
   const float* s = sino + slot * sino_stride;
@@ -946,7 +961,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_quad(Geo<float> g, const Ang
     if (tid < kcn) {
       const AngleFx A = ang[k0 + tid];
       const int pmin = A.rows ? C0 : R0, lmin = A.rows ? R0 : C0;
-      const int pext = A.rows ? 8 * PX - 1 : 31, lext = A.rows ? 31 : 8 * PX - 1;
+      const int pext = A.rows ? TX * PX - 1 : TY - 1, lext = A.rows ? TY - 1 : TX * PX - 1;
       const long long u00 = A.U0 + (long long)pmin * A.P + (long long)lmin * A.Q;
       const long long up = (long long)pext * A.P, ul = (long long)lext * A.Q;
       const long long umin = min(min(u00, u00 + up), min(u00 + ul, u00 + up + ul));
@@ -960,7 +975,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_quad(Geo<float> g, const Ang
   auto fetch = [&](int k0, int kcn, const int* jbs) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int i = tid + e * 256;
+      const int i = tid + e * NT;
       const int kc = i / kW, q = i % kW;
       float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (kc < kcn) {
@@ -996,25 +1011,27 @@ __global__ __launch_bounds__(256) void k_joseph_adj_quad(Geo<float> g, const Ang
     const int kcn1 = min(KC, kend - k1);
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
-      const int i = tid + e * 256;
-      const int kc = i / kW;
-      const float sc = kc < kcn ? s_ds[cur][kc] : 0.0f;
-      sy[i] = make_float4(pre[e].x * sc, pre[e].y * sc, pre[e].z * sc, pre[e].w * sc);
+      const int i = tid + e * NT;
+      if (KC * kW % NT == 0 || i < KC * kW) {
+        const int kc = i / kW;
+        const float sc = kc < kcn ? s_ds[cur][kc] : 0.0f;
+        sy[i] = make_float4(pre[e].x * sc, pre[e].y * sc, pre[e].z * sc, pre[e].w * sc);
+      }
     }
-    for (int i = tid; i < kcn * 40; i += 256) {
-      const int kc = i / 40, e = i % 40;
+    for (int i = tid; i < kcn * kTab; i += NT) {
+      const int kc = i / kTab, e = i % kTab;
       const AngleFx A = ang[k0 + kc];
       const long long sc = A.rows ? A.P : A.Q;  // along a row (column step)
       const long long sr = A.rows ? A.Q : A.P;  // along a column (row step)
-      if (e < 32) {
+      if (e < TY) {
         const int pmin = A.rows ? C0 : R0, lmin = A.rows ? R0 : C0;
         const long long base = A.U0 + (long long)pmin * A.P + (long long)lmin * A.Q -
                                ((long long)s_jb[cur][kc] << 32) + ((long long)(kc * kW) << 32);
         s_row[kc][e] = base + (long long)e * sr;
       } else {
-        s_col[kc][e - 32] = (long long)(e - 32) * sc;
-        if (e == 32) {
-          s_step[kc] = 8 * sc;
+        s_col[kc][e - TY] = (long long)(e - TY) * sc;
+        if (e == TY) {
+          s_step[kc] = TX * sc;
           s_w[kc] = make_float4(A.na32, A.pa32, A.oma, 0.0f);
         }
       }
@@ -1068,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_quad(Geo<float> g, const Ang
   if (r >= h) return;
 #pragma unroll
   for (int p = 0; p < PX; ++p) {
-    const int c = C0 + tx + 8 * p;
+    const int c = C0 + tx + TX * p;
     if (c >= h) continue;
     // p, R p, R^2 p, R^3 p
     const int rr[4] = {r, c, n - 1 - r, n - 1 - c};
@@ -1083,6 +1100,35 @@ __global__ __launch_bounds__(256) void k_joseph_adj_quad(Geo<float> g, const Ang
         out[slot * out_stride + (long)rr[m] * n + cc[m]] = acc[m][p];
     }
   }
+}
+
+// Sum of S partial images (fixed order) into the padded or unpadded output,
+// four pixels of a row per thread (n a multiple of 4: every row and the
+// padded rows start 16-byte aligned). grid (ceil(n/64), ceil(n/16), G),
+// block (16, 16).
+__global__ __launch_bounds__(256) void k_sum_parts4(int n, int pitch, int S, const float* __restrict__ parts,
+                                                    long part_stride, long slot_stride, float* __restrict__ out,
+                                                    long out_stride, int padded) {
+  const int c = (blockIdx.x * 16 + threadIdx.x) * 4;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c >= n || r >= n) return;
+  const long q = (long)r * n + c;
+  const float* src = parts + blockIdx.z * slot_stride;
+  float4 a[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    a[s] = s < S ? *(const float4*)(src + s * part_stride + q) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    v.x += a[s].x;
+    v.y += a[s].y;
+    v.z += a[s].z;
+    v.w += a[s].w;
+  }
+  float* o = padded ? out + blockIdx.z * out_stride + (long)(r + kPad) * pitch + c + kPad
+                    : out + blockIdx.z * out_stride + q;
+  *(float4*)o = v;
 }
 
 // Sum of S partial images (fixed order) into the padded or unpadded output.

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
   const float* uy = ux + plane_stride;
   const T* src = x + slice * x_stride;
   T* dst = wP + blockIdx.z * w_stride + origin;
-  T* dstT = wTP + blockIdx.z * w_stride + origin;
+  T* dstT = wTP ? wTP + blockIdx.z * w_stride + origin : nullptr;
   const int c = blockIdx.x * 32 + threadIdx.x;
   {
     const int r = blockIdx.y * 32 + threadIdx.y;
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
   const int rr = blockIdx.y * 32 + threadIdx.x;
   if (cc < n && rr < n) {
     const T v = tile[threadIdx.x][threadIdx.y];  // w(rr, cc)
-    dstT[(long)cc * pitch + rr] = v;
+    if (wTP) dstT[(long)cc * pitch + rr] = v;
     if (wQ) {  // P_1 takes it at (n - 1 - cc, rr), P_3 at (cc, n - 1 - rr)
       T* q = wQ + blockIdx.z * q_stride + origin;
       q[(long)(n - 1 - cc) * pitch + rr] = v;

@@ -53,10 +53,15 @@ def test_spdhg_fp64_128_rigid4_20_epochs():
     _compare(gst, ost, 1e-11)
 
 
+# (forward, adjoint pixels per thread, angle shares): the handle's default
+# (line-sheared forward, tiled adjoint) and the quarter-turn pair
+@pytest.mark.parametrize("variant", [None, (4, -4, 8)])
 @pytest.mark.parametrize("kind", ["rigid", "field"])
-def test_spdhg_and_pdhg_fp32_50_epochs(kind):
+def test_spdhg_and_pdhg_fp32_50_epochs(kind, variant):
     P = Problem(64, 96, 92, 4, kind, alpha=1e-3, field_scale=1.0)
     h = P.handle(torch.float32)
+    if variant is not None:
+        h.set_variant(*variant)
     d32 = [dev(v, torch.float32) for v in P.d]
     sig, tau, th, p = _steps(P)
     ost = osp.State.zeros(P.n, P.N, P.na, P.nd)
@@ -172,11 +177,18 @@ def test_gpu_converges_to_saddle_point_in_paper_regime():
     assert slope_p <= np.log(rate_p) + 0.02
 
 
-def test_full_size_one_iteration_from_random_state():
+@pytest.mark.parametrize("variant", ["autotune", (3, 8, 6)])
+def test_full_size_one_iteration_from_random_state(variant):
     # 512^2, 720 x 730, 16 non-rigid gates: one SPDHG iteration from a random
-    # state, every element of x, y_i, z, z-bar against the oracle
+    # state, every element of x, y_i, z, z-bar against the oracle; with the
+    # variants the autotuner keeps (those the benchmark times) and with the
+    # line-sheared forward and tiled adjoint
     P = Problem(512, 720, 730, 16, "field", phantom="chest")
     h = P.handle(torch.float32)
+    if variant == "autotune":
+        h.autotune(1)
+    else:
+        h.set_variant(*variant)
     rng = np.random.default_rng(3)
     x = f32(P.x_true + 0.1 * rng.standard_normal((512, 512)))
     z = f32(0.01 * rng.standard_normal((512, 512)))

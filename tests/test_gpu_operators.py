@@ -41,7 +41,7 @@ VARIANTS = [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 2), (1, 4, 1), (1, 4, 4), (0
             # quarter-turn adjoint (falls back to the tiled one on odd sizes)
             (3, -4, 6), (3, -2, 1), (3, -8, 8), (0, -4, 3), (2, -2, 5),
             # quarter-turn forward (unavailable on odd sizes)
-            (4, -4, 8), (4, 4, 4), (4, 8, 6), (4, -2, 16)]
+            (4, -4, 8), (4, 4, 4), (4, 8, 6), (4, -2, 16), (4, -16, 8), (4, -32, 16), (3, -32, 3)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -68,7 +68,7 @@ def test_autotune_keeps_parity():
     P = Problem(128, 120, 182, 3, "field")
     h = P.handle(torch.float32)
     choice = h.autotune(1)
-    assert choice["fwd"] in (0, 1, 2, 3, 4) and choice["adj_px"] in (0, 1, 2, 4, 8, -2, -4, -8)
+    assert choice["fwd"] in (0, 1, 2, 3, 4) and choice["adj_px"] in (0, 1, 2, 4, 8, -2, -4, -8, -16, -32)
     assert 1 <= choice["adj_shares"] <= 16
     assert h.autotune(3) is not None
     x = f32(synth.ellipse_phantom(128, 1))
@@ -165,9 +165,11 @@ def test_determinism():
 
 def test_full_size_field_gate():
     # 512^2, 720 angles x 730 bins, the headline chest phantom and one
-    # non-rigid gate, in the configuration the benchmark times
+    # non-rigid gate, in the configuration the benchmark times (the variants
+    # the autotuner keeps)
     P = Problem(512, 720, 730, 16, "field", phantom="chest")
     h = P.handle(torch.float32)
+    h.autotune(1)
     i = 11
     x = P.x_true
     s = host(h.apply_Ai(i, dev(x, torch.float32)))
@@ -184,6 +186,7 @@ def test_full_size_rigid_samples():
     # D_i^T b against the oracle, one by one
     P = Problem(512, 720, 730, 16, "rigid")
     h = P.handle(torch.float32)
+    h.autotune(1)
     x = P.x_true
     xd = dev(x, torch.float32)
     rng = np.random.default_rng(0)
@@ -264,7 +267,7 @@ def test_degenerate_geometries(geom):
         h = P.handle(dtype)
         variants = [None] if dtype == torch.float64 else [(0, 0, 1), (1, 1, 1), (2, 2, 2), (3, 4, 1), (3, 8, 3),
                                                           (3, -4, 1), (3, -2, 3), (3, -8, 8), (4, -4, 1),
-                                                          (4, 8, 2)]
+                                                          (4, 8, 2), (4, -16, 1), (4, -32, 5)]
         for v in variants:
             if v is not None:
                 try:

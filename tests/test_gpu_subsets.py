@@ -57,7 +57,7 @@ def test_fp64_block_iterations_match_oracle(kind, M):
 
 
 # (forward variant, adjoint pixels per thread, angle shares)
-@pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1), (4, -4, 8)])
+@pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1), (4, -4, 8), (4, -32, 16)])
 def test_fp32_block_iterations_match_oracle(variant):
     P = Problem(64, 96, 92, 4, "field", alpha=1e-3)
     M = 3
@@ -80,8 +80,10 @@ def test_one_subset_block_iterations_equal_gate_iterations():
     sig, tau, th, _ = osp.step_sizes_spdhg([2.0 * 96 * 64] * 3, P.alpha, 3)
     p = [1.0 / 3] * 3
     seq = [int(g) for g in synth.gate_sequence(3, 1, 0, length=7)]
-    for dtype in (torch.float32, torch.float64):
+    for dtype, variant in ((torch.float32, None), (torch.float32, (4, -4, 8)), (torch.float64, None)):
         h = P.handle(dtype)
+        if variant is not None:  # one subset holds all angles: the quarter-turn kernels run
+            h.set_variant(*variant)
         d = [dev(v, dtype) for v in P.d]
         a, b = h.zero_state(), h.zero_state()
         h.spdhg_iterate(a, d, P.alpha, sig, tau, th, p, seq)
