@@ -27,9 +27,11 @@ def _setup(kind, n=48, na=60, nd=70, N=3, K=6, field_scale=1.0):
     return P, sig, tau, th, p, seq, x0, target
 
 
-def _gpu_grad(P, dtype, sig, tau, th, p, seq, x0, target):
+def _gpu_grad(P, dtype, sig, tau, th, p, seq, x0, target, variant=None):
     from paper_2410_10503_amd.autograd import unrolled_spdhg
     h = P.handle(dtype)
+    if variant is not None:
+        h.set_variant(*variant)
     if P.kind == "rigid":
         mot = torch.tensor(P.params, dtype=torch.float64, device="cuda", requires_grad=True)
     else:
@@ -42,15 +44,17 @@ def _gpu_grad(P, dtype, sig, tau, th, p, seq, x0, target):
     return float(loss), host(x0t.grad), mot.grad.double().cpu().numpy(), h
 
 
+# float32 projector variants: the handle's default and the quarter-turn pair
+@pytest.mark.parametrize("variant", [None, (4, -4, 8)])
 @pytest.mark.parametrize("kind", ["rigid", "field"])
-def test_gradients_match_oracle(kind):
+def test_gradients_match_oracle(kind, variant):
     P, sig, tau, th, p, seq, x0, target = _setup(kind)
     L_o, gx_o, gm_o = ograd.unrolled_loss_and_grad(P.ops, x0, P.d, P.alpha, sig, tau, th, p, seq, target)
     L64, gx64, gm64, _ = _gpu_grad(P, torch.float64, sig, tau, th, p, seq, x0, target)
     assert abs(L64 - L_o) <= 1e-11 * abs(L_o)
     assert rel(gx64, gx_o) < 1e-9
     assert rel(gm64, gm_o) < 1e-8
-    L32, gx32, gm32, _ = _gpu_grad(P, torch.float32, sig, tau, th, p, seq, x0, target)
+    L32, gx32, gm32, _ = _gpu_grad(P, torch.float32, sig, tau, th, p, seq, x0, target, variant)
     assert abs(L32 - L_o) <= 1e-5 * abs(L_o)
     assert rel(gx32, gx_o) < 1e-4
     assert rel(gm32, gm_o) < 1e-3
@@ -127,6 +131,7 @@ def test_full_size_rigid16_ten_iterations():
 
     L64, gx64, gm64 = run(h64, torch.float64, d64, P.params, True)
     h32 = P.handle(torch.float32)
+    h32.autotune(1)  # the variants the benchmark's differentiation runs
     L32, gx32, gm32 = run(h32, torch.float32, d32, P.params, True)
     assert abs(L32 - L64) <= 1e-5 * L64
     assert float(torch.linalg.norm(gx32 - gx64) / torch.linalg.norm(gx64)) < 1e-3
