@@ -18,11 +18,14 @@ Everything is float64 NumPy, written from the paper's definitions:
   the objective, the duality gap and the distance plotted in Fig. 1;
 * `grad`      - the gradient of a loss through unrolled SPDHG iterations with
   respect to the starting image and the motion parameters (transposed iteration
-  map).
+  map);
+* `subsets`   - SPDHG over gates x angle subsets;
+* `registration` - rigid registration of a gate's image to the reference
+  (the preliminary step of Section I; the reading is stated there).
 
 Where the paper is silent or garbled, the readings are listed in the design
 notes: step (i) uses the extrapolated z-bar, step (iii) extrapolates from z,
 f_i(u) = |u - d_i|^2 / N and g(x) = alpha |x|^2.
 """
-from . import projector, warp, spdhg, grad, subsets  # noqa: F401
+from . import projector, warp, spdhg, grad, subsets, registration  # noqa: F401
 from .operators import GatedOperators  # noqa: F401
