@@ -209,6 +209,26 @@ mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, co
                                 void* grad_motion);
 
 /* ---------------------------------------------------------------------------
+ * Rigid registration: the preliminary step of Section I, which estimates the
+ * displacement map from the reference motion state to each gate (the paper
+ * does not say how). Reading: the rigid parameters (phi, t_x, t_y) of gate
+ * `gate` minimise E = |D(theta) ref - target|^2 / 2 (D the library's warp),
+ * by gradient descent in the scaled coordinates (phi (n - 1) / 2, t_x, t_y)
+ * (pixels at the image's edge) with Barzilai-Borwein step lengths (the first
+ * trial moves 1 px) and Armijo backtracking (sufficient decrease 1e-4, at most
+ * 40 halvings); it stops after the first accepted step shorter than tol
+ * pixels, at a zero gradient, or after max_iter steps. ref, target: device
+ * [n][n] in the handle's dtype. params: host double[3], the start on entry and
+ * the result on return; the gate's motion is set to the result. loss (may be
+ * NULL): E at the result; steps (may be NULL): steps taken. The gate must be
+ * rigid. Synchronises the stream at every evaluation (warp, residual, FP64
+ * squared norm, motion gradient).
+ * ------------------------------------------------------------------------- */
+mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, const void* target,
+                              double* params, int32_t max_iter, double tol, double* loss,
+                              int32_t* steps);
+
+/* ---------------------------------------------------------------------------
  * FP64 diagnostics (Theorem 1 and the model of Section II-A), computed on the
  * device in double precision whatever the handle's dtype; they synchronise.
  * ------------------------------------------------------------------------- */

@@ -297,6 +297,17 @@ class Handle:
         _lib.check(self._lib.mcr_warp_motion_grad(self._h, int(gate), self._img(img, "img"), self._img(v, "v"),
                                                   self._grad_motion_ptr(gate, grad_motion)))
 
+    def register_rigid(self, gate: int, ref, target, params=(0.0, 0.0, 0.0), max_iter: int = 200,
+                       tol: float = 1e-6):
+        """Rigid parameters (phi, t_x, t_y) of `gate` minimising |D ref - target|^2 / 2, from
+        `params`; the gate's motion is set to them. Returns (params, energy, steps)."""
+        self._sync_stream()
+        th = (ctypes.c_double * 3)(*[float(v) for v in params])
+        E, k = ctypes.c_double(), ctypes.c_int32()
+        _lib.check(self._lib.mcr_register_rigid(self._h, int(gate), self._img(ref, "ref"), self._img(target, "target"),
+                                                th, int(max_iter), float(tol), ctypes.byref(E), ctypes.byref(k)))
+        return (th[0], th[1], th[2]), E.value, k.value
+
     # -- FP64 diagnostics ----------------------------------------------------
     def power_norm_sq(self, gate: int, v0, max_iter: int = 500, rtol: float = 1e-12):
         """|A_gate|^2 (gate >= 0) or the stacked |(A_1; ...; A_N)|^2 (gate = -1)."""

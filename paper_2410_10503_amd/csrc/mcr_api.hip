@@ -20,6 +20,7 @@
 #include "mcr_kernels.h"
 #include "mcr_joseph_tiled.h"
 #include "mcr_grad.h"
+#include "mcr_register.h"
 
 using namespace mcr;
 
@@ -1314,6 +1315,70 @@ mcr_status pdhg_impl(mcr_handle* h, const mcr_state* st, const void* const* d, d
   return iteration<T>(h, st, 0, h->N, true, false, t, cx);
 }
 
+// Rigid registration of a gate's image to the reference: gradient descent on
+// E(theta) = |D(theta) ref - target|^2 / 2 in the scaled coordinates
+// s = (phi (n - 1) / 2, t_x, t_y) with Barzilai-Borwein steps and Armijo
+// backtracking (see mcr_register_rigid). Each evaluation: the warp, the
+// residual, its squared norm (FP64 reduction) and J^T r (motion gradient).
+template <typename T>
+mcr_status register_rigid_impl(mcr_handle* h, int gate, const void* ref, const void* target, double* params,
+                               int max_iter, double tol, double* loss, int32_t* steps) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  const double scale[3] = {(n - 1) / 2.0, 1.0, 1.0};
+  double* gdev = h->red_out + 1;  // result slots 1..3
+  auto eval = [&](const double* s, double& E, double* g) -> mcr_status {
+    for (int m = 0; m < 3; ++m) h->motion[gate].rigid[m] = s[m] / scale[m];
+    STATUS_OK(upload_motion<T>(h));
+    STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)ref));
+    hipLaunchKernelGGL(k_residual_padded<T>, dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n,
+                       h->pitch, w.wP, (const T*)target, w.bP);
+    LAUNCH_OK();
+    STATUS_OK((launch_reduce<T, T, 0>(h, h->padded, w.bP, w.bP, 0)));
+    HIP_OK(hipMemsetAsync(gdev, 0, 3 * sizeof(double), h->stream));
+    STATUS_OK(launch_motion_grad<T>(h, gate, w.bP, (const T*)ref, gdev));
+    STATUS_OK(read_results(h, 4));
+    E = 0.5 * h->red_host[0];
+    for (int m = 0; m < 3; ++m) g[m] = h->red_host[1 + m] / scale[m];
+    return MCR_OK;
+  };
+  auto norm = [](const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
+  double s[3], g[3], E = 0.0;
+  for (int m = 0; m < 3; ++m) s[m] = params[m] * scale[m];
+  STATUS_OK(eval(s, E, g));
+  double gn = norm(g);
+  double alpha = gn > 0 ? 1.0 / gn : 1.0;  // the first trial moves 1 px
+  int k = 0;
+  while (k < max_iter && gn > 0) {
+    double sn[3], gnew[3], En = 0.0;
+    for (int t = 0; t < 41; ++t) {  // Armijo backtracking
+      for (int m = 0; m < 3; ++m) sn[m] = s[m] - alpha * g[m];
+      STATUS_OK(eval(sn, En, gnew));
+      if (En <= E - 1e-4 * alpha * gn * gn) break;
+      alpha *= 0.5;
+    }
+    ++k;
+    const double step = alpha * gn;
+    double ds[3], dg[3];
+    for (int m = 0; m < 3; ++m) {
+      ds[m] = sn[m] - s[m];
+      dg[m] = gnew[m] - g[m];
+      s[m] = sn[m];
+      g[m] = gnew[m];
+    }
+    E = En;
+    gn = norm(g);
+    if (step < tol) break;
+    const double sy = ds[0] * dg[0] + ds[1] * dg[1] + ds[2] * dg[2];
+    alpha = sy > 0 ? (ds[0] * ds[0] + ds[1] * ds[1] + ds[2] * ds[2]) / sy : 2.0 * alpha;  // Barzilai-Borwein
+  }
+  for (int m = 0; m < 3; ++m) params[m] = h->motion[gate].rigid[m] = s[m] / scale[m];
+  STATUS_OK(upload_motion<T>(h));
+  if (loss) *loss = E;
+  if (steps) *steps = k;
+  return MCR_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Operators
 // ---------------------------------------------------------------------------
@@ -1946,6 +2011,21 @@ mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, co
   STATUS_OK(check_ptr(v, "v"));
   STATUS_OK(check_ptr(grad_motion, "grad_motion"));
   return DISPATCH(motion_grad_impl, h, gate, img, v, grad_motion);
+}
+
+mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, const void* target, double* params,
+                              int32_t max_iter, double tol, double* loss, int32_t* steps) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(ref, "ref"));
+  STATUS_OK(check_ptr(target, "target"));
+  STATUS_OK(check_ptr(params, "params"));
+  if (h->motion[gate].kind != MCR_MOTION_RIGID) return fail(MCR_ERR_ARG, "gate %d is not rigid", gate);
+  for (int m = 0; m < 3; ++m)
+    if (!std::isfinite(params[m])) return fail(MCR_ERR_ARG, "params[%d] is not finite", m);
+  if (max_iter < 0) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 0", max_iter);
+  if (!(tol >= 0) || !std::isfinite(tol)) return fail(MCR_ERR_ARG, "tol must be finite and >= 0");
+  return DISPATCH(register_rigid_impl, h, gate, ref, target, params, max_iter, tol, loss, steps);
 }
 
 }  // extern "C"

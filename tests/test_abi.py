@@ -127,3 +127,9 @@ def test_block_step_sizes_match_oracle(lib, N, M, alpha):
 
 def test_set_subsets_rejects_null_handle(lib):
     assert lib.mcr_set_subsets(None, 2) == _lib.MCR_ERR_ARG
+
+
+def test_register_rigid_rejects_null_handle(lib):
+    th = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    assert lib.mcr_register_rigid(None, 0, None, None, th, 10, 1e-6, None, None) == _lib.MCR_ERR_ARG
+    assert b"null handle" in lib.mcr_last_error()

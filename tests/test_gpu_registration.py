@@ -1,0 +1,96 @@
+"""GPU parity of the rigid registration (mcr_register_rigid) against the FP64
+oracle (oracle/registration.py, the same reading of the preliminary step of
+Section I), and recovery of known rigid motions, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+from scipy import ndimage
+
+from gpu_common import Problem, dev, f32, need_gpu
+import synth
+from oracle import registration as oreg, warp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _ref(n, seed=3, blur=1.5):
+    # a smooth reference (blurred ellipses), rounded to float32 for both sides
+    return f32(ndimage.gaussian_filter(synth.ellipse_phantom(n, seed).astype(np.float64), blur * n / 64))
+
+
+def _target(ref, theta):
+    return f32(warp.warp(ref, *warp.rigid_positions(ref.shape[0], *theta)))
+
+
+def _px(theta, n):
+    return np.asarray(theta, float) * np.array([(n - 1) / 2.0, 1.0, 1.0])
+
+
+@pytest.mark.parametrize("theta", [(0.05, 1.7, -2.3), (-0.087, 3.9, 0.6)])
+def test_fp64_registration_matches_oracle(theta):
+    n = 64
+    P = Problem(n, 40, 92, 2, "rigid")
+    ref = _ref(n)
+    tgt = _target(ref, theta)
+    th_o, E_o, k_o = oreg.register_rigid(ref, tgt, max_iter=300, tol=1e-9)
+    h = P.handle(torch.float64)
+    th, E, k = h.register_rigid(1, dev(ref, torch.float64), dev(tgt, torch.float64), max_iter=300, tol=1e-9)
+    # the same iteration on the same data: the same path up to rounding
+    assert k == k_o
+    assert np.abs(_px(th, n) - _px(th_o, n)).max() < 1e-9
+    assert np.abs(_px(th, n) - _px(theta, n)).max() < 1e-6
+    assert abs(E - E_o) <= 1e-12 * float(np.sum(tgt ** 2))
+    # the gate's motion is the result: D ref reproduces the target
+    w = h.warp(1, dev(ref, torch.float64)).cpu().numpy()
+    assert np.abs(w - tgt).max() < 1e-6 * np.abs(tgt).max()
+
+
+def test_energy_at_start_matches_oracle():
+    n = 64
+    P = Problem(n, 40, 92, 2, "rigid")
+    ref, tgt = _ref(n), _target(_ref(n, seed=5), (0.02, 0.5, -0.5))
+    start = (0.03, 1.2, -0.7)
+    E_o, _ = oreg.energy_and_grad(ref, tgt, start)
+    for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        h = P.handle(dtype)
+        th, E, k = h.register_rigid(0, dev(ref, dtype), dev(tgt, dtype), params=start, max_iter=0)
+        assert k == 0 and th == start
+        assert abs(E - E_o) <= bar * E_o
+
+
+def test_full_size_fp32_recovers_sixteen_gates():
+    # 512^2, the 16 rigid gates of the 512^2 rigid workload (rotations up to
+    # 8 degrees, shifts up to 10 px): each gate's image is the reference warped
+    # by its motion (oracle warp); registration from zero in float32
+    n = 512
+    P = Problem(n, 720, 730, 16, "rigid")
+    h = P.handle(torch.float32)
+    ref = _ref(n)
+    rd = dev(ref, torch.float32)
+    for i in range(16):
+        tgt = _target(ref, P.params[i])
+        th, E, k = h.register_rigid(i, rd, dev(tgt, torch.float32), max_iter=300, tol=1e-5)
+        err = np.abs(_px(th, n) - _px(P.params[i], n)).max()
+        assert err < 2e-3, (i, th, P.params[i], err, k)
+
+
+def test_registration_arguments():
+    from paper_2410_10503_amd import McrError
+    P = Problem(32, 20, 48, 2, "field")
+    h = P.handle(torch.float32)
+    x = torch.zeros(32, 32, device="cuda")
+    with pytest.raises(McrError, match="not rigid"):
+        h.register_rigid(0, x, x)
+    R = Problem(32, 20, 48, 2, "rigid")
+    hr = R.handle(torch.float32)
+    with pytest.raises(McrError, match="params"):
+        hr.register_rigid(0, x, x, params=(float("nan"), 0.0, 0.0))
+    with pytest.raises(McrError, match="max_iter"):
+        hr.register_rigid(0, x, x, max_iter=-1)
+    th, E, k = hr.register_rigid(1, x, x)  # zero images: zero gradient, no step
+    assert k == 0 and E == 0.0
