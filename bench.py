@@ -236,6 +236,32 @@ def autograd_measurement(reps: int = 3):
     return out
 
 
+def registration_measurement():
+    """Rigid registration (the preliminary step of Section I) of the 16 gate
+    images of the 512^2 rigid workload to the reference image, each from zero:
+    the gate images are the reference warped by the workload's motion."""
+    import torch
+    import synth
+    from paper_2410_10503_amd import Handle
+    wl = synth.WORKLOADS["ellipses512_rigid16"]
+    N = wl.n_gates
+    params = wl.rigid()
+    h = Handle(wl.n, wl.n_angles, wl.n_det, [("rigid", tuple(params[i])) for i in range(N)], dtype=torch.float32)
+    ref = torch.from_numpy(wl.image()).cuda()
+    targets = [h.warp(i, ref).clone() for i in range(N)]
+    torch.cuda.synchronize()
+    scale = np.array([(wl.n - 1) / 2.0, 1.0, 1.0])
+    t0 = time.perf_counter()
+    res = [h.register_rigid(i, ref, targets[i], max_iter=300, tol=1e-5) for i in range(N)]
+    dt = time.perf_counter() - t0
+    err = max(float(np.abs((np.array(th) - params[i]) * scale).max()) for i, (th, _, _) in enumerate(res))
+    h.close()
+    return {"workload": "16 rigid gates at 512^2 (rotations up to 8 deg, shifts up to 10 px), each gate image "
+                        "registered to the reference from zero, float32",
+            "ms_per_gate": 1e3 * dt / N, "steps_mean": float(np.mean([k for _, _, k in res])),
+            "max_error_px": err}
+
+
 def subsets_measurement(h, d, wl, gate_norms, v0, M: int = 4, epochs: int = 3):
     """Sampling over gates x angle subsets (the next step named in the
     Conclusions) on the same handle and data: M contiguous angle subsets,
@@ -402,6 +428,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64 x 256^2 measurement")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--no-subsets", action="store_true", help="skip the gates x angle-subsets measurement")
+    ap.add_argument("--no-registration", action="store_true", help="skip the rigid-registration measurement")
     ap.add_argument("--variant", default=None,
                     help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
                          "(counter runs serialise dispatches, which would change the autotuner's choice)")
@@ -617,6 +644,10 @@ def main():
         log("differentiation through 10 unrolled iterations ...")
         out["autograd"] = autograd_measurement()
         log(f"autograd: {out['autograd']}")
+    if not args.no_registration:
+        log("rigid registration of 16 gates ...")
+        out["registration"] = registration_measurement()
+        log(f"registration: {out['registration']}")
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on one iteration ...")
         out["cpu_baseline"] = cpu_baseline(wl, x_true, params)
