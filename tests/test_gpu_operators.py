@@ -45,7 +45,8 @@ VARIANTS = [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 2), (1, 4, 1), (1, 4, 4), (0
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("geom", [(64, 96, 92), (75, 40, 300), (200, 90, 290), (33, 16, 48), (96, 720, 140)])
+@pytest.mark.parametrize("geom", [(64, 96, 92), (75, 40, 300), (200, 90, 290), (33, 16, 48), (96, 720, 140),
+                                  (100, 60, 151)])
 def test_projector_variants(variant, geom):
     from paper_2410_10503_amd import McrError
     n, na, nd = geom
@@ -253,7 +254,8 @@ def test_large_and_odd_geometries_sampled(geom):
             assert abs(s[k, j] - ref) <= 1e-5 * np.abs(s).max(), (fwd, k, j, s[k, j], ref)
 
 
-@pytest.mark.parametrize("geom", [(1, 1, 1), (2, 3, 1), (3, 1, 5), (5, 4, 2), (2, 8, 7), (7, 2, 40)])
+@pytest.mark.parametrize("geom", [(1, 1, 1), (2, 3, 1), (3, 1, 5), (5, 4, 2), (2, 8, 7), (7, 2, 40), (6, 4, 41),
+                                  (64, 8, 9)])
 def test_degenerate_geometries(geom):
     # one pixel, one angle, one detector bin, and detectors far wider or
     # narrower than the image: every variant against the oracle
