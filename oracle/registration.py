@@ -22,6 +22,13 @@ in pixels at the image's edge, with Barzilai-Borwein step lengths (the first
 trial moves 1 px) and Armijo backtracking (sufficient decrease 1e-4, step
 halved at most 40 times). It stops after the first accepted step shorter than
 `tol` pixels, at a zero gradient, or after `max_iter` steps.
+
+The chest experiment's non-rigid motion is a linear dilatation (Section III),
+an affine map. `register_affine` takes the displacement field
+u(p) = A (p - c) + t (x = column - c, y = row - c, c = (n - 1) / 2), six
+parameters (A00, A01, A10, A11, t_x, t_y), rounded to float32 per pixel as
+the library stores fields, with the same minimisation in the scaled
+coordinates (A (n - 1) / 2, t).
 """
 from __future__ import annotations
 
@@ -52,7 +59,42 @@ def register_rigid(ref, target, theta0=(0.0, 0.0, 0.0), max_iter: int = 200, tol
         E, g = energy_and_grad(ref, target, s / scale)
         return E, g / scale  # gradient with respect to the scaled coordinates
 
-    s = np.asarray(theta0, dtype=np.float64) * scale
+    s, E, k = _minimise(ev, np.asarray(theta0, dtype=np.float64) * scale, max_iter, tol)
+    return s / scale, E, k
+
+
+def affine_field(n: int, theta) -> np.ndarray:
+    """u [2][n][n] of the affine map theta = (A00, A01, A10, A11, t_x, t_y),
+    each component evaluated as (A_r0 x + A_r1 y) + t_r in float64 and rounded
+    to float32."""
+    c = (n - 1) / 2.0
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    x -= c
+    y -= c
+    a00, a01, a10, a11, tx, ty = (float(v) for v in theta)
+    u = np.stack([(a00 * x + a01 * y) + tx, (a10 * x + a11 * y) + ty])
+    return u.astype(np.float32).astype(np.float64)
+
+
+def energy_and_grad_affine(ref: np.ndarray, target: np.ndarray, theta) -> tuple[float, np.ndarray]:
+    """E(theta) and dE/dtheta for the affine displacement field."""
+    ref = np.asarray(ref, dtype=np.float64)
+    n = ref.shape[0]
+    px, py = warp.field_positions(affine_field(n, theta))
+    r = warp.warp(ref, px, py) - np.asarray(target, dtype=np.float64)
+    gx, gy = warp.warp_gradient_at(ref, px, py)
+    c = (n - 1) / 2.0
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    xx -= c
+    yy -= c
+    hx, hy = r * gx, r * gy
+    g = np.array([np.sum(hx * xx), np.sum(hx * yy), np.sum(hy * xx), np.sum(hy * yy), np.sum(hx), np.sum(hy)])
+    return 0.5 * float(np.sum(r * r)), g
+
+
+def _minimise(ev, s, max_iter, tol):
+    """Gradient descent with Barzilai-Borwein steps and Armijo backtracking on
+    the scaled coordinates s (see the module docstring)."""
     E, g = ev(s)
     gn = float(np.linalg.norm(g))
     alpha = 1.0 / gn if gn > 0 else 1.0
@@ -73,4 +115,18 @@ def register_rigid(ref, target, theta0=(0.0, 0.0, 0.0), max_iter: int = 200, tol
             break
         sy = float(ds @ dg)
         alpha = float(ds @ ds) / sy if sy > 0 else 2.0 * alpha
+    return s, E, k
+
+
+def register_affine(ref, target, theta0=(0.0,) * 6, max_iter: int = 300, tol: float = 1e-6):
+    """Returns (theta, E(theta), steps taken) for the affine displacement field."""
+    n = np.asarray(ref).shape[0]
+    rad = (n - 1) / 2.0
+    scale = np.array([rad, rad, rad, rad, 1.0, 1.0])
+
+    def ev(s):
+        E, g = energy_and_grad_affine(ref, target, s / scale)
+        return E, g / scale
+
+    s, E, k = _minimise(ev, np.asarray(theta0, dtype=np.float64) * scale, max_iter, tol)
     return s / scale, E, k

@@ -46,3 +46,51 @@ def test_identity_target_stays_at_zero():
     ref = _ref(40)
     th, E, k = reg.register_rigid(ref, ref)
     assert not np.asarray(th).any() and E == 0.0 and k == 0
+
+
+def _rot_affine(phi, tx, ty):
+    return (np.cos(phi) - 1.0, -np.sin(phi), np.sin(phi), np.cos(phi) - 1.0, tx, ty)
+
+
+@pytest.mark.parametrize("theta", [(0.03, 1.2, -0.7), (-0.06, -2.5, 3.1)])
+def test_affine_gradient_agrees_with_rigid_chain_rule(theta):
+    # a rotation written as an affine map: dE/dphi from the rigid formula equals
+    # sum_ab dE/dA_ab dA_ab/dphi from the affine one (two separate derivations)
+    n = 48
+    ref = _ref(n)
+    target = warp.warp(_ref(n, seed=4), *warp.rigid_positions(n, 0.02, 0.5, -0.5))
+    E_r, g_r = reg.energy_and_grad(ref, target, theta)
+    phi = theta[0]
+    E_a, g_a = reg.energy_and_grad_affine(ref, target, _rot_affine(*theta))
+    dA = np.array([-np.sin(phi), -np.cos(phi), np.cos(phi), -np.sin(phi)])
+    assert abs(E_a - E_r) <= 1e-5 * E_r
+    assert abs(g_a[:4] @ dA - g_r[0]) <= 1e-4 * abs(g_r[0])
+    np.testing.assert_allclose(g_a[4:], g_r[1:], rtol=1e-4)
+
+
+def test_affine_gradient_matches_central_differences():
+    # steps that move edge samples by 1e-3 px (the field is rounded to float32)
+    n = 48
+    ref = _ref(n)
+    target = warp.warp(_ref(n, seed=4), *warp.field_positions(reg.affine_field(n, (0.01, 0, 0, 0.05, 0, 1))))
+    theta = np.array([0.004, -0.01, 0.02, 0.03, 0.6, 0.2])
+    E, g = reg.energy_and_grad_affine(ref, target, theta)
+    for m in range(6):
+        h = 1e-3 / ((n - 1) / 2.0) if m < 4 else 1e-3
+        tp, tm = theta.copy(), theta.copy()
+        tp[m] += h
+        tm[m] -= h
+        fd = (reg.energy_and_grad_affine(ref, target, tp)[0] - reg.energy_and_grad_affine(ref, target, tm)[0]) / (2 * h)
+        assert abs(fd - g[m]) <= 2e-2 * max(abs(g[m]), 0.1 * np.abs(g[4:]).max()), (m, fd, g[m])
+
+
+@pytest.mark.parametrize("theta", [(0.0, 0.0, 0.0, 0.06, 0.5, -1.0), _rot_affine(0.05, 1.7, -2.3),
+                                   (0.02, 0.0, 0.0, -0.05, -2.0, 0.0)])
+def test_affine_recovers_known_maps(theta):
+    # linear dilatations (the chest experiment's motion kind) and a rotation
+    n = 64
+    ref = _ref(n)
+    target = warp.warp(ref, *warp.field_positions(reg.affine_field(n, theta)))
+    th, E, k = reg.register_affine(ref, target, max_iter=500, tol=1e-9)
+    scale = np.array([(n - 1) / 2.0] * 4 + [1.0, 1.0])
+    assert np.abs((th - np.array(theta)) * scale).max() < 1e-5, (th, theta, k)
