@@ -227,6 +227,19 @@ mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, co
 mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, const void* target,
                               double* params, int32_t max_iter, double tol, double* loss,
                               int32_t* steps);
+/* The same for the chest experiment's non-rigid motion, a linear dilatation
+ * (Section III), taken as the affine displacement field
+ *   u(p) = A (p - c) + t,   x = column - c, y = row - c, c = (n - 1) / 2,
+ * params = host double[6] (A00, A01, A10, A11, t_x, t_y), each component
+ * evaluated as (A_r0 x + A_r1 y) + t_r and rounded to float32 (the field
+ * precision); minimised over the scaled coordinates (A (n - 1) / 2, t). The
+ * gate must be a field gate; its field is set to the result through
+ * mcr_set_motion (which can fail if the map needs a wider gather window than
+ * the transposed warp has). On an error during the iterations the gate's
+ * field is left at the last evaluated map.                                    */
+mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, const void* target,
+                               double* params, int32_t max_iter, double tol, double* loss,
+                               int32_t* steps);
 
 /* ---------------------------------------------------------------------------
  * FP64 diagnostics (Theorem 1 and the model of Section II-A), computed on the

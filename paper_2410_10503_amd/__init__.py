@@ -308,6 +308,19 @@ class Handle:
                                                 th, int(max_iter), float(tol), ctypes.byref(E), ctypes.byref(k)))
         return (th[0], th[1], th[2]), E.value, k.value
 
+    def register_affine(self, gate: int, ref, target, params=(0.0,) * 6, max_iter: int = 300,
+                        tol: float = 1e-6):
+        """Affine displacement field u = A (p - c) + t of field gate `gate`, params (A00, A01, A10,
+        A11, t_x, t_y), minimising |D ref - target|^2 / 2 from `params`; the gate's field is set to
+        it. Returns (params, energy, steps)."""
+        self._sync_stream()
+        th = (ctypes.c_double * 6)(*[float(v) for v in params])
+        E, k = ctypes.c_double(), ctypes.c_int32()
+        _lib.check(self._lib.mcr_register_affine(self._h, int(gate), self._img(ref, "ref"),
+                                                 self._img(target, "target"), th, int(max_iter), float(tol),
+                                                 ctypes.byref(E), ctypes.byref(k)))
+        return tuple(th[m] for m in range(6)), E.value, k.value
+
     # -- FP64 diagnostics ----------------------------------------------------
     def power_norm_sq(self, gate: int, v0, max_iter: int = 500, rtol: float = 1e-12):
         """|A_gate|^2 (gate >= 0) or the stacked |(A_1; ...; A_N)|^2 (gate = -1)."""

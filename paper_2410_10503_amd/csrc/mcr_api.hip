@@ -154,6 +154,10 @@ struct mcr_handle {
   std::vector<int> sub_k;
   long shear_part_floats = 0;
   float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
+  // affine registration scratch (allocated on first use)
+  void* reg_g = nullptr;           // [2][n*n] field gradient planes (handle dtype)
+  double* reg_partial = nullptr;   // [kRedBlocks][6] moment partials
+  float* reg_field = nullptr;      // [2][n*n] the result field, unpadded
   // batched SPDHG (mcr_batch_create): S independent slices sharing the geometry
   struct Batch {
     int S = 0;                        // 0: not a batch handle
@@ -1315,11 +1319,53 @@ mcr_status pdhg_impl(mcr_handle* h, const mcr_state* st, const void* const* d, d
   return iteration<T>(h, st, 0, h->N, true, false, t, cx);
 }
 
-// Rigid registration of a gate's image to the reference: gradient descent on
-// E(theta) = |D(theta) ref - target|^2 / 2 in the scaled coordinates
-// s = (phi (n - 1) / 2, t_x, t_y) with Barzilai-Borwein steps and Armijo
-// backtracking (see mcr_register_rigid). Each evaluation: the warp, the
-// residual, its squared norm (FP64 reduction) and J^T r (motion gradient).
+// Gradient descent on the scaled coordinates s of a registration (D of them)
+// with Barzilai-Borwein step lengths (the first trial moves 1 px) and Armijo
+// backtracking (sufficient decrease 1e-4, at most 40 halvings); stops after
+// the first accepted step shorter than tol, at a zero gradient or after
+// max_iter steps. eval(s, E, g) gives the energy and its gradient in s.
+template <int D, typename Eval>
+mcr_status minimise_bb(Eval eval, double* s, int max_iter, double tol, double& E, int& k) {
+  auto dot = [](const double* a, const double* b) {
+    double v = 0.0;
+    for (int m = 0; m < D; ++m) v += a[m] * b[m];
+    return v;
+  };
+  double g[D];
+  STATUS_OK(eval(s, E, g));
+  double gn = std::sqrt(dot(g, g));
+  double alpha = gn > 0 ? 1.0 / gn : 1.0;
+  k = 0;
+  while (k < max_iter && gn > 0) {
+    double sn[D], gnew[D], En = 0.0;
+    for (int t = 0; t < 41; ++t) {
+      for (int m = 0; m < D; ++m) sn[m] = s[m] - alpha * g[m];
+      STATUS_OK(eval(sn, En, gnew));
+      if (En <= E - 1e-4 * alpha * gn * gn) break;
+      alpha *= 0.5;
+    }
+    ++k;
+    const double step = alpha * gn;
+    double ds[D], dg[D];
+    for (int m = 0; m < D; ++m) {
+      ds[m] = sn[m] - s[m];
+      dg[m] = gnew[m] - g[m];
+      s[m] = sn[m];
+      g[m] = gnew[m];
+    }
+    E = En;
+    gn = std::sqrt(dot(g, g));
+    if (step < tol) break;
+    const double sy = dot(ds, dg);
+    alpha = sy > 0 ? dot(ds, ds) / sy : 2.0 * alpha;
+  }
+  return MCR_OK;
+}
+
+// Rigid registration of a gate's image to the reference: E(theta) =
+// |D(theta) ref - target|^2 / 2 over s = (phi (n - 1) / 2, t_x, t_y) (see
+// mcr_register_rigid). Each evaluation: the warp, the residual, its squared
+// norm (FP64 reduction) and J^T r (motion gradient).
 template <typename T>
 mcr_status register_rigid_impl(mcr_handle* h, int gate, const void* ref, const void* target, double* params,
                                int max_iter, double tol, double* loss, int32_t* steps) {
@@ -1342,38 +1388,79 @@ mcr_status register_rigid_impl(mcr_handle* h, int gate, const void* ref, const v
     for (int m = 0; m < 3; ++m) g[m] = h->red_host[1 + m] / scale[m];
     return MCR_OK;
   };
-  auto norm = [](const double* v) { return std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]); };
-  double s[3], g[3], E = 0.0;
-  for (int m = 0; m < 3; ++m) s[m] = params[m] * scale[m];
-  STATUS_OK(eval(s, E, g));
-  double gn = norm(g);
-  double alpha = gn > 0 ? 1.0 / gn : 1.0;  // the first trial moves 1 px
+  double s[3], E = 0.0;
   int k = 0;
-  while (k < max_iter && gn > 0) {
-    double sn[3], gnew[3], En = 0.0;
-    for (int t = 0; t < 41; ++t) {  // Armijo backtracking
-      for (int m = 0; m < 3; ++m) sn[m] = s[m] - alpha * g[m];
-      STATUS_OK(eval(sn, En, gnew));
-      if (En <= E - 1e-4 * alpha * gn * gn) break;
-      alpha *= 0.5;
-    }
-    ++k;
-    const double step = alpha * gn;
-    double ds[3], dg[3];
-    for (int m = 0; m < 3; ++m) {
-      ds[m] = sn[m] - s[m];
-      dg[m] = gnew[m] - g[m];
-      s[m] = sn[m];
-      g[m] = gnew[m];
-    }
-    E = En;
-    gn = norm(g);
-    if (step < tol) break;
-    const double sy = ds[0] * dg[0] + ds[1] * dg[1] + ds[2] * dg[2];
-    alpha = sy > 0 ? (ds[0] * ds[0] + ds[1] * ds[1] + ds[2] * ds[2]) / sy : 2.0 * alpha;  // Barzilai-Borwein
-  }
+  for (int m = 0; m < 3; ++m) s[m] = params[m] * scale[m];
+  STATUS_OK(minimise_bb<3>(eval, s, max_iter, tol, E, k));
   for (int m = 0; m < 3; ++m) params[m] = h->motion[gate].rigid[m] = s[m] / scale[m];
   STATUS_OK(upload_motion<T>(h));
+  if (loss) *loss = E;
+  if (steps) *steps = k;
+  return MCR_OK;
+}
+
+// Affine registration of a field gate: u(p) = A (p - c) + t, theta = (A00,
+// A01, A10, A11, t_x, t_y), over s = (A (n - 1) / 2, t) (see
+// mcr_register_affine). Each evaluation writes the field into the gate's
+// padded planes, warps, takes the residual and its squared norm, the field
+// gradient planes (motion gradient) and their six moments.
+template <typename T>
+mcr_status register_affine_impl(mcr_handle* h, int gate, const void* ref, const void* target, double* params,
+                                int max_iter, double tol, double* loss, int32_t* steps) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  const long n2 = (long)n * n;
+  if (!h->reg_g) {
+    STATUS_OK(dmalloc(h, &h->reg_g, sizeof(double) * 2 * n2));
+    STATUS_OK(dmalloc(h, (void**)&h->reg_partial, sizeof(double) * 6 * kRedBlocks));
+    STATUS_OK(dmalloc(h, (void**)&h->reg_field, sizeof(float) * 2 * n2));
+  }
+  const double rad = (n - 1) / 2.0;
+  const double scale[6] = {rad, rad, rad, rad, 1.0, 1.0};
+  float* fP = h->fieldP + (long)gate * 2 * h->padded;
+  const dim3 grid(cdiv(n, 16), cdiv(n, 16)), block(16, 16);
+  auto set_field = [&](const double* th) -> mcr_status {
+    hipLaunchKernelGGL(k_affine_field, grid, block, 0, h->stream, n, h->pitch, h->padded, th[0], th[1], th[2], th[3],
+                       th[4], th[5], fP);
+    LAUNCH_OK();
+    return MCR_OK;
+  };
+  auto eval = [&](const double* s, double& E, double* g) -> mcr_status {
+    double th[6];
+    for (int m = 0; m < 6; ++m) th[m] = s[m] / scale[m];
+    STATUS_OK(set_field(th));
+    STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)ref));
+    hipLaunchKernelGGL(k_residual_padded<T>, grid, block, 0, h->stream, n, h->pitch, w.wP, (const T*)target, w.bP);
+    LAUNCH_OK();
+    STATUS_OK((launch_reduce<T, T, 0>(h, h->padded, w.bP, w.bP, 0)));
+    HIP_OK(hipMemsetAsync(h->reg_g, 0, sizeof(T) * 2 * n2, h->stream));
+    STATUS_OK(launch_motion_grad<T>(h, gate, w.bP, (const T*)ref, h->reg_g));
+    hipLaunchKernelGGL(k_affine_moments<T>, dim3(kRedBlocks), dim3(256), 0, h->stream, n, (const T*)h->reg_g,
+                       h->reg_partial);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_affine_moments_final, dim3(1), dim3(256), 0, h->stream, h->reg_partial, h->red_out + 1);
+    LAUNCH_OK();
+    STATUS_OK(read_results(h, 7));
+    E = 0.5 * h->red_host[0];
+    for (int m = 0; m < 6; ++m) g[m] = h->red_host[1 + m] / scale[m];
+    return MCR_OK;
+  };
+  double s[6], E = 0.0;
+  int k = 0;
+  for (int m = 0; m < 6; ++m) s[m] = params[m] * scale[m];
+  STATUS_OK(minimise_bb<6>(eval, s, max_iter, tol, E, k));
+  for (int m = 0; m < 6; ++m) params[m] = s[m] / scale[m];
+  // install the result as the gate's field (gather-window set-up and check)
+  STATUS_OK(set_field(params));
+  for (int pl = 0; pl < 2; ++pl) {
+    hipLaunchKernelGGL(k_from_padded<float>, grid, block, 0, h->stream, n, h->pitch, fP + pl * h->padded,
+                       h->reg_field + pl * n2);
+    LAUNCH_OK();
+  }
+  mcr_motion m{};
+  m.kind = MCR_MOTION_FIELD;
+  m.field = h->reg_field;
+  STATUS_OK(mcr_set_motion(h, gate, &m));
   if (loss) *loss = E;
   if (steps) *steps = k;
   return MCR_OK;
@@ -2011,6 +2098,21 @@ mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, co
   STATUS_OK(check_ptr(v, "v"));
   STATUS_OK(check_ptr(grad_motion, "grad_motion"));
   return DISPATCH(motion_grad_impl, h, gate, img, v, grad_motion);
+}
+
+mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, const void* target, double* params,
+                               int32_t max_iter, double tol, double* loss, int32_t* steps) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(ref, "ref"));
+  STATUS_OK(check_ptr(target, "target"));
+  STATUS_OK(check_ptr(params, "params"));
+  if (h->motion[gate].kind != MCR_MOTION_FIELD) return fail(MCR_ERR_ARG, "gate %d is not a field gate", gate);
+  for (int m = 0; m < 6; ++m)
+    if (!std::isfinite(params[m])) return fail(MCR_ERR_ARG, "params[%d] is not finite", m);
+  if (max_iter < 0) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 0", max_iter);
+  if (!(tol >= 0) || !std::isfinite(tol)) return fail(MCR_ERR_ARG, "tol must be finite and >= 0");
+  return DISPATCH(register_affine_impl, h, gate, ref, target, params, max_iter, tol, loss, steps);
 }
 
 mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, const void* target, double* params,

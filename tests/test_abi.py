@@ -133,3 +133,9 @@ def test_register_rigid_rejects_null_handle(lib):
     th = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
     assert lib.mcr_register_rigid(None, 0, None, None, th, 10, 1e-6, None, None) == _lib.MCR_ERR_ARG
     assert b"null handle" in lib.mcr_last_error()
+
+
+def test_register_affine_rejects_null_handle(lib):
+    th = (ctypes.c_double * 6)()
+    assert lib.mcr_register_affine(None, 0, None, None, th, 10, 1e-6, None, None) == _lib.MCR_ERR_ARG
+    assert b"null handle" in lib.mcr_last_error()

@@ -94,3 +94,84 @@ def test_registration_arguments():
         hr.register_rigid(0, x, x, max_iter=-1)
     th, E, k = hr.register_rigid(1, x, x)  # zero images: zero gradient, no step
     assert k == 0 and E == 0.0
+
+
+def _affine_target(ref, theta):
+    return f32(warp.warp(ref, *warp.field_positions(oreg.affine_field(ref.shape[0], theta))))
+
+
+def _apx(theta, n):
+    return np.asarray(theta, float) * np.array([(n - 1) / 2.0] * 4 + [1.0, 1.0])
+
+
+def _rot_affine(phi, tx, ty):
+    return (np.cos(phi) - 1.0, -np.sin(phi), np.sin(phi), np.cos(phi) - 1.0, tx, ty)
+
+
+@pytest.mark.parametrize("theta", [(0.0, 0.0, 0.0, 0.06, 0.5, -1.0), _rot_affine(0.05, 1.7, -2.3)])
+def test_fp64_affine_registration_matches_oracle(theta):
+    n = 64
+    P = Problem(n, 40, 92, 2, "field")
+    ref = _ref(n)
+    tgt = _affine_target(ref, theta)
+    th_o, E_o, k_o = oreg.register_affine(ref, tgt, max_iter=500, tol=1e-9)
+    h = P.handle(torch.float64)
+    th, E, k = h.register_affine(1, dev(ref, torch.float64), dev(tgt, torch.float64), max_iter=500, tol=1e-9)
+    assert k == k_o
+    assert np.abs(_apx(th, n) - _apx(th_o, n)).max() < 1e-9
+    assert np.abs(_apx(th, n) - _apx(theta, n)).max() < 1e-5
+    assert abs(E - E_o) <= 1e-12 * float(np.sum(tgt ** 2))
+
+
+def test_affine_energy_at_start_and_installed_field():
+    n = 64
+    P = Problem(n, 40, 92, 2, "field")
+    ref, tgt = _ref(n), _affine_target(_ref(n, seed=5), (0.01, 0.0, 0.0, 0.04, 0.3, -0.2))
+    start = (0.004, -0.01, 0.02, 0.03, 0.6, 0.2)
+    E_o, _ = oreg.energy_and_grad_affine(ref, tgt, start)
+    b = f32(synth.random_image(n, 8))
+    for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        h = P.handle(dtype)
+        th, E, k = h.register_affine(0, dev(ref, dtype), dev(tgt, dtype), params=start, max_iter=0)
+        assert k == 0 and th == start
+        assert abs(E - E_o) <= bar * E_o
+        # the gate now carries the start map: its warp and transposed warp
+        # against the oracle's with the same (float32) field
+        pos = warp.field_positions(oreg.affine_field(n, start))
+        assert np.abs(h.warp(0, dev(ref, dtype)).cpu().numpy() - warp.warp(ref, *pos)).max() <= 10 * bar
+        wt = h.warp_adjoint(0, dev(b, dtype)).cpu().numpy()
+        ref_wt = warp.warp_adjoint(b, *pos)
+        assert np.linalg.norm(wt - ref_wt) <= 10 * bar * np.linalg.norm(ref_wt)
+
+
+def test_full_size_fp32_recovers_ten_dilatations():
+    # 512^2, 10 field gates with the chest experiment's motion kind: vertical
+    # linear dilatations growing with the gate phase (up to 8 px at the edge)
+    # plus small shifts; each registered from zero in float32
+    n = 512
+    P = Problem(n, 720, 730, 10, "field")
+    h = P.handle(torch.float32)
+    ref = _ref(n)
+    rd = dev(ref, torch.float32)
+    for i in range(10):
+        q = i / 9.0
+        theta = (0.0, 0.0, 0.0, 8.0 * q / 255.5, 0.5 * q, -0.7 * q)
+        tgt = _affine_target(ref, theta)
+        th, E, k = h.register_affine(i, rd, dev(tgt, torch.float32), max_iter=500, tol=1e-5)
+        err = np.abs(_apx(th, n) - _apx(theta, n)).max()
+        assert err < 2e-3, (i, th, theta, err, k)
+
+
+def test_affine_registration_arguments():
+    from paper_2410_10503_amd import McrError
+    R = Problem(32, 20, 48, 2, "rigid")
+    hr = R.handle(torch.float32)
+    x = torch.zeros(32, 32, device="cuda")
+    with pytest.raises(McrError, match="not a field gate"):
+        hr.register_affine(0, x, x)
+    P = Problem(32, 20, 48, 2, "field")
+    h = P.handle(torch.float32)
+    with pytest.raises(McrError, match="params"):
+        h.register_affine(0, x, x, params=(0.0, float("inf"), 0.0, 0.0, 0.0, 0.0))
+    th, E, k = h.register_affine(1, x, x)
+    assert k == 0 and E == 0.0
