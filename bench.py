@@ -256,10 +256,34 @@ def registration_measurement():
     dt = time.perf_counter() - t0
     err = max(float(np.abs((np.array(th) - params[i]) * scale).max()) for i, (th, _, _) in enumerate(res))
     h.close()
-    return {"workload": "16 rigid gates at 512^2 (rotations up to 8 deg, shifts up to 10 px), each gate image "
-                        "registered to the reference from zero, float32",
-            "ms_per_gate": 1e3 * dt / N, "steps_mean": float(np.mean([k for _, _, k in res])),
-            "max_error_px": err}
+    out = {"workload": "16 rigid gates at 512^2 (rotations up to 8 deg, shifts up to 10 px), each gate image "
+                       "registered to the reference from zero, float32",
+           "ms_per_gate": 1e3 * dt / N, "steps_mean": float(np.mean([k for _, _, k in res])),
+           "max_error_px": err}
+    # the chest experiment's motion kind: 10 gates of vertical linear
+    # dilatation (up to 8 px at the edge) plus small shifts, as affine fields
+    # (the gate images: the reference warped by the library with each field)
+    Nf = 10
+    n = wl.n
+    c = (n - 1) / 2.0
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64) - c
+    thetas = [(0.0, 0.0, 0.0, 8.0 * (i / 9.0) / c, 0.5 * i / 9.0, -0.7 * i / 9.0) for i in range(Nf)]
+    fields = [torch.from_numpy(np.stack([(t[0] * xx + t[1] * yy) + t[4], (t[2] * xx + t[3] * yy) + t[5]])
+                               .astype(np.float32)).cuda() for t in thetas]
+    hf = Handle(n, wl.n_angles, wl.n_det, [("field", f) for f in fields], dtype=torch.float32)
+    targets = [hf.warp(i, ref).clone() for i in range(Nf)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [hf.register_affine(i, ref, targets[i], max_iter=500, tol=1e-5) for i in range(Nf)]
+    dt = time.perf_counter() - t0
+    sa = np.array([c] * 4 + [1.0, 1.0])
+    err = max(float(np.abs((np.array(th) - np.array(thetas[i])) * sa).max()) for i, (th, _, _) in enumerate(res))
+    hf.close()
+    out["affine"] = {"workload": "10 field gates at 512^2, vertical linear dilatations up to 8 px plus shifts, "
+                                 "affine registration from zero, float32",
+                     "ms_per_gate": 1e3 * dt / Nf, "steps_mean": float(np.mean([k for _, _, k in res])),
+                     "max_error_px": err}
+    return out
 
 
 def subsets_measurement(h, d, wl, gate_norms, v0, M: int = 4, epochs: int = 3):
