@@ -601,6 +601,14 @@ __global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __
     ua.cx = slice_tc[2 * si.slice + 1];
     ua.do_x = si.do_x;
   }
+  const long q = (long)qr * n + qc;
+  // the update's inputs are loaded before the gathers, so that their latency
+  // overlaps them (and x is not reloaded after the stores of z and z-bar)
+  T z0 = T(0), x0 = T(0);
+  if (MODE == 2) {
+    z0 = ua.z[q];
+    if (ua.do_x) x0 = ua.x[q];
+  }
   T dz = T(0), dzb = T(0);
   for (int gi = 0; gi < G; ++gi) {
     const int gate = gate0 + gi;
@@ -647,17 +655,16 @@ __global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __
     dz += part;
     if (MODE == 2) dzb = fmaT(gs[gate].coef, part, dzb);
   }
-  const long q = (long)qr * n + qc;
   if (MODE == 0) {
     out[q] = dz;
   } else if (MODE == 1) {
     out[q] += dz;
   } else {
-    const T z = ua.z[q] + dz;
+    const T z = z0 + dz;
     const T zb = z + dzb;
     ua.z[q] = z;
     ua.zbar[q] = zb;
-    if (ua.do_x) ua.x[q] = (ua.x[q] - ua.tau * zb) * ua.cx;
+    if (ua.do_x) ua.x[q] = (x0 - ua.tau * zb) * ua.cx;
   }
 }
 
