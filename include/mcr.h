@@ -339,6 +339,8 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           k +- n_angles/2; needs an even n and n_angles and a launch over
  *           all angles, else the tiled kernel runs with 2, 4, 8, 8, 8
  *           pixels per thread).
+ * A new handle starts with forward 4 where available (else 3, 2, 0) and the
+ * adjoint -4 with 12 shares on even n and n_angles (else 8 pixels, 6 shares).
  * All variants compute the same weights; results differ only by summation
  * order. mcr_autotune times the variants on this geometry with
  * gates_per_launch gates per launch (1 for SPDHG, N for PDHG), keeps the

@@ -1818,7 +1818,12 @@ mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_moti
   if ((s = init_work<double>(h)) != MCR_OK) return cleanup(s);
   if (dtype == MCR_F32 && (s = init_work<float>(h)) != MCR_OK) return cleanup(s);
   if ((s = mcr_set_motion(h, -1, nullptr)) != MCR_OK) return cleanup(s);
-  h->tune.fwd = h->shear_npieces > 0 ? 3 : (h->sched_ok ? 2 : 0);
+  // defaults before any autotuning: the quarter-turn pair where the geometry
+  // has the symmetry, else the line-sheared forward and the tiled adjoint
+  h->tune.fwd = h->quad_npieces > 0 ? 4 : (h->shear_npieces > 0 ? 3 : (h->sched_ok ? 2 : 0));
+  const bool even = geom->n % 2 == 0 && geom->n_angles % 2 == 0;
+  h->tune.adj_px = even ? -4 : 8;
+  h->tune.adj_s = even ? 12 : 6;
   *out = h;
   return MCR_OK;
 }

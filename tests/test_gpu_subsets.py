@@ -80,9 +80,9 @@ def test_one_subset_block_iterations_equal_gate_iterations():
     sig, tau, th, _ = osp.step_sizes_spdhg([2.0 * 96 * 64] * 3, P.alpha, 3)
     p = [1.0 / 3] * 3
     seq = [int(g) for g in synth.gate_sequence(3, 1, 0, length=7)]
-    for dtype, variant in ((torch.float32, None), (torch.float32, (4, -4, 8)), (torch.float64, None)):
+    for dtype, variant in ((torch.float32, (3, 4, 4)), (torch.float32, (4, -4, 8)), (torch.float64, None)):
         h = P.handle(dtype)
-        if variant is not None:  # one subset holds all angles: the quarter-turn kernels run
+        if variant is not None:  # with (4, -4, 8) one subset holds all angles: the quarter-turn kernels run
             h.set_variant(*variant)
         d = [dev(v, dtype) for v in P.d]
         a, b = h.zero_state(), h.zero_state()
