@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A_i+A_i^* pairs/sec and SPDHG epochs/sec at 512², N=16; HBM GB/s vs peak"
 PEAK_HBM_GBS = 8000.0
+LDS_READ_TBS = 128.0  # LDS 16-byte read rate measured on one MI355X (all CUs)
 PEAK_FP32_TFLOPS = 157.3
 
 
@@ -623,6 +624,16 @@ def main():
     roof["nnz_per_launch"] = nnz
     if dom in ("project", "backproject"):
         roof["weights_per_s"] = nnz / avg_s   # interpolation weights applied per second
+        # on-chip reads: the LDS-staged projector kernels read 8 bytes (two
+        # floats) per sample, a ray on a line (about nnz / 2 of them) or a
+        # pixel at an angle (n^2 n_a), against the LDS read rate measured on
+        # the MI355X with 16-byte reads at conflict-free addresses
+        samples = nnz / 2.0 if dom == "project" else float(n) * n * na
+        roof["lds_read_tbs"] = 8.0 * samples / avg_s / 1e12
+        roof["lds_read_roof_tbs"] = LDS_READ_TBS
+        roof["lds_frac"] = roof["lds_read_tbs"] / LDS_READ_TBS
+    if roof["traffic"]:
+        roof["hbm_gbs_measured"] = roof["traffic"] / avg_s / 1e9
 
     out = {
         "metric": METRIC,
