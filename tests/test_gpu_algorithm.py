@@ -210,3 +210,51 @@ def test_full_size_one_iteration_from_random_state(variant):
     assert rel(host(gst.y[g]), ost.y[g]) < 1e-5
     assert rel(host(gst.z) - z, ost.z - z) < 1e-5
     assert rel(host(gst.zbar) - z, ost.zbar - z) < 1e-5
+
+
+@pytest.mark.parametrize("name,epochs", [("ellipses512_rigid8", 50), ("chest512_field16", 100)])
+def test_full_size_fp32_epochs_against_fp64(name, epochs):
+    # the 512^2, 720 x 730 workloads for 50 / 100 epochs: SPDHG (and PDHG for
+    # the rigid one) in float32 against the same iterations in FP64 on the
+    # GPU, whose every step matches the FP64 oracle (the tests above) and is
+    # used as the reference at this size, where the CPU oracle would take
+    # hours. Same float32-rounded data, gate draws and step sizes.
+    wl = synth.WORKLOADS[name]
+    P = Problem(512, 720, 730, wl.n_gates, wl.motion, alpha=wl.alpha, max_rot=wl.max_rot_deg,
+                max_shift=wl.max_shift, phantom=wl.phantom)
+    N = P.N
+    h64, h32 = P.handle(torch.float64), P.handle(torch.float32)
+    h32.autotune(1)
+    x = dev(P.x_true, torch.float64)
+    noise = synth.unit_noise((N, 720, 730), 2)
+    d = []
+    for i in range(N):
+        s = host(h64.apply_Ai(i, x))
+        d.append(f32(s + 0.01 * np.abs(s).max() * noise[i] / np.sqrt(N)))
+    sig, tau, th, _ = osp.step_sizes_spdhg([3.7e5] * N, P.alpha, N)
+    p = [1.0 / N] * N
+    runs = {}
+    for dt, h in ((torch.float64, h64), (torch.float32, h32)):
+        dd = [dev(v, dt) for v in d]
+        st = h.zero_state()
+        for e in range(epochs):
+            h.spdhg_epoch(st, dd, P.alpha, sig, tau, th, p, synth.gate_sequence(N, 3, e))
+        runs[dt] = st
+    a, b = runs[torch.float32], runs[torch.float64]
+    ya = np.concatenate([host(v).ravel() for v in a.y])
+    yb = np.concatenate([host(v).ravel() for v in b.y])
+    errs = {"x": rel(host(a.x), host(b.x)), "zbar": rel(host(a.zbar), host(b.zbar)), "y": rel(ya, yb)}
+    print(f"{name}: SPDHG float32 vs FP64 after {epochs} epochs: {errs}", flush=True)
+    assert max(errs.values()) < F32_EPOCHS
+    if wl.motion == "rigid":
+        psig, ptau, pth, _ = osp.step_sizes_pdhg(N * 3.7e5, P.alpha, N)
+        pr = {}
+        for dt, h in ((torch.float64, h64), (torch.float32, h32)):
+            dd = [dev(v, dt) for v in d]
+            st = h.zero_state()
+            for _ in range(epochs):
+                h.pdhg_epoch(st, dd, P.alpha, psig, ptau, pth)
+            pr[dt] = host(st.x)
+        err = rel(pr[torch.float32], pr[torch.float64])
+        print(f"{name}: PDHG float32 vs FP64 x after {epochs} epochs: {err:.2e}", flush=True)
+        assert err < F32_EPOCHS
