@@ -684,8 +684,42 @@ mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
 // Tables of the quarter-turn forward (float handles with even n and n_angles).
 mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
   if (h->geo.n % 2 || h->geo.n_angles % 2) return MCR_OK;
-  const Schedule qs = build_quad_schedule(h->geo.n, h->geo.n_det, af);
+  Schedule qs = build_quad_schedule(h->geo.n, h->geo.n_det, af);
   if (!qs.ok || qs.pieces.empty()) return MCR_OK;  // variant 4 unavailable on this geometry
+  // consecutive workgroups go to the 8 XCDs in turn: sort the pieces by the
+  // middle image row of their lines and cut them into 8 runs of equal line
+  // counts; run x goes to positions = x (mod 8), so that each XCD's L2 holds
+  // about an eighth of the image planes; shorter runs are padded with
+  // entries of unit -1
+  {
+    std::vector<std::pair<int, int4>> keyed;
+    long total = 0;
+    for (const int4& pc : qs.pieces) {
+      int lo = INT_MAX, hi = -1, lines = 0;
+      for (int b = pc.x; b < pc.x + pc.y; ++b) {
+        lo = std::min(lo, qs.bands[b].x);
+        hi = std::max(hi, qs.bands[b].x + qs.bands[b].y - 1);
+        lines += qs.bands[b].y;
+      }
+      keyed.push_back({hi >= lo ? (lo + hi) / 2 : 0, pc});
+      total += lines;
+    }
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const std::pair<int, int4>& a, const std::pair<int, int4>& b) { return a.first < b.first; });
+    std::vector<std::vector<int4>> bucket(8);
+    long cum = 0;
+    for (const auto& kp : keyed) {
+      const int4& pc = kp.second;
+      bucket[std::min<long>(7, total > 0 ? 8 * cum / total : 0)].push_back(pc);
+      for (int b = pc.x; b < pc.x + pc.y; ++b) cum += qs.bands[b].y;
+    }
+    size_t len = 0;
+    for (const auto& bk : bucket) len = std::max(len, bk.size());
+    std::vector<int4> order(8 * len, make_int4(0, 0, -1, 0));
+    for (int x = 0; x < 8; ++x)
+      for (size_t q = 0; q < bucket[x].size(); ++q) order[8 * q + x] = bucket[x][q];
+    qs.pieces = order;
+  }
   const int ns = h->nslots;
   STATUS_OK(dmalloc(h, (void**)&h->wf.wQ, sizeof(float) * 3 * h->padded * ns));
   h->quad_part_floats = qs.part_floats;

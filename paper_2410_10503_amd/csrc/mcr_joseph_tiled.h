@@ -464,7 +464,10 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 // four planes' values at one pixel (a float4) and one crossing, one
 // conversion and one pair of weights serve four rays; the bins run over
 // [0, ceil(n_det/2)) only. The work split is the line-sheared one of
-// k_joseph_fwd_shear (same schedule format, kQuCap entries per band); a tap
+// k_joseph_fwd_shear (same schedule format, kQuCap entries per band, the
+// piece list ordered so that block i, which runs on XCD i mod 8, gets pieces
+// from the i mod 8-th eighth of the image rows; entries with unit -1 are
+// padding); a tap
 // reads the entries at the crossing's column and the next one and
 // interpolates. Multi-piece units write 8 partial sums per thread (planes x
 // two rays), added by k_joseph_fwd_quad_finish.
@@ -524,6 +527,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int4 pc = pieces[piece0 + blockIdx.x];
+  if (pc.z < 0) return;  // padding entry of the XCD-ordered piece list
   const int4 un = units[pc.z];
   const int4 ch = chunks[un.x];
   const long long Bm = (long long)(((unsigned long long)(unsigned)ch.w << 32) | (unsigned)ch.z);
