@@ -1035,7 +1035,7 @@ mcr_status launch_twarp(mcr_handle* h, int gate0, int G, T* out, UpdateArgs<T> u
   Work<T>& w = work<T>(h);
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_TWARP);
-  dim3 grid(cdiv(n, 16), cdiv(n, 16), slots ? nslots : 1), block(16, 16);
+  dim3 grid(cdiv(n, 32), cdiv(n, 8), slots ? nslots : 1), block(32, 8);
   const int R = slots ? radius : max_radius(h, gate0, G);
   const Geo<T> g = geo_of<T>(h);
 #define TW(RR)                                                                                   \

@@ -558,7 +558,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_fx(Geo<float> g, const Angle
 //   mode 0: out = sum_g D_g^T b_g                       (plain adjoint)
 //   mode 1: out += sum_g D_g^T b_g                      (accumulate)
 //   mode 2: z += dz; zbar = z + sum_g coef_g dz_g; optionally x = (x - tau zbar) cx
-// grid (ceil(n/16), ceil(n/16)), block (16, 16)
+// grid (ceil(n/32), ceil(n/8)), block (32, 8)
 // ---------------------------------------------------------------------------
 template <typename T>
 struct UpdateArgs {
@@ -582,8 +582,9 @@ __global__ __launch_bounds__(256) void k_twarp(Geo<T> g, const GateMotion<T>* __
                                                T* __restrict__ out, UpdateArgs<T> ua,
                                                const SlotInfo* __restrict__ slots, long slice_stride,
                                                const T* __restrict__ slice_tc) {
-  const int qc = blockIdx.x * 16 + threadIdx.x;
-  const int qr = blockIdx.y * 16 + threadIdx.y;
+  // 32 x 8 tiles: each row of a tile is one 128-byte line of the images
+  const int qc = blockIdx.x * 32 + threadIdx.x;
+  const int qr = blockIdx.y * 8 + threadIdx.y;
   const int n = g.n, pitch = g.pitch;
   if (qc >= n || qr >= n) return;
   const long origin = (long)kPad * pitch + kPad;
