@@ -144,7 +144,9 @@ def batched_measurement(steps: int, seed: int = 4):
         tau.append(b)
         th.append(c)
         p += [1.0 / ngs[s_]] * ngs[s_]
-    variant = bh.autotune(1)
+    # the batched launches cover the slices still iterating (S at the first
+    # step, fewer later): tune for the mean number of slices per launch
+    variant = bh.autotune(max(1, round(G / max(ngs))))
 
     def seqs(e):
         return [int(g) for s_ in range(S) for g in synth.gate_sequence(ngs[s_], 500 + s_, e)]
