@@ -104,11 +104,32 @@ def cpu_baseline(wl, x_true, fields_or_params):
             "host_cpus": os.cpu_count(), "cpu_model": cpu}
 
 
-def batched_measurement(steps: int, seed: int = 4):
+def copy_gbs(nbytes: int = 1 << 30, reps: int = 5):
+    """Device-to-device copy rate (bytes read + written per second) of a
+    buffer far larger than the on-chip caches: the achievable streaming rate
+    the streaming kernels are compared with."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    rate = 2.0 * nbytes * reps / (e0.elapsed_time(e1) / 1e3)
+    del a, b
+    return rate / 1e9
+
+
+def batched_measurement(steps: int, seed: int = 4, variant=None, per_slice: bool = True):
     """64 independent 256^2 slices (360 x 366), gate counts uniform in {4..32},
     rigid and non-rigid motion alternating: epochs/s of the batched, graph-
     replayed epoch, of the same without the graph, and of the per-slice form
-    (one handle per slice, epochs one after the other)."""
+    (one handle per slice, epochs one after the other). Also the streaming
+    rate of the step (i) and transposed-warp + update launches of one plain
+    epoch (HIP events per launch) against the device copy rate."""
     import torch
     import synth
     from paper_2410_10503_amd import BatchHandle, Handle, step_sizes
@@ -146,7 +167,10 @@ def batched_measurement(steps: int, seed: int = 4):
         p += [1.0 / ngs[s_]] * ngs[s_]
     # the batched launches cover the slices still iterating (S at the first
     # step, fewer later): tune for the mean number of slices per launch
-    variant = bh.autotune(max(1, round(G / max(ngs))))
+    if variant is None:
+        variant = bh.autotune(max(1, round(G / max(ngs))))
+    else:
+        bh.set_variant(variant["fwd"], variant["adj_px"], variant["adj_shares"])
 
     def seqs(e):
         return [int(g) for s_ in range(S) for g in synth.gate_sequence(ngs[s_], 500 + s_, e)]
@@ -162,6 +186,31 @@ def batched_measurement(steps: int, seed: int = 4):
             bh.batch_spdhg_epoch(st, d, alpha, sig, tau, th, p, seqs(1 + e), use_graph=use_graph)
         torch.cuda.synchronize()
         out["epochs_per_s_graph" if use_graph else "epochs_per_s_plain"] = steps / (time.perf_counter() - t0)
+    # streaming launches of one plain epoch: step (i) of all slices reads x
+    # and z-bar and writes x (3 images per slice); the transposed warp +
+    # update of a gate iteration reads b and z and writes z and z-bar (4
+    # images), plus x read and written except at a slice's last iteration,
+    # plus the two field planes of a field gate. The images of the 64 slices
+    # (17 MB per array) may be served from the 256 MB last-level cache.
+    bh.profile(True)
+    bh.profile_read()
+    bh.batch_spdhg_epoch(st, d, alpha, sig, tau, th, p, seqs(1 + steps), use_graph=False)
+    ks = bh.profile_read()
+    bh.profile(False)
+    img_b = 4.0 * n * n
+    g_field = sum(ngs[s_] for s_ in range(S) if s_ % 2)
+    copy_rate = copy_gbs()
+    stream = {"copy_gbs": copy_rate}
+    for name, nbytes in (("xstep", 3 * S * img_b), ("twarp", img_b * (4 * G + 2 * (G - S) + 2 * g_field))):
+        ms, cnt = ks[name]
+        if cnt:
+            gbs = nbytes / (ms / 1e3) / 1e9
+            stream[name] = {"launches": cnt, "us_per_launch": 1e3 * ms / cnt, "bytes_per_epoch": nbytes,
+                            "gbs": gbs, "frac_of_copy": gbs / copy_rate, "frac_of_peak": gbs / PEAK_HBM_GBS}
+    out["streaming"] = stream
+    if not per_slice:
+        bh.close()
+        return out
     # per-slice form: one handle per slice, same kernels and variant
     handles = []
     for s_ in range(S):
@@ -459,8 +508,10 @@ def main():
     ap.add_argument("--variant", default=None,
                     help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
                          "(counter runs serialise dispatches, which would change the autotuner's choice)")
-    ap.add_argument("--experiment", choices=["paper"], default=None,
-                    help="run the Section III reproduction (rates vs Theorem 1, MC vs no-MC) instead of the bench")
+    ap.add_argument("--experiment", choices=["paper", "batched"], default=None,
+                    help="paper: the Section III reproduction (rates vs Theorem 1, MC vs no-MC); batched: the "
+                         "64-slice batched workload alone (--steps epochs, --variant applies), for counter "
+                         "runs; either instead of the bench")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -471,6 +522,14 @@ def main():
 
     if args.experiment == "paper":
         print(json.dumps({"experiment": "section III reproduction", "results": paper_experiment()}), flush=True)
+        return
+    if args.experiment == "batched":
+        v = None
+        if args.variant:
+            f, px, sh = (int(t) for t in args.variant.split(","))
+            v = {"fwd": f, "adj_px": px, "adj_shares": sh}
+        res = batched_measurement(args.steps, variant=v, per_slice=False)
+        print(json.dumps({"experiment": "batched", "results": res}), flush=True)
         return
 
     import torch
