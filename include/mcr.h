@@ -170,8 +170,9 @@ mcr_status mcr_batch_create(const mcr_geometry* geom, int32_t n_slices, const in
  * global gate order. Host arrays: alpha, tau, theta [S]; sigma, p [sum N_s];
  * gate_seq [sum N_s], slice s's draws (local gate indices) at its first global
  * gate. use_graph != 0 replays the epoch as a HIP graph (captured on first use
- * and whenever x, z or zbar move) on a stream of the handle, ordered after
- * and before the handle's stream by events.                                   */
+ * and again whenever x, z or zbar move, or after mcr_set_variant,
+ * mcr_autotune, mcr_set_motion or mcr_set_rigid_params) on a stream of the
+ * handle, ordered after and before the handle's stream by events.             */
 mcr_status mcr_batch_spdhg_epoch(mcr_handle* h, void* x, void* z, void* zbar, void* y, const void* d,
                                  const double* alpha, const double* sigma, const double* tau,
                                  const double* theta, const double* p, const int32_t* gate_seq,

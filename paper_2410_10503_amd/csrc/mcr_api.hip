@@ -164,7 +164,6 @@ struct mcr_handle {
     std::vector<int> ng, off;         // gates per slice, first global gate of each slice
     int tmax = 0;                     // largest gate count
     std::vector<int> nact;            // slices still iterating at step t
-    int rmax = 1;                     // largest gather-window radius
     SlotInfo* slots = nullptr;        // device [tmax][S]
     void* tc = nullptr;               // device [S][2] (tau, c_x) in the handle's dtype
     void* pin = nullptr;              // pinned staging of slots + tc
@@ -176,7 +175,11 @@ struct mcr_handle {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const void* key[3] = {nullptr, nullptr, nullptr};  // x, z, zbar baked into the graph
+    unsigned long gen = 0;            // handle's config_gen when the graph was captured
   } batch;
+  // bumped whenever a choice that a captured launch sequence bakes in changes
+  // (projector variants, gather-window radii)
+  unsigned long config_gen = 0;
   // kernel timing
   bool prof = false;
   struct Rec {
@@ -1644,7 +1647,8 @@ mcr_status batch_launches(mcr_handle* h, T* x, T* z, T* zbar) {
     STATUS_OK(launch_warp<T>(h, 0, cnt, x, sl, n2));
     STATUS_OK((launch_project<T, 1>(h, 0, cnt, w.dy, h->sino, sl)));
     STATUS_OK(launch_backproject<T>(h, cnt, w.dy, h->sino, w.bP, h->padded, 1));
-    STATUS_OK((launch_twarp<T, 2>(h, 0, 1, nullptr, UpdateArgs<T>{x, z, zbar, T(0), T(0), 0}, sl, cnt, tc, B.rmax)));
+    STATUS_OK((launch_twarp<T, 2>(h, 0, 1, nullptr, UpdateArgs<T>{x, z, zbar, T(0), T(0), 0}, sl, cnt, tc,
+                                  max_radius(h, 0, h->N))));
   }
   return MCR_OK;
 }
@@ -1696,10 +1700,12 @@ mcr_status batch_epoch_impl(mcr_handle* h, void* x, void* z, void* zbar, void* y
   HIP_OK(hipEventRecord(B.pin_ev, h->stream));
   B.pin_recorded = true;
   if (!use_graph) return batch_launches<T>(h, (T*)x, (T*)z, (T*)zbar);
-  // graph: captured once per (x, z, zbar), replayed on the batch stream after
-  // the uploads above (event ordering keeps the caller's stream semantics)
-  if (!B.exec || B.key[0] != x || B.key[1] != z || B.key[2] != zbar) {
+  // graph: captured once per (x, z, zbar) and handle configuration (variants,
+  // window radii), replayed on the batch stream after the uploads above (event
+  // ordering keeps the caller's stream semantics)
+  if (!B.exec || B.key[0] != x || B.key[1] != z || B.key[2] != zbar || B.gen != h->config_gen) {
     if (B.exec) {
+      HIP_OK(hipStreamSynchronize(B.gstream));  // the previous replay may still run
       (void)hipGraphExecDestroy(B.exec);
       B.exec = nullptr;
     }
@@ -1727,6 +1733,7 @@ mcr_status batch_epoch_impl(mcr_handle* h, void* x, void* z, void* zbar, void* y
     B.key[0] = x;
     B.key[1] = z;
     B.key[2] = zbar;
+    B.gen = h->config_gen;
   }
   HIP_OK(hipEventRecord(B.ev_in, h->stream));
   HIP_OK(hipStreamWaitEvent(B.gstream, B.ev_in, 0));
@@ -1953,6 +1960,7 @@ mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion)
                   i, 2 * kMaxRadius + 1, 2 * kMaxRadius + 1, need);
     h->radius[i] = std::max(1, need);
   }
+  ++h->config_gen;
   STATUS_OK(upload_motion<double>(h));
   if (h->wf.ready) STATUS_OK(upload_motion<float>(h));
   return MCR_OK;
@@ -1992,6 +2000,7 @@ mcr_status mcr_set_rigid_params(mcr_handle* h, const double* params) {
   if (h->wf.ready) HIP_OK(hipMemcpyAsync(h->wf.motion, mf, bf, hipMemcpyHostToDevice, h->stream));
   HIP_OK(hipEventRecord(h->mot_ev, h->stream));
   h->mot_recorded = true;
+  ++h->config_gen;
   return MCR_OK;
 }
 
@@ -2382,6 +2391,7 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       g_tune_cache[key] = best;
     }
   }
+  ++h->config_gen;
   if (fwd) *fwd = h->tune.fwd;
   if (adj_px) *adj_px = h->tune.adj_px;
   if (adj_s) *adj_s = h->tune.adj_s;
@@ -2403,6 +2413,7 @@ mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t a
   h->tune.fwd = fwd;
   h->tune.adj_px = adj_px;
   h->tune.adj_s = adj_s;
+  ++h->config_gen;
   return MCR_OK;
 }
 
@@ -2434,7 +2445,6 @@ mcr_status mcr_batch_create(const mcr_geometry* geom, int32_t n_slices, const in
     for (int s = 0; s < n_slices; ++s) c += B.ng[s] > t;
     B.nact[t] = c;
   }
-  for (int r : h->radius) B.rmax = std::max(B.rmax, r);
   const size_t esz = dtype == MCR_F32 ? sizeof(float) : sizeof(double);
   const size_t slot_bytes = sizeof(SlotInfo) * (size_t)tmax * n_slices;
   mcr_status st = dmalloc(h, (void**)&B.slots, slot_bytes);

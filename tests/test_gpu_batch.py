@@ -136,3 +136,36 @@ def test_batched_workload_shape():
         h.spdhg_epoch(s1, [d[o + k] for k in range(P.N)], alpha[i], sig[o:o + P.N], tau[i], th[i], p[o:o + P.N],
                       seqs[i])
         assert rel(host(st["x"][i]), host(s1.x)) < 1e-6
+
+
+def test_graph_follows_motion_and_variant_changes():
+    # a captured epoch bakes in the projector variants and the transposed
+    # warp's window radius: after set_motion (a compressing field that needs a
+    # wider window) and after set_variant, graph replays still equal plain
+    # launches on a twin handle
+    probs = _make(48, 40, 70, [3, 4, 2], field_every=2)
+    alpha, sig, tau, th, p = _params(probs)
+    d = torch.cat([torch.stack([dev(v, torch.float32) for v in P.d]) for P in probs]).contiguous()
+    a, b = _batch(probs), _batch(probs)
+    for h in (a, b):
+        h.set_variant(3, 4, 2)
+    sa, sb = a.zero_batch_state(), b.zero_batch_state()
+    n = probs[0].n
+    c = (n - 1) / 2.0
+    u = np.zeros((2, n, n), np.float32)
+    u[1] = (-0.55 * (np.arange(n) - c))[:, None]   # pull-back compresses rows: q within ~2.2 px map near p
+    gate = a.offsets[1] + 1                        # a gate of the field slice
+    for e in range(3):
+        if e == 1:
+            for h in (a, b):
+                h.set_motion(gate, ("field", torch.from_numpy(u).cuda()))
+            assert a.info()["window_radius"] >= 2
+        if e == 2:
+            for h in (a, b):
+                h.set_variant(0, 2, 1)
+        seq = [g for sq in _seqs(probs, e) for g in sq]
+        a.batch_spdhg_epoch(sa, d, alpha, sig, tau, th, p, seq, use_graph=True)
+        b.batch_spdhg_epoch(sb, d, alpha, sig, tau, th, p, seq, use_graph=False)
+        torch.cuda.synchronize()
+        for k in ("x", "z", "zbar", "y"):
+            assert torch.equal(sa[k], sb[k]), (e, k)
