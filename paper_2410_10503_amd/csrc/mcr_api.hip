@@ -2344,8 +2344,12 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       const int G = gates_per_launch;
       mcr_handle::Tune best = h->tune;
       mcr_status st = MCR_OK;
-      // each variant is timed; the first one (in the order below) within 3%
-      // of the fastest is kept, so that near-ties resolve the same way run to run
+      // each variant is timed in two rounds over all candidates and keeps its
+      // faster round (the first round also brings the GPU to its sustained
+      // clocks, which otherwise favours the candidates timed last); the first
+      // one (in the order below) within 3% of the fastest is kept, so that
+      // near-ties resolve the same way run to run
+      constexpr int kRounds = 2;
       auto pick = [](const std::vector<float>& t) {
         const float lo = *std::min_element(t.begin(), t.end());
         for (size_t i = 0; i < t.size(); ++i)
@@ -2353,14 +2357,16 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
         return 0;
       };
       std::vector<int> fv;
-      std::vector<float> ft;
-      for (int f = 4; f >= 0 && st == MCR_OK; --f) {  // preferred: the newest kernel
-        if (!fwd_variant_ok(h, f)) continue;
-        h->tune.fwd = f;
-        float ms = 0.0f;
-        st = time_launches(h, [&] { return launch_project<float, 0>(h, 0, G, w.dy, h->sino); }, 5, &ms);
-        fv.push_back(f);
-        ft.push_back(st == MCR_OK ? ms : 1e30f);
+      for (int f = 4; f >= 0; --f)  // preferred: the newest kernel
+        if (fwd_variant_ok(h, f)) fv.push_back(f);
+      std::vector<float> ft(fv.size(), 1e30f);
+      for (int r = 0; r < kRounds; ++r) {
+        for (size_t i = 0; i < fv.size() && st == MCR_OK; ++i) {
+          h->tune.fwd = fv[i];
+          float ms = 0.0f;
+          st = time_launches(h, [&] { return launch_project<float, 0>(h, 0, G, w.dy, h->sino); }, 5, &ms);
+          if (st == MCR_OK) ft[i] = std::min(ft[i], ms);
+        }
       }
       if (st == MCR_OK && !fv.empty()) best.fwd = fv[pick(ft)];
       h->tune.fwd = best.fwd;
@@ -2369,15 +2375,17 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       const int cand[][2] = {{-4, 8}, {-4, 12}, {-4, 16}, {-16, 8}, {-16, 16}, {-32, 16}, {-8, 16}, {-2, 8},
                              {8, 6}, {8, 8}, {8, 4}, {4, 4}, {4, 6}, {4, 8}, {4, 2}, {4, 1}, {2, 2}, {2, 1}, {1, 1},
                              {0, 1}};
-      std::vector<float> at;
-      for (const auto& c : cand) {
-        if (st != MCR_OK) break;
-        h->tune.adj_px = c[0];
-        h->tune.adj_s = c[1];
-        float ms = 0.0f;
-        st = time_launches(h, [&] { return launch_backproject<float>(h, G, w.dy, h->sino, w.bP, h->padded, 1); }, 5,
-                           &ms);
-        at.push_back(st == MCR_OK ? ms : 1e30f);
+      const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
+      std::vector<float> at(nc, 1e30f);
+      for (int r = 0; r < kRounds; ++r) {
+        for (int i = 0; i < nc && st == MCR_OK; ++i) {
+          h->tune.adj_px = cand[i][0];
+          h->tune.adj_s = cand[i][1];
+          float ms = 0.0f;
+          st = time_launches(h, [&] { return launch_backproject<float>(h, G, w.dy, h->sino, w.bP, h->padded, 1); },
+                             5, &ms);
+          if (st == MCR_OK) at[i] = std::min(at[i], ms);
+        }
       }
       if (st == MCR_OK) {
         const int a = pick(at);
