@@ -20,8 +20,9 @@ Everything is float64 NumPy, written from the paper's definitions:
   respect to the starting image and the motion parameters (transposed iteration
   map);
 * `subsets`   - SPDHG over gates x angle subsets;
-* `registration` - rigid registration of a gate's image to the reference
-  (the preliminary step of Section I; the reading is stated there).
+* `registration` - rigid, affine and dense displacement-field registration of
+  a gate's image to the reference (the preliminary step of Section I; the
+  readings are stated there).
 
 Where the paper is silent or garbled, the readings are listed in the design
 notes: step (i) uses the extrapolated z-bar, step (iii) extrapolates from z,

@@ -29,6 +29,21 @@ u(p) = A (p - c) + t (x = column - c, y = row - c, c = (n - 1) / 2), six
 parameters (A00, A01, A10, A11, t_x, t_y), rounded to float32 per pixel as
 the library stores fields, with the same minimisation in the scaled
 coordinates (A (n - 1) / 2, t).
+
+`register_field` estimates a dense displacement field u [2][n][n] (the
+displacement maps of Section II-A themselves). The reading: u minimises
+
+    E(u) = 1/2 |D_u ref - target|^2 + lambda / 2 R(u),
+
+R(u) the sum, over both components, of the squared differences between
+horizontally and vertically adjacent pixels of the image (a discrete
+Dirichlet energy; pixels outside the image take no part). Its gradient is
+r * grad(ref)(p + u(p)) + lambda L u, r the residual and (L u)(p) the sum of
+u(p) - u(q) over the image neighbours q of p. The field is stored in
+float32, so E and its gradient are evaluated on the float32-rounded field;
+the iterate itself is kept in float64. The minimisation is the same
+Barzilai-Borwein / Armijo descent, directly in the field's pixel units, with
+`tol` bounding the Euclidean norm of the whole accepted step.
 """
 from __future__ import annotations
 
@@ -130,3 +145,46 @@ def register_affine(ref, target, theta0=(0.0,) * 6, max_iter: int = 300, tol: fl
 
     s, E, k = _minimise(ev, np.asarray(theta0, dtype=np.float64) * scale, max_iter, tol)
     return s / scale, E, k
+
+
+def field_regulariser(u) -> tuple[float, np.ndarray]:
+    """R(u) (see the module docstring) and L u, for u [2][n][n]."""
+    u = np.asarray(u, dtype=np.float64)
+    dx = np.diff(u, axis=2)  # u(r, c + 1) - u(r, c)
+    dy = np.diff(u, axis=1)  # u(r + 1, c) - u(r, c)
+    R = float(np.sum(dx * dx) + np.sum(dy * dy))
+    Lu = np.zeros_like(u)
+    Lu[:, :, :-1] -= dx
+    Lu[:, :, 1:] += dx
+    Lu[:, :-1, :] -= dy
+    Lu[:, 1:, :] += dy
+    return R, Lu
+
+
+def energy_and_grad_field(ref, target, u, lam: float, round32: bool = True) -> tuple[float, np.ndarray]:
+    """E(u) and dE/du [2][n][n] for the dense displacement field (evaluated on
+    the float32-rounded field unless round32 is False)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    ue = u.astype(np.float32).astype(np.float64) if round32 else u
+    px, py = warp.field_positions(ue)
+    r = warp.warp(ref, px, py) - np.asarray(target, dtype=np.float64)
+    gx, gy = warp.warp_gradient_at(ref, px, py)
+    R, Lu = field_regulariser(ue)
+    E = 0.5 * float(np.sum(r * r)) + 0.5 * lam * R
+    return E, np.stack([r * gx, r * gy]) + lam * Lu
+
+
+def register_field(ref, target, u0=None, lam: float = 0.1, max_iter: int = 200, tol: float = 1e-3):
+    """Returns (u [2][n][n] float64, E(u), steps taken) for the dense field,
+    started from u0 (default zero)."""
+    n = np.asarray(ref).shape[0]
+    shape = (2, n, n)
+    s0 = np.zeros(shape) if u0 is None else np.asarray(u0, dtype=np.float64)
+
+    def ev(s):
+        E, g = energy_and_grad_field(ref, target, s.reshape(shape), lam)
+        return E, g.ravel()
+
+    s, E, k = _minimise(ev, s0.ravel().copy(), max_iter, tol)
+    return s.reshape(shape), E, k
