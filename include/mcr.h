@@ -107,7 +107,9 @@ mcr_status mcr_create(const mcr_geometry* geom, int32_t n_gates, const mcr_motio
                       mcr_dtype dtype, void* stream, mcr_handle** out);
 mcr_status mcr_destroy(mcr_handle* h);
 mcr_status mcr_set_stream(mcr_handle* h, void* stream);
-/* Replace the motion of one gate (synchronises the handle's stream first). */
+/* Replace the motion of one gate (synchronises the handle's stream first).
+ * MCR_ERR_STATE if a field folds too strongly for the transposed warp's
+ * gather window; the gate is then reset to the identity.                      */
 mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion);
 /* Replace the rigid parameters of every gate at once (host [N][3] doubles:
  * phi, t_x, t_y); all gates must be rigid. Asynchronous: the update is queued
@@ -241,6 +243,24 @@ mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, cons
 mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, const void* target,
                                double* params, int32_t max_iter, double tol, double* loss,
                                int32_t* steps);
+/* Dense registration: the displacement field itself (the maps u_i of Section
+ * II-A, estimated in Section I's preliminary step). Reading: u [2][n][n]
+ * minimises
+ *   E(u) = |D_u ref - target|^2 / 2 + lambda / 2 R(u),
+ * R(u) the sum, over both components, of the squared differences between
+ * horizontally and vertically adjacent pixels of the image (a discrete
+ * Dirichlet energy), by the same descent directly on the field in pixels:
+ * u is kept in FP64 and evaluated on its float32 rounding (the field
+ * precision); tol bounds the Euclidean norm of the whole accepted step.
+ * field: device float32 [2][n][n] (u_x plane, u_y plane), the start on
+ * entry and the result on return; the gate's motion is then set to it
+ * through mcr_set_motion (MCR_ERR_STATE, gate reset to the identity, if it
+ * folds too strongly for the transposed warp's window). lambda >= 0. The
+ * gate must be a field gate. Workspace: 8 n^2 doubles, allocated on the
+ * first call. Synchronises the stream at every evaluation. On an error
+ * during the iterations the gate's field is left at the last evaluated map. */
+mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, const void* target, void* field,
+                              double lambda, int32_t max_iter, double tol, double* loss, int32_t* steps);
 
 /* ---------------------------------------------------------------------------
  * FP64 diagnostics (Theorem 1 and the model of Section II-A), computed on the

@@ -176,8 +176,18 @@ class Handle:
     def set_motion(self, gate: int, motion):
         keep = []
         m = self._motion(motion, keep)
-        _lib.check(self._lib.mcr_set_motion(self._h, int(gate), ctypes.byref(m)))
+        self._checked_motion_call(gate, lambda: self._lib.mcr_set_motion(self._h, int(gate), ctypes.byref(m)))
         self._kinds[int(gate)] = m.kind
+
+    def _checked_motion_call(self, gate, call):
+        """Runs a call that installs a gate's motion; a field rejected by the
+        gather-window check leaves the gate at the identity."""
+        try:
+            _lib.check(call())
+        except _lib.McrError as e:
+            if e.status == _lib.MCR_ERR_STATE and "reset to the identity" in str(e):
+                self._kinds[int(gate)] = _lib.MOTION_IDENTITY
+            raise
 
     def set_rigid_params(self, params):
         """All gates' rigid (phi, t_x, t_y) at once, [N][3]; queued on the stream."""
@@ -316,10 +326,29 @@ class Handle:
         self._sync_stream()
         th = (ctypes.c_double * 6)(*[float(v) for v in params])
         E, k = ctypes.c_double(), ctypes.c_int32()
-        _lib.check(self._lib.mcr_register_affine(self._h, int(gate), self._img(ref, "ref"),
-                                                 self._img(target, "target"), th, int(max_iter), float(tol),
-                                                 ctypes.byref(E), ctypes.byref(k)))
+        rp, tp = self._img(ref, "ref"), self._img(target, "target")
+        self._checked_motion_call(gate, lambda: self._lib.mcr_register_affine(
+            self._h, int(gate), rp, tp, th, int(max_iter), float(tol), ctypes.byref(E), ctypes.byref(k)))
         return tuple(th[m] for m in range(6)), E.value, k.value
+
+    def register_field(self, gate: int, ref, target, field=None, lam: float = 0.01, max_iter: int = 300,
+                       tol: float = 1e-4):
+        """Dense displacement field of field gate `gate` minimising |D_u ref - target|^2 / 2 +
+        lam / 2 R(u) (R: squared differences of adjacent pixels), from `field` (float32 [2][n][n]
+        device tensor, overwritten with the result; zero if None); the gate's field is set to it.
+        Returns (field, energy, steps)."""
+        self._sync_stream()
+        if field is None:
+            field = torch.zeros((2, self.n, self.n), dtype=torch.float32, device=self.device)
+        if not (isinstance(field, torch.Tensor) and field.dtype == torch.float32 and field.is_cuda
+                and tuple(field.shape) == (2, self.n, self.n) and field.is_contiguous()):
+            raise ValueError("field must be a contiguous float32 device tensor of shape [2][n][n]")
+        E, k = ctypes.c_double(), ctypes.c_int32()
+        rp, tp = self._img(ref, "ref"), self._img(target, "target")
+        self._checked_motion_call(gate, lambda: self._lib.mcr_register_field(
+            self._h, int(gate), rp, tp, field.data_ptr(), float(lam), int(max_iter), float(tol), ctypes.byref(E),
+            ctypes.byref(k)))
+        return field, E.value, k.value
 
     # -- FP64 diagnostics ----------------------------------------------------
     def power_norm_sq(self, gate: int, v0, max_iter: int = 500, rtol: float = 1e-12):

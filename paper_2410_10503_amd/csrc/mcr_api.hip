@@ -158,6 +158,7 @@ struct mcr_handle {
   void* reg_g = nullptr;           // [2][n*n] field gradient planes (handle dtype)
   double* reg_partial = nullptr;   // [kRedBlocks][6] moment partials
   float* reg_field = nullptr;      // [2][n*n] the result field, unpadded
+  double* reg_dense = nullptr;     // [4][2][n*n] dense registration: u, g, trial u, trial g (FP64)
   // batched SPDHG (mcr_batch_create): S independent slices sharing the geometry
   struct Batch {
     int S = 0;                        // 0: not a batch handle
@@ -1503,6 +1504,98 @@ mcr_status register_affine_impl(mcr_handle* h, int gate, const void* ref, const 
   return MCR_OK;
 }
 
+// Dense displacement-field registration of a field gate (see
+// mcr_register_field): descent on u [2][n][n] with the steps of minimise_bb,
+// the vectors on the device. Each evaluation (the gate's field planes hold
+// float32(u)): the warp, the residual and its squared norm, the motion
+// gradient planes, the regulariser's gradient and energy, |g|^2.
+template <typename T>
+mcr_status register_field_impl(mcr_handle* h, int gate, const void* ref, const void* target, float* field,
+                               double lam, int max_iter, double tol, double* loss, int32_t* steps) {
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
+  const long n2 = (long)n * n;
+  if (!h->reg_g) {
+    STATUS_OK(dmalloc(h, &h->reg_g, sizeof(double) * 2 * n2));
+    STATUS_OK(dmalloc(h, (void**)&h->reg_partial, sizeof(double) * 6 * kRedBlocks));
+    STATUS_OK(dmalloc(h, (void**)&h->reg_field, sizeof(float) * 2 * n2));
+  }
+  if (!h->reg_dense) STATUS_OK(dmalloc(h, (void**)&h->reg_dense, sizeof(double) * 8 * n2));
+  double* u = h->reg_dense;
+  double* g = u + 2 * n2;
+  double* u1 = g + 2 * n2;
+  double* g1 = u1 + 2 * n2;
+  float* fP = h->fieldP + (long)gate * 2 * h->padded;
+  const dim3 grid(cdiv(n, 16), cdiv(n, 16)), block(16, 16);
+  auto eval = [&](double* gout, double& E, double& gsq) -> mcr_status {
+    STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)ref));
+    hipLaunchKernelGGL(k_residual_padded<T>, grid, block, 0, h->stream, n, h->pitch, w.wP, (const T*)target, w.bP);
+    LAUNCH_OK();
+    STATUS_OK((launch_reduce<T, T, 0>(h, h->padded, w.bP, w.bP, 0)));
+    HIP_OK(hipMemsetAsync(h->reg_g, 0, sizeof(T) * 2 * n2, h->stream));
+    STATUS_OK(launch_motion_grad<T>(h, gate, w.bP, (const T*)ref, h->reg_g));
+    hipLaunchKernelGGL(k_field_reg_grad<T>, dim3(kRedBlocks), dim3(256), 0, h->stream, n, h->pitch, h->padded, fP,
+                       (const T*)h->reg_g, lam, gout, h->red_partial);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, 1);
+    LAUNCH_OK();
+    STATUS_OK((launch_reduce<double, double, 0>(h, 2 * n2, gout, gout, 2)));
+    STATUS_OK(read_results(h, 3));
+    E = 0.5 * h->red_host[0] + 0.5 * lam * h->red_host[1];
+    gsq = h->red_host[2];
+    return MCR_OK;
+  };
+  hipLaunchKernelGGL(k_field_load, grid, block, 0, h->stream, n, h->pitch, h->padded, (const float*)field, u, fP);
+  LAUNCH_OK();
+  double E = 0.0, gsq = 0.0;
+  STATUS_OK(eval(g, E, gsq));
+  double gn = std::sqrt(gsq);
+  double alpha = gn > 0 ? 1.0 / gn : 1.0;
+  int k = 0;
+  while (k < max_iter && gn > 0) {
+    double En = 0.0, gsqn = 0.0;
+    for (int t = 0; t < 41; ++t) {
+      hipLaunchKernelGGL(k_field_trial, grid, block, 0, h->stream, n, h->pitch, h->padded, u, g, alpha, u1, fP);
+      LAUNCH_OK();
+      STATUS_OK(eval(g1, En, gsqn));
+      if (En <= E - 1e-4 * alpha * gn * gn) break;
+      alpha *= 0.5;
+    }
+    ++k;
+    const double step = alpha * gn;
+    hipLaunchKernelGGL(k_dot_diff, dim3(kRedBlocks), dim3(256), 0, h->stream, 2 * n2, u1, u, g1, g, h->red_partial);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, 0);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_dot_diff, dim3(kRedBlocks), dim3(256), 0, h->stream, 2 * n2, u1, u, u1, u, h->red_partial);
+    LAUNCH_OK();
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, 1);
+    LAUNCH_OK();
+    STATUS_OK(read_results(h, 2));
+    const double sy = h->red_host[0], ss = h->red_host[1];
+    std::swap(u, u1);
+    std::swap(g, g1);
+    E = En;
+    gn = std::sqrt(gsqn);
+    if (step < tol) break;
+    alpha = sy > 0 ? ss / sy : 2.0 * alpha;
+  }
+  // the planes hold float32(u) of the last evaluation, the accepted iterate:
+  // hand it back and install it as the gate's field (gather-window set-up
+  // and check)
+  for (int pl = 0; pl < 2; ++pl) {
+    hipLaunchKernelGGL(k_from_padded<float>, grid, block, 0, h->stream, n, h->pitch, fP + pl * h->padded,
+                       field + pl * n2);
+    LAUNCH_OK();
+  }
+  if (loss) *loss = E;
+  if (steps) *steps = k;
+  mcr_motion m{};
+  m.kind = MCR_MOTION_FIELD;
+  m.field = field;
+  return mcr_set_motion(h, gate, &m);
+}
+
 // ---------------------------------------------------------------------------
 // Operators
 // ---------------------------------------------------------------------------
@@ -1954,10 +2047,20 @@ mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion)
     int need = 0;
     HIP_OK(hipMemcpyAsync(&need, h->need, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIP_OK(hipStreamSynchronize(h->stream));
-    if (need > kMaxRadius)
+    if (need > kMaxRadius) {
+      // leave a consistent handle: the gate's field planes already hold the
+      // rejected field, so the gate falls back to the identity
+      h->motion[i].kind = MCR_MOTION_IDENTITY;
+      h->motion[i].field = nullptr;
+      h->radius[i] = 1;
+      ++h->config_gen;
+      STATUS_OK(upload_motion<double>(h));
+      if (h->wf.ready) STATUS_OK(upload_motion<float>(h));
       return fail(MCR_ERR_STATE,
-                  "gate %d: the displacement field folds too strongly for a %dx%d transposed-warp window (needs %d)",
+                  "gate %d: the displacement field folds too strongly for a %dx%d transposed-warp window (needs %d); "
+                  "the gate is reset to the identity",
                   i, 2 * kMaxRadius + 1, 2 * kMaxRadius + 1, need);
+    }
     h->radius[i] = std::max(1, need);
   }
   ++h->config_gen;
@@ -2161,6 +2264,20 @@ mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, con
   if (max_iter < 0) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 0", max_iter);
   if (!(tol >= 0) || !std::isfinite(tol)) return fail(MCR_ERR_ARG, "tol must be finite and >= 0");
   return DISPATCH(register_affine_impl, h, gate, ref, target, params, max_iter, tol, loss, steps);
+}
+
+mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, const void* target, void* field,
+                              double lambda, int32_t max_iter, double tol, double* loss, int32_t* steps) {
+  STATUS_OK(check_handle(h));
+  STATUS_OK(check_gate(h, gate));
+  STATUS_OK(check_ptr(ref, "ref"));
+  STATUS_OK(check_ptr(target, "target"));
+  STATUS_OK(check_ptr(field, "field"));
+  if (h->motion[gate].kind != MCR_MOTION_FIELD) return fail(MCR_ERR_ARG, "gate %d is not a field gate", gate);
+  if (!(lambda >= 0) || !std::isfinite(lambda)) return fail(MCR_ERR_ARG, "lambda must be finite and >= 0");
+  if (max_iter < 0) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 0", max_iter);
+  if (!(tol >= 0) || !std::isfinite(tol)) return fail(MCR_ERR_ARG, "tol must be finite and >= 0");
+  return DISPATCH(register_field_impl, h, gate, ref, target, (float*)field, lambda, max_iter, tol, loss, steps);
 }
 
 mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, const void* target, double* params,

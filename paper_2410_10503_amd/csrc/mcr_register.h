@@ -86,4 +86,93 @@ __global__ __launch_bounds__(256) void k_affine_moments_final(const double* __re
   }
 }
 
+// Dense displacement-field registration: the iterate u [2][n*n] (FP64) and
+// its float32 rounding in the gate's padded field planes (plane_stride
+// apart), which the warp and the motion gradient read.
+//   k_field_load:  u = f (the caller's float32 field), planes = f
+//   k_field_trial: u_new = u - alpha g, planes = float(u_new)
+// grid (ceil(n/16), ceil(n/16)), block (16, 16)
+__global__ __launch_bounds__(256) void k_field_load(int n, int pitch, long plane_stride, const float* __restrict__ f,
+                                                    double* __restrict__ u, float* __restrict__ fP) {
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c >= n || r >= n) return;
+  const long n2 = (long)n * n, q = (long)r * n + c, o = (long)(r + kPad) * pitch + c + kPad;
+  for (int pl = 0; pl < 2; ++pl) {
+    const float v = f[pl * n2 + q];
+    u[pl * n2 + q] = double(v);
+    fP[pl * plane_stride + o] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_field_trial(int n, int pitch, long plane_stride,
+                                                     const double* __restrict__ u, const double* __restrict__ g,
+                                                     double alpha, double* __restrict__ u_new,
+                                                     float* __restrict__ fP) {
+#pragma clang fp contract(off)
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c >= n || r >= n) return;
+  const long n2 = (long)n * n, q = (long)r * n + c, o = (long)(r + kPad) * pitch + c + kPad;
+  for (int pl = 0; pl < 2; ++pl) {
+    const double step = alpha * g[pl * n2 + q];
+    const double v = u[pl * n2 + q] - step;
+    u_new[pl * n2 + q] = v;
+    fP[pl * plane_stride + o] = float(v);
+  }
+}
+
+// Gradient of the regularised misfit from the data part gd (the motion
+// gradient planes, handle dtype): g = gd + lam L u, (L u)(p) the sum of
+// u(p) - u(q) over the image neighbours q of p, u the float32 field planes;
+// partial[block] = the block's share of R(u), the squared differences of
+// horizontally and vertically adjacent pixels (both components). Grid-stride
+// over the pixels: grid kRedBlocks, block 256.
+template <typename T>
+__global__ __launch_bounds__(256) void k_field_reg_grad(int n, int pitch, long plane_stride,
+                                                        const float* __restrict__ fP, const T* __restrict__ gd,
+                                                        double lam, double* __restrict__ g,
+                                                        double* __restrict__ partial) {
+  __shared__ double sh[4];
+  const long n2 = (long)n * n;
+  const long origin = (long)kPad * pitch + kPad;
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n2; i += (long)kRedBlocks * 256) {
+    const int r = (int)(i / n), c = (int)(i % n);
+    for (int pl = 0; pl < 2; ++pl) {
+      const float* u = fP + pl * plane_stride + origin + (long)r * pitch + c;
+      const double v = double(u[0]);
+      double L = 0.0;
+      if (c + 1 < n) {
+        const double d = double(u[1]) - v;
+        L -= d;
+        acc = __builtin_fma(d, d, acc);
+      }
+      if (c > 0) L += v - double(u[-1]);
+      if (r + 1 < n) {
+        const double d = double(u[pitch]) - v;
+        L -= d;
+        acc = __builtin_fma(d, d, acc);
+      }
+      if (r > 0) L += v - double(u[-pitch]);
+      g[pl * n2 + i] = double(gd[pl * n2 + i]) + lam * L;
+    }
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// partial[block] = the block's share of sum (a1 - a0)(b1 - b0) (FP64), for the
+// Barzilai-Borwein step lengths. Grid-stride: grid kRedBlocks, block 256.
+__global__ __launch_bounds__(256) void k_dot_diff(long count, const double* __restrict__ a1,
+                                                  const double* __restrict__ a0, const double* __restrict__ b1,
+                                                  const double* __restrict__ b0, double* __restrict__ partial) {
+  __shared__ double sh[4];
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < count; i += (long)kRedBlocks * 256)
+    acc = __builtin_fma(a1[i] - a0[i], b1[i] - b0[i], acc);
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
 }  // namespace mcr

@@ -139,3 +139,7 @@ def test_register_affine_rejects_null_handle(lib):
     th = (ctypes.c_double * 6)()
     assert lib.mcr_register_affine(None, 0, None, None, th, 10, 1e-6, None, None) == _lib.MCR_ERR_ARG
     assert b"null handle" in lib.mcr_last_error()
+
+
+def test_register_field_rejects_null_handle(lib):
+    assert lib.mcr_register_field(None, 0, None, None, None, 0.1, 10, 1e-4, None, None) == _lib.MCR_ERR_ARG

@@ -175,3 +175,145 @@ def test_affine_registration_arguments():
         h.register_affine(0, x, x, params=(0.0, float("inf"), 0.0, 0.0, 0.0, 0.0))
     th, E, k = h.register_affine(1, x, x)
     assert k == 0 and E == 0.0
+
+
+# -- dense displacement fields (mcr_register_field) ---------------------------
+
+def _bump_field(n, ax, ay, sigma):
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    c = (n - 1) / 2.0
+    b = np.exp(-((xx - c) ** 2 + (yy - c) ** 2) / (2 * sigma * sigma))
+    return f32(np.stack([ax * b, ay * b]))
+
+
+def _field_target(ref, u):
+    return f32(warp.warp(ref, *warp.field_positions(u)))
+
+
+def test_fp64_field_registration_matches_oracle():
+    n = 48
+    P = Problem(n, 40, 70, 2, "field")
+    ref = _ref(n)
+    tgt = _field_target(ref, _bump_field(n, 1.2, -0.8, 10.0))
+    u_o, E_o, k_o = oreg.register_field(ref, tgt, lam=0.01, max_iter=60, tol=1e-4)
+    h = P.handle(torch.float64)
+    u, E, k = h.register_field(1, dev(ref, torch.float64), dev(tgt, torch.float64), lam=0.01, max_iter=60,
+                               tol=1e-4)
+    # the same iteration on the same data: the same path up to rounding
+    print("fp64 field registration: steps", k, k_o, "E", E, E_o)
+    assert k == k_o
+    assert np.abs(u.cpu().numpy() - f32(u_o)).max() < 1e-5
+    assert abs(E - E_o) <= 1e-9 * E_o
+
+
+def test_field_energy_at_start_and_installed_field():
+    n = 48
+    P = Problem(n, 40, 70, 2, "field")
+    ref, tgt = _ref(n), _field_target(_ref(n, seed=5), _bump_field(n, 0.7, 0.4, 8.0))
+    rng = np.random.default_rng(3)
+    start = f32(_bump_field(n, -0.5, 0.9, 12.0) + rng.uniform(-0.2, 0.2, size=(2, n, n)))
+    lam = 0.2
+    E_o, _ = oreg.energy_and_grad_field(ref, tgt, start, lam)
+    b = f32(synth.random_image(n, 8))
+    pos = warp.field_positions(start)
+    for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        h = P.handle(dtype)
+        f = torch.from_numpy(start.astype(np.float32)).cuda()
+        u, E, k = h.register_field(0, dev(ref, dtype), dev(tgt, dtype), field=f, lam=lam, max_iter=0)
+        assert k == 0 and torch.equal(u.cpu(), torch.from_numpy(start.astype(np.float32)))
+        assert abs(E - E_o) <= bar * E_o, (dtype, E, E_o)
+        # the gate now carries the start field: warp and transposed warp
+        assert np.abs(h.warp(0, dev(ref, dtype)).cpu().numpy() - warp.warp(ref, *pos)).max() <= 10 * bar
+        wt = h.warp_adjoint(0, dev(b, dtype)).cpu().numpy()
+        ref_wt = warp.warp_adjoint(b, *pos)
+        assert np.linalg.norm(wt - ref_wt) <= 10 * bar * np.linalg.norm(ref_wt)
+
+
+def test_fp32_field_registration_tracks_oracle():
+    n = 64
+    P = Problem(n, 40, 92, 2, "field")
+    ref = _ref(n)
+    ustar = _bump_field(n, 1.5, -1.0, 12.0)
+    tgt = _field_target(ref, ustar)
+    h = P.handle(torch.float32)
+    rd, td = dev(ref, torch.float32), dev(tgt, torch.float32)
+    # the first step (the normalised gradient, halved by the same Armijo
+    # tests): float32 rounding of the gradient only
+    u1_o, E1_o, _ = oreg.register_field(ref, tgt, lam=0.01, max_iter=1, tol=1e-4)
+    u1, E1, k1 = h.register_field(1, rd, td, lam=0.01, max_iter=1, tol=1e-4)
+    assert k1 == 1
+    assert np.abs(u1.cpu().numpy() - u1_o).max() < 1e-4
+    assert abs(E1 - E1_o) <= 1e-4 * E1_o
+    # 40 steps: the Barzilai-Borwein lengths amplify the rounding, so the
+    # paths part; both descend alike (energy, distance to the true field)
+    u_o, E_o, k_o = oreg.register_field(ref, tgt, lam=0.01, max_iter=40, tol=1e-4)
+    u, E, k = h.register_field(1, rd, td, field=torch.zeros(2, n, n, device="cuda"), lam=0.01, max_iter=40,
+                               tol=1e-4)
+    gm = np.hypot(*np.gradient(ref))
+    m = gm > 0.1 * gm.max()
+    err = np.sqrt(np.mean(np.sum((u.cpu().numpy() - ustar) ** 2, axis=0)[m]))
+    err_o = np.sqrt(np.mean(np.sum((u_o - ustar) ** 2, axis=0)[m]))
+    print("fp32 field registration: steps", k, k_o, "E", E, E_o, "rms error", err, err_o)
+    assert abs(E - E_o) <= 5e-2 * E_o
+    assert err <= 1.2 * err_o + 0.01
+
+
+def test_full_size_fp32_affine_then_dense():
+    # 512^2 (the headline image size): a vertical dilatation of up to 4 px at
+    # the edges plus a smooth bump of up to 2 px; the affine registration
+    # takes the dilatation, the dense registration started from its field
+    # then lowers the misfit and the distance to the true field further (a
+    # single-level descent: slow on this smooth reference, so 300 steps give
+    # a partial refinement; the FP64 oracle on the same problem reaches 0.68
+    # of the affine misfit and 0.82 of its field error)
+    n = 512
+    P = Problem(n, 720, 730, 2, "field")
+    h = P.handle(torch.float32)
+    ref = _ref(n)
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    c = (n - 1) / 2.0
+    b = np.exp(-((xx - c - 0.1 * n) ** 2 + (yy - c) ** 2) / (2 * (0.12 * n) ** 2))
+    ustar = f32(np.stack([2.0 * b, -1.4 * b + 4.0 * (yy - c) / c]))
+    tgt = _field_target(ref, ustar)
+    rd, td = dev(ref, torch.float32), dev(tgt, torch.float32)
+    th, Ea, ka = h.register_affine(1, rd, td, max_iter=300, tol=1e-5)
+    ua = f32(np.stack([(th[0] * (xx - c) + th[1] * (yy - c)) + th[4], (th[2] * (xx - c) + th[3] * (yy - c)) + th[5]]))
+    lam = 0.1
+    E_aff, _ = oreg.energy_and_grad_field(ref, tgt, ua, lam)
+    u, E, k = h.register_field(1, rd, td, field=torch.from_numpy(ua.astype(np.float32)).cuda(), lam=lam,
+                               max_iter=300, tol=1e-3)
+    gm = np.hypot(*np.gradient(ref))
+    m = gm > 0.1 * gm.max()
+    rms = lambda v: np.sqrt(np.mean(np.sum(v ** 2, axis=0)[m]))  # noqa: E731
+    err_aff, err = rms(ua - ustar), rms(u.cpu().numpy() - ustar)
+    print("512^2: affine", ka, "steps; dense", k, "steps, E", E_aff, "->", E, "rms error", err_aff, "->", err)
+    assert E <= 0.8 * E_aff
+    assert err <= 0.9 * err_aff
+    # the gate's field is the result
+    w = h.warp(1, rd).cpu().numpy()
+    assert np.abs(w - warp.warp(ref, *warp.field_positions(u.cpu().numpy()))).max() < 1e-4
+
+
+def test_field_registration_arguments():
+    from paper_2410_10503_amd import McrError
+    R = Problem(32, 20, 48, 2, "rigid")
+    hr = R.handle(torch.float32)
+    x = torch.zeros(32, 32, device="cuda")
+    with pytest.raises(McrError, match="not a field gate"):
+        hr.register_field(0, x, x)
+    P = Problem(32, 20, 48, 2, "field")
+    h = P.handle(torch.float32)
+    with pytest.raises(McrError, match="lambda"):
+        h.register_field(0, x, x, lam=-1.0)
+    u, E, k = h.register_field(1, x, x)
+    assert k == 0 and E == 0.0 and not u.any()
+    # a start field that compresses the rows tenfold needs a wider gather
+    # window than the transposed warp has: the gate falls back to the identity
+    n = 32
+    yy = np.mgrid[0:n, 0:n][0].astype(np.float64)
+    fold = np.zeros((2, n, n), np.float32)
+    fold[1] = -0.9 * (yy - (n - 1) / 2.0)
+    img = dev(f32(synth.random_image(n, 2)), torch.float32)
+    with pytest.raises(McrError, match="reset to the identity"):
+        h.register_field(0, img, img, field=torch.from_numpy(fold).cuda(), max_iter=0)
+    assert torch.equal(h.warp(0, img), img)
