@@ -44,6 +44,14 @@ float32, so E and its gradient are evaluated on the float32-rounded field;
 the iterate itself is kept in float64. The minimisation is the same
 Barzilai-Borwein / Armijo descent, directly in the field's pixel units, with
 `tol` bounding the Euclidean norm of the whole accepted step.
+
+A single level of that descent converges slowly when the images are smooth
+or piecewise constant and the displacement spans several pixels. The
+reading adds a scale-space schedule: for each width sigma of a given list
+(pixels, decreasing; 0 = no smoothing) both images are smoothed with the
+separable Gaussian of that width (weights exp(-k^2 / (2 sigma^2)) for
+|k| <= int(3 sigma + 0.5), normalised to sum 1, zero outside the image) and
+the descent runs from the previous level's field.
 """
 from __future__ import annotations
 
@@ -175,16 +183,50 @@ def energy_and_grad_field(ref, target, u, lam: float, round32: bool = True) -> t
     return E, np.stack([r * gx, r * gy]) + lam * Lu
 
 
-def register_field(ref, target, u0=None, lam: float = 0.1, max_iter: int = 200, tol: float = 1e-3):
-    """Returns (u [2][n][n] float64, E(u), steps taken) for the dense field,
-    started from u0 (default zero)."""
+def gaussian_smooth(img, sigma: float) -> np.ndarray:
+    """The separable Gaussian of width sigma (see the module docstring),
+    along columns then rows, zero outside the image; sigma = 0: a copy."""
+    img = np.asarray(img, dtype=np.float64)
+    if sigma == 0:
+        return img.copy()
+    R = int(3.0 * sigma + 0.5)
+    k = np.arange(-R, R + 1, dtype=np.float64)
+    w = np.exp(-k * k / (2.0 * sigma * sigma))
+    w /= w.sum()
+    n = img.shape[0]
+    out = img
+    for axis in (1, 0):
+        acc = np.zeros_like(out)
+        for j, wj in zip(range(-R, R + 1), w):
+            # acc[p] += w_j * out[p + j e_axis], zero outside the image
+            src = [slice(None), slice(None)]
+            dst = [slice(None), slice(None)]
+            if j >= 0:
+                src[axis], dst[axis] = slice(j, n), slice(0, n - j)
+            else:
+                src[axis], dst[axis] = slice(0, n + j), slice(-j, n)
+            acc[tuple(dst)] += wj * out[tuple(src)]
+        out = acc
+    return out
+
+
+def register_field(ref, target, u0=None, lam: float = 0.1, max_iter: int = 200, tol: float = 1e-3,
+                   sigmas=()):
+    """Returns (u [2][n][n] float64, E(u) of the last level, steps taken over
+    all levels) for the dense field, started from u0 (default zero); sigmas:
+    the scale-space schedule (empty: one level on the images themselves),
+    max_iter and tol per level."""
     n = np.asarray(ref).shape[0]
     shape = (2, n, n)
-    s0 = np.zeros(shape) if u0 is None else np.asarray(u0, dtype=np.float64)
+    s = (np.zeros(shape) if u0 is None else np.asarray(u0, dtype=np.float64)).ravel().copy()
+    E, k_total = 0.0, 0
+    for sigma in (tuple(sigmas) or (0.0,)):
+        rs, ts = gaussian_smooth(ref, sigma), gaussian_smooth(target, sigma)
 
-    def ev(s):
-        E, g = energy_and_grad_field(ref, target, s.reshape(shape), lam)
-        return E, g.ravel()
+        def ev(v, rs=rs, ts=ts):
+            Ev, g = energy_and_grad_field(rs, ts, v.reshape(shape), lam)
+            return Ev, g.ravel()
 
-    s, E, k = _minimise(ev, s0.ravel().copy(), max_iter, tol)
-    return s.reshape(shape), E, k
+        s, E, k = _minimise(ev, s, max_iter, tol)
+        k_total += k
+    return s.reshape(shape), E, k_total

@@ -171,3 +171,35 @@ def test_field_recovers_smooth_displacement():
     err = np.sqrt(np.mean(np.sum((u - ustar) ** 2, axis=0)[m]))
     err0 = np.sqrt(np.mean(np.sum(ustar ** 2, axis=0)[m]))
     assert err < 0.15 and err < 0.2 * err0, (err, err0)
+
+
+@pytest.mark.parametrize("sigma", [0.7, 1.0, 2.5, 4.0])
+def test_gaussian_smooth_is_the_library_gaussian_filter(sigma):
+    # the scale-space smoothing against scipy's Gaussian filter with the
+    # same truncation (radius int(3 sigma + 0.5)) and zero boundary
+    rng = np.random.default_rng(1)
+    img = rng.standard_normal((37, 37))
+    ref = ndimage.gaussian_filter(img, sigma, mode="constant", cval=0.0, truncate=3.0)
+    assert np.abs(reg.gaussian_smooth(img, sigma) - ref).max() < 1e-14
+    assert np.array_equal(reg.gaussian_smooth(img, 0.0), img)
+
+
+def test_field_scale_space_schedule():
+    # a zero-width schedule is the single level; a coarse-to-fine schedule
+    # recovers a displacement of a few pixels that one level leaves far off
+    n = 64
+    ref = _ref(n, blur=2.0)
+    yy = np.mgrid[0:n, 0:n][0].astype(np.float64)
+    ustar = _bump_field(n, 1.0, -0.7, 8.0)
+    ustar[1] += 1.6 * (yy - (n - 1) / 2.0) / ((n - 1) / 2.0)
+    ustar = ustar.astype(np.float32).astype(np.float64)
+    target = warp.warp(ref, *warp.field_positions(ustar))
+    u1, E1, k1 = reg.register_field(ref, target, lam=0.1, max_iter=120, tol=1e-3)
+    u0, E0, k0 = reg.register_field(ref, target, lam=0.1, max_iter=120, tol=1e-3, sigmas=(0.0,))
+    assert k0 == k1 and E0 == E1 and np.array_equal(u0, u1)
+    us, Es, ks = reg.register_field(ref, target, lam=0.1, max_iter=120, tol=1e-3, sigmas=(4.0, 2.0, 1.0, 0.0))
+    gm = np.hypot(*np.gradient(ref))
+    m = gm > 0.1 * gm.max()
+    rms = lambda v: np.sqrt(np.mean(np.sum(v ** 2, axis=0)[m]))  # noqa: E731
+    assert rms(us - ustar) < 0.5 * rms(u1 - ustar), (rms(us - ustar), rms(u1 - ustar))
+    assert Es < 0.5 * E1
