@@ -252,15 +252,24 @@ mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, con
  * Dirichlet energy), by the same descent directly on the field in pixels:
  * u is kept in FP64 and evaluated on its float32 rounding (the field
  * precision); tol bounds the Euclidean norm of the whole accepted step.
+ * Scale-space schedule: for each width sigmas[l] (pixels; a host array of
+ * n_levels in [0, 16], each in [0, 32]; 0 = no smoothing) both images are
+ * smoothed with the separable Gaussian exp(-k^2 / (2 sigma^2)),
+ * |k| <= int(3 sigma + 0.5), normalised, zero outside the image, and the
+ * descent (max_iter, tol per level) runs on them from the previous level's
+ * field; n_levels = 0: one level on the images themselves. loss: E of the
+ * last level; steps: summed over the levels.
  * field: device float32 [2][n][n] (u_x plane, u_y plane), the start on
  * entry and the result on return; the gate's motion is then set to it
  * through mcr_set_motion (MCR_ERR_STATE, gate reset to the identity, if it
  * folds too strongly for the transposed warp's window). lambda >= 0. The
- * gate must be a field gate. Workspace: 8 n^2 doubles, allocated on the
- * first call. Synchronises the stream at every evaluation. On an error
- * during the iterations the gate's field is left at the last evaluated map. */
+ * gate must be a field gate. Workspace: 8 n^2 doubles (3 n^2 more with
+ * levels), allocated on the first call. Synchronises the stream at every
+ * evaluation. On an error during the iterations the gate's field is left at
+ * the last evaluated map.                                                     */
 mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, const void* target, void* field,
-                              double lambda, int32_t max_iter, double tol, double* loss, int32_t* steps);
+                              double lambda, const double* sigmas, int32_t n_levels, int32_t max_iter,
+                              double tol, double* loss, int32_t* steps);
 
 /* ---------------------------------------------------------------------------
  * FP64 diagnostics (Theorem 1 and the model of Section II-A), computed on the

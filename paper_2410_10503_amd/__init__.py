@@ -332,11 +332,12 @@ class Handle:
         return tuple(th[m] for m in range(6)), E.value, k.value
 
     def register_field(self, gate: int, ref, target, field=None, lam: float = 0.01, max_iter: int = 300,
-                       tol: float = 1e-4):
+                       tol: float = 1e-4, sigmas=()):
         """Dense displacement field of field gate `gate` minimising |D_u ref - target|^2 / 2 +
         lam / 2 R(u) (R: squared differences of adjacent pixels), from `field` (float32 [2][n][n]
         device tensor, overwritten with the result; zero if None); the gate's field is set to it.
-        Returns (field, energy, steps)."""
+        sigmas: scale-space schedule (Gaussian widths in pixels, coarse to fine; empty: one level
+        on the images themselves). Returns (field, energy, steps)."""
         self._sync_stream()
         if field is None:
             field = torch.zeros((2, self.n, self.n), dtype=torch.float32, device=self.device)
@@ -345,9 +346,11 @@ class Handle:
             raise ValueError("field must be a contiguous float32 device tensor of shape [2][n][n]")
         E, k = ctypes.c_double(), ctypes.c_int32()
         rp, tp = self._img(ref, "ref"), self._img(target, "target")
+        sg = [float(v) for v in sigmas]
+        sga = (ctypes.c_double * max(1, len(sg)))(*sg)
         self._checked_motion_call(gate, lambda: self._lib.mcr_register_field(
-            self._h, int(gate), rp, tp, field.data_ptr(), float(lam), int(max_iter), float(tol), ctypes.byref(E),
-            ctypes.byref(k)))
+            self._h, int(gate), rp, tp, field.data_ptr(), float(lam), sga, len(sg), int(max_iter), float(tol),
+            ctypes.byref(E), ctypes.byref(k)))
         return field, E.value, k.value
 
     # -- FP64 diagnostics ----------------------------------------------------

@@ -71,7 +71,7 @@ SIGNATURES = {
     "mcr_warp_motion_grad": [_P, _I, _P, _P, _P],
     "mcr_register_rigid": [_P, _I, _P, _P, _PD, _I, _D, _PD, _PI],
     "mcr_register_affine": [_P, _I, _P, _P, _PD, _I, _D, _PD, _PI],
-    "mcr_register_field": [_P, _I, _P, _P, _P, _D, _I, _D, _PD, _PI],
+    "mcr_register_field": [_P, _I, _P, _P, _P, _D, _PD, _I, _I, _D, _PD, _PI],
     "mcr_batch_create": [ctypes.POINTER(Geometry), _I, _PI, ctypes.POINTER(Motion), _I, _P, ctypes.POINTER(_P)],
     "mcr_batch_spdhg_epoch": [_P, _P, _P, _P, _P, _P, _PD, _PD, _PD, _PD, _PD, _PI, _I],
     "mcr_profile_enable": [_P, _I],

@@ -58,6 +58,9 @@ inline unsigned cdiv(long a, long b) { return (unsigned)((a + b - 1) / b); }
 
 constexpr int kFwdKA = 8, kFwdJD = 32, kFwdWL = 128;  // tiled forward: angles, bins, LDS row
 constexpr int kMaxShares = 16;                          // tiled adjoint: angle shares
+constexpr double kMaxBlurSigma = 32.0;  // widest scale-space Gaussian of the dense registration (px)
+constexpr int kMaxBlurRadius = 96;      // int(3 kMaxBlurSigma + 0.5)
+constexpr int kMaxLevels = 16;          // scale-space levels per dense registration
 
 
 // Per-precision workspace and tables.
@@ -159,6 +162,8 @@ struct mcr_handle {
   double* reg_partial = nullptr;   // [kRedBlocks][6] moment partials
   float* reg_field = nullptr;      // [2][n*n] the result field, unpadded
   double* reg_dense = nullptr;     // [4][2][n*n] dense registration: u, g, trial u, trial g (FP64)
+  double* reg_blur = nullptr;      // [3][n*n] smoothed reference, target and a pass in between (handle dtype)
+  double* reg_w = nullptr;         // [2 kMaxBlurRadius + 1] Gaussian weights
   // batched SPDHG (mcr_batch_create): S independent slices sharing the geometry
   struct Batch {
     int S = 0;                        // 0: not a batch handle
@@ -1510,8 +1515,9 @@ mcr_status register_affine_impl(mcr_handle* h, int gate, const void* ref, const 
 // float32(u)): the warp, the residual and its squared norm, the motion
 // gradient planes, the regulariser's gradient and energy, |g|^2.
 template <typename T>
-mcr_status register_field_impl(mcr_handle* h, int gate, const void* ref, const void* target, float* field,
-                               double lam, int max_iter, double tol, double* loss, int32_t* steps) {
+mcr_status register_field_impl(mcr_handle* h, int gate, const void* ref0, const void* target0, float* field,
+                               double lam, const double* sigmas, int n_levels, int max_iter, double tol,
+                               double* loss, int32_t* steps) {
   Work<T>& w = work<T>(h);
   const int n = h->geo.n;
   const long n2 = (long)n * n;
@@ -1521,6 +1527,12 @@ mcr_status register_field_impl(mcr_handle* h, int gate, const void* ref, const v
     STATUS_OK(dmalloc(h, (void**)&h->reg_field, sizeof(float) * 2 * n2));
   }
   if (!h->reg_dense) STATUS_OK(dmalloc(h, (void**)&h->reg_dense, sizeof(double) * 8 * n2));
+  if (n_levels > 0 && !h->reg_blur) {
+    STATUS_OK(dmalloc(h, (void**)&h->reg_blur, sizeof(double) * 3 * n2));
+    STATUS_OK(dmalloc(h, (void**)&h->reg_w, sizeof(double) * (2 * kMaxBlurRadius + 1)));
+  }
+  const void* ref = ref0;
+  const void* target = target0;
   double* u = h->reg_dense;
   double* g = u + 2 * n2;
   double* u1 = g + 2 * n2;
@@ -1547,38 +1559,71 @@ mcr_status register_field_impl(mcr_handle* h, int gate, const void* ref, const v
   };
   hipLaunchKernelGGL(k_field_load, grid, block, 0, h->stream, n, h->pitch, h->padded, (const float*)field, u, fP);
   LAUNCH_OK();
-  double E = 0.0, gsq = 0.0;
-  STATUS_OK(eval(g, E, gsq));
-  double gn = std::sqrt(gsq);
-  double alpha = gn > 0 ? 1.0 / gn : 1.0;
-  int k = 0;
-  while (k < max_iter && gn > 0) {
-    double En = 0.0, gsqn = 0.0;
-    for (int t = 0; t < 41; ++t) {
-      hipLaunchKernelGGL(k_field_trial, grid, block, 0, h->stream, n, h->pitch, h->padded, u, g, alpha, u1, fP);
-      LAUNCH_OK();
-      STATUS_OK(eval(g1, En, gsqn));
-      if (En <= E - 1e-4 * alpha * gn * gn) break;
-      alpha *= 0.5;
+  // scale-space levels (none given: one level on the images themselves)
+  double E = 0.0;
+  int k_total = 0;
+  std::vector<double> wts;
+  for (int level = 0; level < std::max(1, n_levels); ++level) {
+    const double sigma = n_levels > 0 ? sigmas[level] : 0.0;
+    if (sigma > 0) {
+      const int R = (int)(3.0 * sigma + 0.5);
+      wts.assign(2 * R + 1, 0.0);
+      double sum = 0.0;
+      for (int j = -R; j <= R; ++j) sum += (wts[j + R] = std::exp(-double(j) * j / (2.0 * sigma * sigma)));
+      for (double& v : wts) v /= sum;
+      HIP_OK(hipMemcpyAsync(h->reg_w, wts.data(), sizeof(double) * wts.size(), hipMemcpyHostToDevice, h->stream));
+      T* rb = (T*)h->reg_blur;
+      T* tb = rb + n2;
+      T* tmp = tb + n2;
+      for (int im = 0; im < 2; ++im) {
+        hipLaunchKernelGGL((k_blur<T, 1>), grid, block, 0, h->stream, n, R, h->reg_w,
+                           (const T*)(im == 0 ? ref0 : target0), tmp);
+        LAUNCH_OK();
+        hipLaunchKernelGGL((k_blur<T, 0>), grid, block, 0, h->stream, n, R, h->reg_w, (const T*)tmp,
+                           im == 0 ? rb : tb);
+        LAUNCH_OK();
+      }
+      HIP_OK(hipStreamSynchronize(h->stream));  // the weights' host copy may go now
+      ref = rb;
+      target = tb;
+    } else {
+      ref = ref0;
+      target = target0;
     }
-    ++k;
-    const double step = alpha * gn;
-    hipLaunchKernelGGL(k_dot_diff, dim3(kRedBlocks), dim3(256), 0, h->stream, 2 * n2, u1, u, g1, g, h->red_partial);
-    LAUNCH_OK();
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, 0);
-    LAUNCH_OK();
-    hipLaunchKernelGGL(k_dot_diff, dim3(kRedBlocks), dim3(256), 0, h->stream, 2 * n2, u1, u, u1, u, h->red_partial);
-    LAUNCH_OK();
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, 1);
-    LAUNCH_OK();
-    STATUS_OK(read_results(h, 2));
-    const double sy = h->red_host[0], ss = h->red_host[1];
-    std::swap(u, u1);
-    std::swap(g, g1);
-    E = En;
-    gn = std::sqrt(gsqn);
-    if (step < tol) break;
-    alpha = sy > 0 ? ss / sy : 2.0 * alpha;
+    double gsq = 0.0;
+    STATUS_OK(eval(g, E, gsq));
+    double gn = std::sqrt(gsq);
+    double alpha = gn > 0 ? 1.0 / gn : 1.0;
+    int k = 0;
+    while (k < max_iter && gn > 0) {
+      double En = 0.0, gsqn = 0.0;
+      for (int t = 0; t < 41; ++t) {
+        hipLaunchKernelGGL(k_field_trial, grid, block, 0, h->stream, n, h->pitch, h->padded, u, g, alpha, u1, fP);
+        LAUNCH_OK();
+        STATUS_OK(eval(g1, En, gsqn));
+        if (En <= E - 1e-4 * alpha * gn * gn) break;
+        alpha *= 0.5;
+      }
+      ++k;
+      const double step = alpha * gn;
+      hipLaunchKernelGGL(k_dot_diff, dim3(kRedBlocks), dim3(256), 0, h->stream, 2 * n2, u1, u, g1, g, h->red_partial);
+      LAUNCH_OK();
+      hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, 0);
+      LAUNCH_OK();
+      hipLaunchKernelGGL(k_dot_diff, dim3(kRedBlocks), dim3(256), 0, h->stream, 2 * n2, u1, u, u1, u, h->red_partial);
+      LAUNCH_OK();
+      hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->red_partial, h->red_out, 1);
+      LAUNCH_OK();
+      STATUS_OK(read_results(h, 2));
+      const double sy = h->red_host[0], ss = h->red_host[1];
+      std::swap(u, u1);
+      std::swap(g, g1);
+      E = En;
+      gn = std::sqrt(gsqn);
+      if (step < tol) break;
+      alpha = sy > 0 ? ss / sy : 2.0 * alpha;
+    }
+    k_total += k;
   }
   // the planes hold float32(u) of the last evaluation, the accepted iterate:
   // hand it back and install it as the gate's field (gather-window set-up
@@ -1589,7 +1634,7 @@ mcr_status register_field_impl(mcr_handle* h, int gate, const void* ref, const v
     LAUNCH_OK();
   }
   if (loss) *loss = E;
-  if (steps) *steps = k;
+  if (steps) *steps = k_total;
   mcr_motion m{};
   m.kind = MCR_MOTION_FIELD;
   m.field = field;
@@ -2267,7 +2312,8 @@ mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, con
 }
 
 mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, const void* target, void* field,
-                              double lambda, int32_t max_iter, double tol, double* loss, int32_t* steps) {
+                              double lambda, const double* sigmas, int32_t n_levels, int32_t max_iter, double tol,
+                              double* loss, int32_t* steps) {
   STATUS_OK(check_handle(h));
   STATUS_OK(check_gate(h, gate));
   STATUS_OK(check_ptr(ref, "ref"));
@@ -2277,7 +2323,16 @@ mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, cons
   if (!(lambda >= 0) || !std::isfinite(lambda)) return fail(MCR_ERR_ARG, "lambda must be finite and >= 0");
   if (max_iter < 0) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 0", max_iter);
   if (!(tol >= 0) || !std::isfinite(tol)) return fail(MCR_ERR_ARG, "tol must be finite and >= 0");
-  return DISPATCH(register_field_impl, h, gate, ref, target, (float*)field, lambda, max_iter, tol, loss, steps);
+  if (n_levels < 0 || n_levels > kMaxLevels)
+    return fail(MCR_ERR_ARG, "n_levels = %d must be in [0, %d]", n_levels, kMaxLevels);
+  if (n_levels > 0) {
+    STATUS_OK(check_ptr(sigmas, "sigmas"));
+    for (int l = 0; l < n_levels; ++l)
+      if (!(sigmas[l] >= 0 && sigmas[l] <= kMaxBlurSigma))
+        return fail(MCR_ERR_ARG, "sigmas[%d] must be in [0, %g]", l, kMaxBlurSigma);
+  }
+  return DISPATCH(register_field_impl, h, gate, ref, target, (float*)field, lambda, sigmas, n_levels, max_iter, tol,
+                  loss, steps);
 }
 
 mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, const void* target, double* params,

@@ -175,4 +175,22 @@ __global__ __launch_bounds__(256) void k_dot_diff(long count, const double* __re
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// One pass of the separable Gaussian of the scale-space schedule: out[p] =
+// sum_k w[k + R] in[p + k e], e along the row (AXIS 1) or the column (AXIS 0),
+// zero outside the image, accumulated in FP64 in the order of k.
+// grid (ceil(n/16), ceil(n/16)), block (16, 16)
+template <typename T, int AXIS>
+__global__ __launch_bounds__(256) void k_blur(int n, int R, const double* __restrict__ w, const T* __restrict__ in,
+                                              T* __restrict__ out) {
+  const int c = blockIdx.x * 16 + threadIdx.x;
+  const int r = blockIdx.y * 16 + threadIdx.y;
+  if (c >= n || r >= n) return;
+  double acc = 0.0;
+  for (int k = -R; k <= R; ++k) {
+    const int rr = AXIS == 0 ? r + k : r, cc = AXIS == 1 ? c + k : c;
+    if ((unsigned)rr < (unsigned)n && (unsigned)cc < (unsigned)n) acc += w[k + R] * double(in[(long)rr * n + cc]);
+  }
+  out[(long)r * n + c] = T(acc);
+}
+
 }  // namespace mcr

@@ -142,4 +142,4 @@ def test_register_affine_rejects_null_handle(lib):
 
 
 def test_register_field_rejects_null_handle(lib):
-    assert lib.mcr_register_field(None, 0, None, None, None, 0.1, 10, 1e-4, None, None) == _lib.MCR_ERR_ARG
+    assert lib.mcr_register_field(None, 0, None, None, None, 0.1, None, 0, 10, 1e-4, None, None) == _lib.MCR_ERR_ARG

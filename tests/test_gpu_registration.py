@@ -317,3 +317,83 @@ def test_field_registration_arguments():
     with pytest.raises(McrError, match="reset to the identity"):
         h.register_field(0, img, img, field=torch.from_numpy(fold).cuda(), max_iter=0)
     assert torch.equal(h.warp(0, img), img)
+
+
+def test_fp64_scale_space_registration_matches_oracle():
+    n = 48
+    P = Problem(n, 40, 70, 2, "field")
+    ref = _ref(n)
+    yy = np.mgrid[0:n, 0:n][0].astype(np.float64)
+    ustar = _bump_field(n, 1.0, -0.7, 8.0)
+    ustar[1] = f32(ustar[1] + 1.5 * (yy - (n - 1) / 2.0) / ((n - 1) / 2.0))
+    tgt = _field_target(ref, ustar)
+    sig = (3.0, 1.5, 0.0)
+    h = P.handle(torch.float64)
+    rd, td = dev(ref, torch.float64), dev(tgt, torch.float64)
+    # 8 steps per level: the same path up to rounding
+    u_o, E_o, k_o = oreg.register_field(ref, tgt, lam=0.05, max_iter=8, tol=1e-4, sigmas=sig)
+    u, E, k = h.register_field(1, rd, td, lam=0.05, max_iter=8, tol=1e-4, sigmas=sig)
+    print("fp64 scale-space registration, 8 steps per level: steps", k, k_o, "E", E, E_o)
+    assert k == k_o
+    assert np.abs(u.cpu().numpy() - f32(u_o)).max() < 1e-4
+    assert abs(E - E_o) <= 1e-6 * E_o
+    # 40 steps per level: the field is evaluated in float32, so a last-bit
+    # difference of the smoothed images (exp, summation order) can move a
+    # float32 rounding of the field, which the step lengths then amplify
+    # (one level of 40 steps stays within 2e-7 px; across three levels the
+    # paths part by up to ~0.02 px): the same energy to 1%
+    u_o, E_o, k_o = oreg.register_field(ref, tgt, lam=0.05, max_iter=40, tol=1e-4, sigmas=sig)
+    u, E, k = h.register_field(1, rd, td, field=torch.zeros(2, n, n, device="cuda"), lam=0.05, max_iter=40,
+                               tol=1e-4, sigmas=sig)
+    du = float(np.abs(u.cpu().numpy() - f32(u_o)).max())
+    print("fp64 scale-space registration, 40 steps per level: steps", k, k_o, "E", E, E_o, "max du", du)
+    assert k == k_o
+    assert abs(E - E_o) <= 1e-2 * E_o
+    assert du < 0.05
+
+
+@pytest.mark.parametrize("sigma", [0.8, 2.5, 6.0])
+def test_scale_space_energy_at_start(sigma):
+    # one level of width sigma, no steps: the energy of the smoothed images
+    # at the start field, against the oracle's smoothing and energy
+    n = 40
+    P = Problem(n, 30, 60, 2, "field")
+    ref, tgt = _ref(n), _field_target(_ref(n, seed=5), _bump_field(n, 0.7, 0.4, 8.0))
+    start = f32(_bump_field(n, -0.5, 0.9, 10.0))
+    E_o, _ = oreg.energy_and_grad_field(oreg.gaussian_smooth(ref, sigma), oreg.gaussian_smooth(tgt, sigma), start,
+                                        0.2)
+    for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
+        h = P.handle(dtype)
+        f = torch.from_numpy(start.astype(np.float32)).cuda()
+        u, E, k = h.register_field(0, dev(ref, dtype), dev(tgt, dtype), field=f, lam=0.2, max_iter=0,
+                                   sigmas=(sigma,))
+        assert k == 0
+        assert abs(E - E_o) <= bar * E_o, (dtype, E, E_o)
+
+
+def test_full_size_fp32_scale_space_from_zero():
+    # 512^2, the same motion as the affine-then-dense case (dilatation up to
+    # 4 px + a 2 px bump), registered from zero through a coarse-to-fine
+    # schedule (the FP64 oracle on the same problem: misfit to 0.067, field
+    # error at edge pixels to 0.75 of the true field's size; the component
+    # along an edge is not determined by the data)
+    n = 512
+    P = Problem(n, 720, 730, 2, "field")
+    h = P.handle(torch.float32)
+    ref = _ref(n)
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    c = (n - 1) / 2.0
+    b = np.exp(-((xx - c - 0.1 * n) ** 2 + (yy - c) ** 2) / (2 * (0.12 * n) ** 2))
+    ustar = f32(np.stack([2.0 * b, -1.4 * b + 4.0 * (yy - c) / c]))
+    tgt = _field_target(ref, ustar)
+    lam = 0.1
+    E0, _ = oreg.energy_and_grad_field(ref, tgt, np.zeros((2, n, n)), lam)
+    u, E, k = h.register_field(1, dev(ref, torch.float32), dev(tgt, torch.float32), lam=lam, max_iter=150,
+                               tol=1e-3, sigmas=(8.0, 4.0, 2.0, 1.0, 0.0))
+    gm = np.hypot(*np.gradient(ref))
+    m = gm > 0.1 * gm.max()
+    rms = lambda v: np.sqrt(np.mean(np.sum(v ** 2, axis=0)[m]))  # noqa: E731
+    err, err0 = rms(u.cpu().numpy() - ustar), rms(ustar)
+    print("512^2 scale-space registration: steps", k, "E", E0, "->", E, "rms error", err0, "->", err)
+    assert E < 0.1 * E0
+    assert err < 0.85 * err0
