@@ -238,8 +238,9 @@ mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, cons
  * precision); minimised over the scaled coordinates (A (n - 1) / 2, t). The
  * gate must be a field gate; its field is set to the result through
  * mcr_set_motion (which can fail if the map needs a wider gather window than
- * the transposed warp has). On an error during the iterations the gate's
- * field is left at the last evaluated map.                                    */
+ * the transposed warp has). On any error after the start (a non-finite
+ * energy, MCR_ERR_NONFINITE, included) the gate is reset to the identity, as
+ * its field planes then hold a map whose gather windows were not set up.     */
 mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, const void* target,
                                double* params, int32_t max_iter, double tol, double* loss,
                                int32_t* steps);
@@ -265,8 +266,8 @@ mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, con
  * folds too strongly for the transposed warp's window). lambda >= 0. The
  * gate must be a field gate. Workspace: 8 n^2 doubles (3 n^2 more with
  * levels), allocated on the first call. Synchronises the stream at every
- * evaluation. On an error during the iterations the gate's field is left at
- * the last evaluated map.                                                     */
+ * evaluation. On any error after the start the gate is reset to the
+ * identity, as for mcr_register_affine.                                       */
 mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, const void* target, void* field,
                               double lambda, const double* sigmas, int32_t n_levels, int32_t max_iter,
                               double tol, double* loss, int32_t* steps);

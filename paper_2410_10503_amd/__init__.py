@@ -181,11 +181,12 @@ class Handle:
 
     def _checked_motion_call(self, gate, call):
         """Runs a call that installs a gate's motion; a field rejected by the
-        gather-window check leaves the gate at the identity."""
+        gather-window check, or a registration that fails after its start,
+        leaves the gate at the identity."""
         try:
             _lib.check(call())
         except _lib.McrError as e:
-            if e.status == _lib.MCR_ERR_STATE and "reset to the identity" in str(e):
+            if "reset to the identity" in str(e):
                 self._kinds[int(gate)] = _lib.MOTION_IDENTITY
             raise
 

@@ -1376,6 +1376,7 @@ mcr_status minimise_bb(Eval eval, double* s, int max_iter, double tol, double& E
   };
   double g[D];
   STATUS_OK(eval(s, E, g));
+  if (!std::isfinite(E)) return fail(MCR_ERR_NONFINITE, "registration energy is not finite (check ref and target)");
   double gn = std::sqrt(dot(g, g));
   double alpha = gn > 0 ? 1.0 / gn : 1.0;
   k = 0;
@@ -1509,6 +1510,18 @@ mcr_status register_affine_impl(mcr_handle* h, int gate, const void* ref, const 
   return MCR_OK;
 }
 
+// The gate's motion becomes the identity (its field planes may hold a map
+// whose gather windows were never set up: a rejected or interrupted one).
+mcr_status reset_gate_identity(mcr_handle* h, int gate) {
+  h->motion[gate].kind = MCR_MOTION_IDENTITY;
+  h->motion[gate].field = nullptr;
+  h->radius[gate] = 1;
+  ++h->config_gen;
+  STATUS_OK(upload_motion<double>(h));
+  if (h->wf.ready) STATUS_OK(upload_motion<float>(h));
+  return MCR_OK;
+}
+
 // Dense displacement-field registration of a field gate (see
 // mcr_register_field): descent on u [2][n][n] with the steps of minimise_bb,
 // the vectors on the device. Each evaluation (the gate's field planes hold
@@ -1592,6 +1605,8 @@ mcr_status register_field_impl(mcr_handle* h, int gate, const void* ref0, const 
     }
     double gsq = 0.0;
     STATUS_OK(eval(g, E, gsq));
+    if (!std::isfinite(E))
+      return fail(MCR_ERR_NONFINITE, "registration energy is not finite (check ref, target and field)");
     double gn = std::sqrt(gsq);
     double alpha = gn > 0 ? 1.0 / gn : 1.0;
     int k = 0;
@@ -2095,12 +2110,7 @@ mcr_status mcr_set_motion(mcr_handle* h, int32_t gate, const mcr_motion* motion)
     if (need > kMaxRadius) {
       // leave a consistent handle: the gate's field planes already hold the
       // rejected field, so the gate falls back to the identity
-      h->motion[i].kind = MCR_MOTION_IDENTITY;
-      h->motion[i].field = nullptr;
-      h->radius[i] = 1;
-      ++h->config_gen;
-      STATUS_OK(upload_motion<double>(h));
-      if (h->wf.ready) STATUS_OK(upload_motion<float>(h));
+      STATUS_OK(reset_gate_identity(h, i));
       return fail(MCR_ERR_STATE,
                   "gate %d: the displacement field folds too strongly for a %dx%d transposed-warp window (needs %d); "
                   "the gate is reset to the identity",
@@ -2308,7 +2318,14 @@ mcr_status mcr_register_affine(mcr_handle* h, int32_t gate, const void* ref, con
     if (!std::isfinite(params[m])) return fail(MCR_ERR_ARG, "params[%d] is not finite", m);
   if (max_iter < 0) return fail(MCR_ERR_ARG, "max_iter = %d must be >= 0", max_iter);
   if (!(tol >= 0) || !std::isfinite(tol)) return fail(MCR_ERR_ARG, "tol must be finite and >= 0");
-  return DISPATCH(register_affine_impl, h, gate, ref, target, params, max_iter, tol, loss, steps);
+  const mcr_status st = DISPATCH(register_affine_impl, h, gate, ref, target, params, max_iter, tol, loss, steps);
+  if (st != MCR_OK && h->motion[gate].kind == MCR_MOTION_FIELD) {
+    // the gate's planes hold an evaluated map whose windows were not set up
+    const std::string msg = mcr_last_error();
+    (void)reset_gate_identity(h, gate);
+    return fail(st, "%s; the gate is reset to the identity", msg.c_str());
+  }
+  return st;
 }
 
 mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, const void* target, void* field,
@@ -2331,8 +2348,15 @@ mcr_status mcr_register_field(mcr_handle* h, int32_t gate, const void* ref, cons
       if (!(sigmas[l] >= 0 && sigmas[l] <= kMaxBlurSigma))
         return fail(MCR_ERR_ARG, "sigmas[%d] must be in [0, %g]", l, kMaxBlurSigma);
   }
-  return DISPATCH(register_field_impl, h, gate, ref, target, (float*)field, lambda, sigmas, n_levels, max_iter, tol,
-                  loss, steps);
+  const mcr_status st = DISPATCH(register_field_impl, h, gate, ref, target, (float*)field, lambda, sigmas, n_levels,
+                                 max_iter, tol, loss, steps);
+  if (st != MCR_OK && h->motion[gate].kind == MCR_MOTION_FIELD) {
+    // the gate's planes hold an evaluated map whose windows were not set up
+    const std::string msg = mcr_last_error();
+    (void)reset_gate_identity(h, gate);
+    return fail(st, "%s; the gate is reset to the identity", msg.c_str());
+  }
+  return st;
 }
 
 mcr_status mcr_register_rigid(mcr_handle* h, int32_t gate, const void* ref, const void* target, double* params,

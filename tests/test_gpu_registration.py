@@ -397,3 +397,24 @@ def test_full_size_fp32_scale_space_from_zero():
     print("512^2 scale-space registration: steps", k, "E", E0, "->", E, "rms error", err0, "->", err)
     assert E < 0.1 * E0
     assert err < 0.85 * err0
+
+
+def test_non_finite_inputs_are_reported_and_leave_a_consistent_gate():
+    from paper_2410_10503_amd import McrError
+    n = 32
+    img = dev(f32(synth.random_image(n, 2)), torch.float32)
+    bad = img.clone()
+    bad[5, 7] = float("nan")
+    R = Problem(n, 20, 48, 2, "rigid")
+    hr = R.handle(torch.float32)
+    with pytest.raises(McrError, match="not finite"):
+        hr.register_rigid(0, img, bad)
+    P = Problem(n, 20, 48, 2, "field")
+    for call in (lambda h: h.register_field(0, img, bad), lambda h: h.register_affine(0, img, bad)):
+        h = P.handle(torch.float32)
+        with pytest.raises(McrError, match="reset to the identity"):
+            call(h)
+        assert torch.equal(h.warp(0, img), img)
+        # the handle stays usable: the other gate's operator pair still runs
+        s = h.apply_Ai(1, img)
+        assert torch.isfinite(h.apply_Ai_adjoint(1, s)).all()
