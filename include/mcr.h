@@ -188,11 +188,14 @@ mcr_status mcr_batch_spdhg_epoch(mcr_handle* h, void* x, void* z, void* zbar, vo
 /* As mcr_spdhg_iterate, and before iteration k (gate g = gate_seq[k]) has
  * touched the duals it stores x after step (i) into x1_ckpt[k] ([n][n]) and
  * y_g into y_ckpt[k] ([n_angles][n_det]): host arrays of n_iter device
- * pointers. Same results as mcr_spdhg_iterate, bit for bit.                    */
+ * pointers. b_ckpt (may be NULL; else n_iter device pointers of [n][n])
+ * receives the iteration's backprojection A^T (y_g' - y_g), which spares
+ * mcr_spdhg_step_backward its recomputation (one warp, projection and
+ * backprojection per step). Same results as mcr_spdhg_iterate, bit for bit. */
 mcr_status mcr_spdhg_iterate_ckpt(mcr_handle* h, const mcr_state* st, const void* const* d,
                                   double alpha, const double* sigma, double tau, double theta,
                                   const double* p, const int32_t* gate_seq, int32_t n_iter,
-                                  void* const* x1_ckpt, void* const* y_ckpt);
+                                  void* const* x1_ckpt, void* const* y_ckpt, void* const* b_ckpt);
 /* Reverse of one SPDHG iteration on `gate` from its checkpoint (x1, y_before)
  * and the gate's data d_gate, with that iteration's sigma (of the gate), tau,
  * theta, p (of the gate). On entry gx, gy_gate, gz, gzbar ([n][n] except
@@ -200,12 +203,16 @@ mcr_status mcr_spdhg_iterate_ckpt(mcr_handle* h, const mcr_state* st, const void
  * x, y_gate, z, z-bar; on return those of its inputs. grad_motion (may be
  * NULL) accumulates d/d(motion of gate): device double[3] (phi, t_x, t_y) for
  * rigid gates, device [2][n][n] (u_x, u_y planes) for fields, unused for the
- * identity. The reverse map is the transpose of the iteration (see
- * mcr_grad.h); each call costs two projections and two backprojections.      */
+ * identity. b_ckpt (may be NULL): the iteration's backprojection stored by
+ * mcr_spdhg_iterate_ckpt; given, the step costs one projection and one
+ * backprojection, else it recomputes it (two of each; the same results bit
+ * for bit). The reverse map is the transpose of the iteration (see
+ * mcr_grad.h).                                                                */
 mcr_status mcr_spdhg_step_backward(mcr_handle* h, int32_t gate, const void* x1,
                                    const void* y_before, const void* d_gate, double alpha,
                                    double sigma, double tau, double theta, double p, void* gx,
-                                   void* gy_gate, void* gz, void* gzbar, void* grad_motion);
+                                   void* gy_gate, void* gz, void* gzbar, void* grad_motion,
+                                   const void* b_ckpt);
 /* grad_motion += d/d(motion of gate) <img, D_gate v> (img, v: [n][n]); layout
  * of grad_motion as above.                                                     */
 mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, const void* v,

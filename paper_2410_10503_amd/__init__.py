@@ -266,18 +266,23 @@ class Handle:
                                             float(alpha), _dbl_array(sigma), float(tau), float(theta)))
 
     # -- differentiation ----------------------------------------------------
-    def spdhg_iterate_ckpt(self, st: ReconState, d, alpha, sigma, tau, theta, p, gate_seq, x1_ckpt, y_ckpt):
-        """spdhg_iterate that also stores, per iteration, x after step (i) and the drawn gate's old dual."""
+    def spdhg_iterate_ckpt(self, st: ReconState, d, alpha, sigma, tau, theta, p, gate_seq, x1_ckpt, y_ckpt,
+                           b_ckpt=None):
+        """spdhg_iterate that also stores, per iteration, x after step (i) and the drawn gate's old dual
+        (and, if b_ckpt is given, the iteration's backprojection, which spares the reverse step its
+        recomputation)."""
         self._sync_stream()
         seq = [int(g) for g in gate_seq]
-        if len(x1_ckpt) != len(seq) or len(y_ckpt) != len(seq):
-            raise ValueError("one image and one sinogram checkpoint per iteration")
+        if len(x1_ckpt) != len(seq) or len(y_ckpt) != len(seq) or (b_ckpt is not None and len(b_ckpt) != len(seq)):
+            raise ValueError("one checkpoint of each kind per iteration")
         c_seq = (ctypes.c_int32 * max(1, len(seq)))(*seq)
         xs = (ctypes.c_void_p * max(1, len(seq)))(*[self._img(t, "x1_ckpt") for t in x1_ckpt])
         ys = (ctypes.c_void_p * max(1, len(seq)))(*[self._sino(t, "y_ckpt") for t in y_ckpt])
+        bs = None if b_ckpt is None else (ctypes.c_void_p * max(1, len(seq)))(*[self._img(t, "b_ckpt")
+                                                                                for t in b_ckpt])
         _lib.check(self._lib.mcr_spdhg_iterate_ckpt(self._h, ctypes.byref(self._state(st)), self._ptrs(d, "d"),
                                                     float(alpha), _dbl_array(sigma), float(tau), float(theta),
-                                                    _dbl_array(p), c_seq, len(seq), xs, ys))
+                                                    _dbl_array(p), c_seq, len(seq), xs, ys, bs))
 
     def _grad_motion_ptr(self, gate, gm):
         if gm is None:
@@ -293,14 +298,15 @@ class Handle:
         return gm.data_ptr()
 
     def spdhg_step_backward(self, gate, x1, y_before, d_gate, alpha, sigma_g, tau, theta, p_g, gx, gy, gz, gzbar,
-                            grad_motion=None):
-        """Reverse of one SPDHG iteration (adjoints updated in place, motion gradient accumulated)."""
+                            grad_motion=None, b_ckpt=None):
+        """Reverse of one SPDHG iteration (adjoints updated in place, motion gradient accumulated);
+        b_ckpt: the iteration's stored backprojection, or None to recompute it."""
         self._sync_stream()
         _lib.check(self._lib.mcr_spdhg_step_backward(
             self._h, int(gate), self._img(x1, "x1"), self._sino(y_before, "y_before"), self._sino(d_gate, "d_gate"),
             float(alpha), float(sigma_g), float(tau), float(theta), float(p_g), self._img(gx, "gx"),
             self._sino(gy, "gy"), self._img(gz, "gz"), self._img(gzbar, "gzbar"),
-            self._grad_motion_ptr(gate, grad_motion)))
+            self._grad_motion_ptr(gate, grad_motion), None if b_ckpt is None else self._img(b_ckpt, "b_ckpt")))
 
     def warp_motion_grad(self, gate, img, v, grad_motion):
         """grad_motion += d/d(motion of gate) <img, D_gate v>."""

@@ -66,8 +66,8 @@ SIGNATURES = {
     "mcr_block_norm_sq": [_P, _I, _I, _P, _I, _D, _PD, _PI],
     "mcr_spdhg_blocks_iterate": [_P, ctypes.POINTER(State), _PP, _D, _PD, _D, _D, _PD, _PI, _I],
     "mcr_step_sizes_blocks": [_I, _I, _PD, _D, _PD, _PD, _PD, _PD],
-    "mcr_spdhg_iterate_ckpt": [_P, ctypes.POINTER(State), _PP, _D, _PD, _D, _D, _PD, _PI, _I, _PP, _PP],
-    "mcr_spdhg_step_backward": [_P, _I, _P, _P, _P, _D, _D, _D, _D, _D, _P, _P, _P, _P, _P],
+    "mcr_spdhg_iterate_ckpt": [_P, ctypes.POINTER(State), _PP, _D, _PD, _D, _D, _PD, _PI, _I, _PP, _PP, _PP],
+    "mcr_spdhg_step_backward": [_P, _I, _P, _P, _P, _D, _D, _D, _D, _D, _P, _P, _P, _P, _P, _P],
     "mcr_warp_motion_grad": [_P, _I, _P, _P, _P],
     "mcr_register_rigid": [_P, _I, _P, _P, _PD, _I, _D, _PD, _PI],
     "mcr_register_affine": [_P, _I, _P, _P, _PD, _I, _D, _PD, _PI],

@@ -5,9 +5,10 @@ runs len(gate_seq) SPDHG iterations from (x0, y = 0, z = 0, z-bar = 0) with
 the given motion and returns the final image. Gradients flow to x0 and to the
 motion parameters: a [N][3] float64 tensor of rigid (phi, t_x, t_y) or a
 [N][2][n][n] tensor of displacement fields. The forward pass keeps one
-checkpoint per iteration (the image after step (i) and the drawn gate's old
-dual); the backward pass runs the library's reverse of each iteration
-(mcr_spdhg_step_backward) from its checkpoint. All arithmetic runs in the
+checkpoint per iteration (the image after step (i), the drawn gate's old
+dual and the iteration's backprojection); the backward pass runs the
+library's reverse of each iteration (mcr_spdhg_step_backward) from its
+checkpoint. All arithmetic runs in the
 library's kernels; this module moves tensors.
 """
 from __future__ import annotations
@@ -32,10 +33,11 @@ class UnrolledSPDHG(torch.autograd.Function):
         K = len(gate_seq)
         x1c = [handle.new_image() for _ in range(K)]
         yc = [handle.new_sino() for _ in range(K)]
-        handle.spdhg_iterate_ckpt(st, d, alpha, sigma, tau, theta, p, gate_seq, x1c, yc)
+        bc = [handle.new_image() for _ in range(K)]  # spares the reverse steps a recomputation each
+        handle.spdhg_iterate_ckpt(st, d, alpha, sigma, tau, theta, p, gate_seq, x1c, yc, bc)
         ctx.handle, ctx.kind = handle, kind
         ctx.args = (list(d), alpha, list(sigma), tau, theta, list(p), [int(g) for g in gate_seq])
-        ctx.ckpt = (x1c, yc)
+        ctx.ckpt = (x1c, yc, bc)
         ctx.motion_shape = tuple(motion.shape)
         ctx.motion_device = motion.device
         ctx.motion_dtype = motion.dtype
@@ -45,7 +47,7 @@ class UnrolledSPDHG(torch.autograd.Function):
     def backward(ctx, gout):
         h = ctx.handle
         d, alpha, sigma, tau, theta, p, seq = ctx.args
-        x1c, yc = ctx.ckpt
+        x1c, yc, bc = ctx.ckpt
         gx = gout.detach().to(h.dtype).contiguous().clone()
         gz = torch.zeros_like(gx)
         gzb = torch.zeros_like(gx)
@@ -59,7 +61,7 @@ class UnrolledSPDHG(torch.autograd.Function):
             if g not in gy:
                 gy[g] = torch.zeros((h.n_angles, h.n_det), dtype=h.dtype, device=h.device)
             h.spdhg_step_backward(g, x1c[k], yc[k], d[g], alpha, sigma[g], tau, theta, p[g], gx, gy[g], gz, gzb,
-                                  gm[g])
+                                  gm[g], b_ckpt=bc[k])
         gmot = gm.to(device=ctx.motion_device, dtype=ctx.motion_dtype).reshape(ctx.motion_shape)
         return gx, gmot, None, None, None, None, None, None, None, None, None
 

@@ -1269,8 +1269,10 @@ mcr_status launch_motion_grad(mcr_handle* h, int gate, const T* hP, const T* v, 
 template <typename T>
 mcr_status spdhg_ckpt_impl(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
                            const double* sigma, double tau, double theta, const double* p, const int32_t* seq,
-                           int n_iter, void* const* x1c, void* const* yc) {
+                           int n_iter, void* const* x1c, void* const* yc, void* const* bc) {
   STATUS_OK(set_params<T>(h, st, d, sigma, theta, p));
+  Work<T>& w = work<T>(h);
+  const int n = h->geo.n;
   const T t = T(tau), cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
   const long n2 = (long)h->geo.n * h->geo.n;
   for (int k = 0; k < n_iter; ++k) {
@@ -1279,6 +1281,11 @@ mcr_status spdhg_ckpt_impl(mcr_handle* h, const mcr_state* st, const void* const
     HIP_OK(hipMemcpyAsync(x1c[k], st->x, sizeof(T) * n2, hipMemcpyDeviceToDevice, h->stream));
     HIP_OK(hipMemcpyAsync(yc[k], st->y[g], sizeof(T) * h->sino, hipMemcpyDeviceToDevice, h->stream));
     STATUS_OK(iteration<T>(h, st, g, 1, false, false, t, cx));
+    if (bc) {  // the iteration's backprojection, still in the padded work image
+      hipLaunchKernelGGL(k_from_padded<T>, dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n, h->pitch,
+                         w.bP, (T*)bc[k]);
+      LAUNCH_OK();
+    }
   }
   return MCR_OK;
 }
@@ -1286,7 +1293,7 @@ mcr_status spdhg_ckpt_impl(mcr_handle* h, const mcr_state* st, const void* const
 template <typename T>
 mcr_status step_backward_impl(mcr_handle* h, int gate, const void* x1, const void* yb, const void* dg,
                               double alpha, double sigma, double tau, double theta, double p, void* gx,
-                              void* gy, void* gz, void* gzb, void* gmot) {
+                              void* gy, void* gz, void* gzb, void* gmot, const void* bck) {
   Work<T>& w = work<T>(h);
   const int N = h->N;
   if ((int)w.sc_host.size() != N) {
@@ -1300,10 +1307,18 @@ mcr_status step_backward_impl(mcr_handle* h, int gate, const void* x1, const voi
   const long n2 = (long)h->geo.n * h->geo.n;
   const T cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
   const dim3 gi(cdiv(n2, 256)), gs(cdiv(h->sino, 256)), blk(256);
-  // recompute dy = y1 - y and b = A^T dy from the checkpoint
-  STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)x1));
-  STATUS_OK((launch_project<T, 2>(h, gate, 1, w.dy, h->sino)));
-  STATUS_OK(launch_backproject<T>(h, 1, w.dy, h->sino, w.bP, h->padded, 1));
+  // b = A^T dy, dy = y1 - y: stored by the forward, or recomputed from the
+  // checkpoint (the same kernels on the same inputs: the same values)
+  if (bck) {
+    const int n = h->geo.n;
+    hipLaunchKernelGGL((k_to_padded<T, T>), dim3(cdiv(n, 16), cdiv(n, 16)), dim3(16, 16), 0, h->stream, n, h->pitch,
+                       (const T*)bck, w.bP);
+    LAUNCH_OK();
+  } else {
+    STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)x1));
+    STATUS_OK((launch_project<T, 2>(h, gate, 1, w.dy, h->sino)));
+    STATUS_OK(launch_backproject<T>(h, 1, w.dy, h->sino, w.bP, h->padded, 1));
+  }
   // z / z-bar
   {
     Timed tm(h, MCR_KERNEL_OTHER);
@@ -2258,7 +2273,7 @@ mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const*
 mcr_status mcr_spdhg_iterate_ckpt(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
                                   const double* sigma, double tau, double theta, const double* p,
                                   const int32_t* gate_seq, int32_t n_iter, void* const* x1_ckpt,
-                                  void* const* y_ckpt) {
+                                  void* const* y_ckpt, void* const* b_ckpt) {
   STATUS_OK(check_handle(h));
   STATUS_OK(check_alg(h, st, d, alpha, sigma, tau, theta, p));
   STATUS_OK(check_ptr(p, "p"));
@@ -2270,15 +2285,17 @@ mcr_status mcr_spdhg_iterate_ckpt(mcr_handle* h, const mcr_state* st, const void
   }
   for (int k = 0; k < n_iter; ++k) {
     STATUS_OK(check_gate(h, gate_seq[k]));
-    if (!x1_ckpt[k] || !y_ckpt[k]) return fail(MCR_ERR_ARG, "checkpoint %d is null", k);
+    if (!x1_ckpt[k] || !y_ckpt[k] || (b_ckpt && !b_ckpt[k])) return fail(MCR_ERR_ARG, "checkpoint %d is null", k);
   }
   if (n_iter == 0) return MCR_OK;
-  return DISPATCH(spdhg_ckpt_impl, h, st, d, alpha, sigma, tau, theta, p, gate_seq, n_iter, x1_ckpt, y_ckpt);
+  return DISPATCH(spdhg_ckpt_impl, h, st, d, alpha, sigma, tau, theta, p, gate_seq, n_iter, x1_ckpt, y_ckpt,
+                  b_ckpt);
 }
 
 mcr_status mcr_spdhg_step_backward(mcr_handle* h, int32_t gate, const void* x1, const void* y_before,
                                    const void* d_gate, double alpha, double sigma, double tau, double theta,
-                                   double p, void* gx, void* gy_gate, void* gz, void* gzbar, void* grad_motion) {
+                                   double p, void* gx, void* gy_gate, void* gz, void* gzbar, void* grad_motion,
+                                   const void* b_ckpt) {
   STATUS_OK(check_handle(h));
   STATUS_OK(check_gate(h, gate));
   STATUS_OK(check_ptr(x1, "x1"));
@@ -2294,7 +2311,7 @@ mcr_status mcr_spdhg_step_backward(mcr_handle* h, int32_t gate, const void* x1, 
   if (!(theta >= 0) || !std::isfinite(theta)) return fail(MCR_ERR_ARG, "theta = %g must be finite and >= 0", theta);
   if (!(p > 0) || !(p <= 1)) return fail(MCR_ERR_ARG, "p = %g must be in (0, 1]", p);
   return DISPATCH(step_backward_impl, h, gate, x1, y_before, d_gate, alpha, sigma, tau, theta, p, gx, gy_gate, gz,
-                  gzbar, grad_motion);
+                  gzbar, grad_motion, b_ckpt);
 }
 
 mcr_status mcr_warp_motion_grad(mcr_handle* h, int32_t gate, const void* img, const void* v, void* grad_motion) {

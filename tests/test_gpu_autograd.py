@@ -70,9 +70,42 @@ def test_checkpointed_iterate_is_bitwise_plain():
     b.x.copy_(dev(x0, torch.float32))
     h.spdhg_iterate(a, d, P.alpha, sig, tau, th, p, seq)
     h.spdhg_iterate_ckpt(b, d, P.alpha, sig, tau, th, p, seq, [h.new_image() for _ in seq],
-                         [h.new_sino() for _ in seq])
+                         [h.new_sino() for _ in seq], [h.new_image() for _ in seq])
     for u, v in [(a.x, b.x), (a.z, b.z), (a.zbar, b.zbar)] + list(zip(a.y, b.y)):
         assert torch.equal(u, v)
+
+
+@pytest.mark.parametrize("kind", ["rigid", "field"])
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_stored_backprojections_give_the_same_reverse_pass(kind, dtype):
+    # the forward's stored backprojections against their recomputation in
+    # the reverse steps: the same kernels on the same inputs, so the same
+    # adjoints and motion gradients bit for bit
+    P, sig, tau, th, p, seq, x0, target = _setup(kind)
+    h = P.handle(dtype)
+    d = [dev(v, dtype) for v in P.d]
+    st = h.zero_state()
+    st.x.copy_(dev(x0, dtype))
+    x1c = [h.new_image() for _ in seq]
+    yc = [h.new_sino() for _ in seq]
+    bc = [h.new_image() for _ in seq]
+    h.spdhg_iterate_ckpt(st, d, P.alpha, sig, tau, th, p, seq, x1c, yc, bc)
+    w = dev(synth.random_image(P.n, 11), dtype)
+    out = []
+    for stored in (True, False):
+        gx, gz, gzb = w.clone(), torch.zeros_like(w), torch.zeros_like(w)
+        gy = [torch.zeros((P.na, P.nd), dtype=dtype, device="cuda") for _ in range(P.N)]
+        if kind == "rigid":
+            gm = torch.zeros((P.N, 3), dtype=torch.float64, device="cuda")
+        else:
+            gm = torch.zeros((P.N, 2, P.n, P.n), dtype=dtype, device="cuda")
+        for k in range(len(seq) - 1, -1, -1):
+            g = seq[k]
+            h.spdhg_step_backward(g, x1c[k], yc[k], d[g], P.alpha, sig[g], tau, th, p[g], gx, gy[g], gz, gzb, gm[g],
+                                  b_ckpt=bc[k] if stored else None)
+        out.append((gx, gz, gzb, torch.stack(gy), gm))
+    for a_, b_ in zip(*out):
+        assert torch.equal(a_, b_)
 
 
 def test_jacobian_transpose_identity():
