@@ -307,6 +307,11 @@ def test_field_registration_arguments():
         h.register_field(0, x, x, lam=-1.0)
     u, E, k = h.register_field(1, x, x)
     assert k == 0 and E == 0.0 and not u.any()
+    for bad in ((40.0,), (-1.0,), (float("nan"),)):
+        with pytest.raises(McrError, match="sigmas"):
+            h.register_field(1, x, x, sigmas=bad)
+    with pytest.raises(McrError, match="n_levels"):
+        h.register_field(1, x, x, sigmas=(1.0,) * 17)
     # a start field that compresses the rows tenfold needs a wider gather
     # window than the transposed warp has: the gate falls back to the identity
     n = 32
