@@ -284,6 +284,15 @@ def autograd_measurement(reps: int = 3):
         torch.cuda.synchronize()
         out[name] = 1e3 * (time.perf_counter() - t0) / reps
     out["ratio"] = out["forward_and_backward_ms"] / out["plain_forward_ms"]
+    # the library's launches alone (HIP events around each), against the wall
+    # time above (which also holds the host work of the autograd function)
+    for name, fn in (("plain_forward_kernel_ms", plain), ("forward_and_backward_kernel_ms", with_grad)):
+        h.profile(True)
+        h.profile_read()
+        fn()
+        torch.cuda.synchronize()
+        out[name] = sum(v[0] for v in h.profile_read().values())
+        h.profile(False)
     h.close()
     return out
 
