@@ -239,6 +239,64 @@ def batched_measurement(steps: int, seed: int = 4, variant=None, per_slice: bool
     return out
 
 
+def pdhg_spdhg_measurement(epochs: int = 10, check_epochs: int = 5):
+    """PDHG against SPDHG on the 512^2 rigid workload (8 gates, 720 x 730,
+    FP32): epochs/s of each (a PDHG epoch is one iteration over all gates,
+    launched 8 gates wide; an SPDHG epoch 8 one-gate iterations), and the
+    relative L2 difference of x after `check_epochs` epochs from zero against
+    the FP64 path on the device (which the tests pin to the FP64 oracle)."""
+    import torch
+    import synth
+    from paper_2410_10503_amd import Handle, step_sizes
+    wl = synth.WORKLOADS["ellipses512_rigid8"]
+    N = wl.n_gates
+    params = wl.rigid()
+    motion = [("rigid", tuple(params[i])) for i in range(N)]
+    hs = {dt: Handle(wl.n, wl.n_angles, wl.n_det, motion, dtype=dt) for dt in (torch.float32, torch.float64)}
+    h = hs[torch.float32]
+    xg = torch.from_numpy(wl.image()).cuda()
+    scale = 0.01 * float(h.project(xg).abs().max()) / math.sqrt(N)
+    noise = torch.from_numpy(synth.unit_noise((N, wl.n_angles, wl.n_det), wl.noise_seed).astype(np.float32)).cuda()
+    data = {torch.float32: [h.apply_Ai(i, xg) + scale * noise[i] for i in range(N)]}
+    data[torch.float64] = [v.double() for v in data[torch.float32]]
+    v0 = torch.from_numpy(synth.random_image(wl.n, 17).astype(np.float64)).cuda()
+    norms = [h.power_norm_sq(i, v0, max_iter=25, rtol=1e-6)[0] for i in range(N)]
+    stacked = h.power_norm_sq(-1, v0, max_iter=25, rtol=1e-6)[0]
+    steps = {"spdhg": step_sizes("spdhg", norms, wl.alpha, N), "pdhg": step_sizes("pdhg", [stacked], wl.alpha, N)}
+    p = [1.0 / N] * N
+    out = {"workload": f"{wl.name}: {wl.n}^2, {wl.n_angles}x{wl.n_det}, {N} rigid gates, float32"}
+
+    def epoch(hh, st, d, algo, e):
+        sig, tau, th, _ = steps[algo]
+        if algo == "pdhg":
+            hh.pdhg_epoch(st, d, wl.alpha, sig, tau, th)
+        else:
+            hh.spdhg_epoch(st, d, wl.alpha, sig, tau, th, p, synth.gate_sequence(N, wl.gate_seed, e))
+
+    for algo in ("pdhg", "spdhg"):
+        variant = h.autotune(N if algo == "pdhg" else 1)  # launches 8 gates or one gate wide
+        xs = {}
+        for dt, hh in hs.items():
+            st = hh.zero_state()
+            for e in range(check_epochs):
+                epoch(hh, st, data[dt], algo, e)
+            xs[dt] = st.x.double()
+        rel = float(torch.linalg.norm(xs[torch.float32] - xs[torch.float64]) / torch.linalg.norm(xs[torch.float64]))
+        st = h.zero_state()
+        for e in range(5):
+            epoch(h, st, data[torch.float32], algo, e)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for e in range(epochs):
+            epoch(h, st, data[torch.float32], algo, 5 + e)
+        torch.cuda.synchronize()
+        out[algo] = {"epochs_per_s": epochs / (time.perf_counter() - t0), "projector_variant": variant,
+                     f"rel_l2_x_vs_fp64_after_{check_epochs}_epochs": rel, "per_epoch_rate": steps[algo][3]}
+    for hh in hs.values():
+        hh.close()
+    return out
+
+
 def autograd_measurement(reps: int = 3):
     """Differentiation through 10 unrolled SPDHG iterations at 512^2, 720 x 730,
     16 rigid gates: the plain 10 iterations against the checkpointed forward
@@ -559,6 +617,7 @@ def main():
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--no-subsets", action="store_true", help="skip the gates x angle-subsets measurement")
     ap.add_argument("--no-registration", action="store_true", help="skip the rigid-registration measurement")
+    ap.add_argument("--no-pdhg", action="store_true", help="skip the PDHG vs SPDHG measurement")
     ap.add_argument("--variant", default=None,
                     help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
                          "(counter runs serialise dispatches, which would change the autotuner's choice)")
@@ -786,6 +845,10 @@ def main():
         log("gates x angle subsets ...")
         out["subsets"] = subsets_measurement(h, d, wl, norms, v0)
         log(f"subsets: {out['subsets']}")
+    if not args.no_pdhg:
+        log("PDHG vs SPDHG on the 512^2 rigid workload ...")
+        out["pdhg_vs_spdhg"] = pdhg_spdhg_measurement()
+        log(f"pdhg_vs_spdhg: {out['pdhg_vs_spdhg']}")
     if not args.no_batch:
         log("batched workload: 64 slices of 256^2 ...")
         out["batched"] = batched_measurement(max(2, args.steps // 3))
