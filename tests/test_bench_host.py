@@ -1,0 +1,38 @@
+"""Host logic of bench.py, on the CPU: the algorithmic work count against the
+oracle's assembled matrix, the counter-summary lookup, and the one-GPU rule."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+from oracle import projector
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("geom", [(8, 6, 13), (12, 8, 17), (16, 10, 23), (9, 7, 14)])
+def test_joseph_nnz_counts_the_matrix(geom):
+    # the roofline's work per launch (2 nnz FLOP) counts the nonzero weights
+    # of the Joseph matrix: the oracle's assembled matrix has exactly that many
+    n, na, nd = geom
+    M = projector.matrix(n, na, nd)
+    assert bench.joseph_nnz(n, na, nd) == int(np.count_nonzero(M))
+
+
+def test_measured_traffic_follows_the_committed_summary():
+    # a line for another variant is never used; the summary's own line only
+    # while the kernel sources hash as they did when the counters were taken
+    assert bench.measured_traffic("project", {"fwd": 3, "adj_px": 8, "adj_shares": 6}) is None
+    t = bench.measured_traffic("project", {"fwd": 4, "adj_px": -4, "adj_shares": 12})
+    if t is None:
+        pytest.skip("the kernel sources changed since the counter summary was taken")
+    assert t > 0
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
