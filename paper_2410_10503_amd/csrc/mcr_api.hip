@@ -1296,14 +1296,7 @@ mcr_status step_backward_impl(mcr_handle* h, int gate, const void* x1, const voi
                               void* gy, void* gz, void* gzb, void* gmot, const void* bck) {
   Work<T>& w = work<T>(h);
   const int N = h->N;
-  if ((int)w.sc_host.size() != N) {
-    w.sc_host.assign(N, GateScalars<T>{});
-    w.pt_host.assign(N, GatePtrs<T>{});
-  }
   const double cyd = 1.0 / (1.0 + sigma * N / 2.0);
-  w.sc_host[gate] = GateScalars<T>{T(sigma), T(cyd), T(theta / p), T(0)};
-  w.pt_host[gate] = GatePtrs<T>{(T*)yb, (const T*)dg};
-  STATUS_OK(upload_params<T>(h, w.sc_host, w.pt_host));
   const long n2 = (long)h->geo.n * h->geo.n;
   const T cx = T(1.0 / (1.0 + 2.0 * tau * alpha));
   const dim3 gi(cdiv(n2, 256)), gs(cdiv(h->sino, 256)), blk(256);
@@ -1315,6 +1308,15 @@ mcr_status step_backward_impl(mcr_handle* h, int gate, const void* x1, const voi
                        (const T*)bck, w.bP);
     LAUNCH_OK();
   } else {
+    // the recomputation's dual step reads the gate's scalars and pointers
+    // from the device tables (their upload waits for the previous one)
+    if ((int)w.sc_host.size() != N) {
+      w.sc_host.assign(N, GateScalars<T>{});
+      w.pt_host.assign(N, GatePtrs<T>{});
+    }
+    w.sc_host[gate] = GateScalars<T>{T(sigma), T(cyd), T(theta / p), T(0)};
+    w.pt_host[gate] = GatePtrs<T>{(T*)yb, (const T*)dg};
+    STATUS_OK(upload_params<T>(h, w.sc_host, w.pt_host));
     STATUS_OK(launch_warp<T>(h, gate, 1, (const T*)x1));
     STATUS_OK((launch_project<T, 2>(h, gate, 1, w.dy, h->sino)));
     STATUS_OK(launch_backproject<T>(h, 1, w.dy, h->sino, w.bP, h->padded, 1));
