@@ -621,10 +621,11 @@ def main():
     ap.add_argument("--variant", default=None,
                     help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
                          "(counter runs serialise dispatches, which would change the autotuner's choice)")
-    ap.add_argument("--experiment", choices=["paper", "batched"], default=None,
+    ap.add_argument("--experiment", choices=["paper", "batched", "autograd", "registration", "pdhg"], default=None,
                     help="paper: the Section III reproduction (rates vs Theorem 1, MC vs no-MC); batched: the "
                          "64-slice batched workload alone (--steps epochs, --variant applies), for counter "
-                         "runs; either instead of the bench")
+                         "runs; autograd, registration, pdhg: that measurement of the bench alone; each "
+                         "instead of the bench")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -635,6 +636,11 @@ def main():
 
     if args.experiment == "paper":
         print(json.dumps({"experiment": "section III reproduction", "results": paper_experiment()}), flush=True)
+        return
+    if args.experiment in ("autograd", "registration", "pdhg"):
+        fn = {"autograd": autograd_measurement, "registration": registration_measurement,
+              "pdhg": pdhg_spdhg_measurement}[args.experiment]
+        print(json.dumps({"experiment": args.experiment, "results": fn()}), flush=True)
         return
     if args.experiment == "batched":
         v = None
