@@ -10,11 +10,17 @@ class GatedOperators:
     """The N gate operators of one problem.
 
     motion: "identity", ("rigid", params [N][3]) or ("field", fields [N][2][n][n]).
+    matrix (optional): projector.sparse_matrix(n, n_angles, n_det); A and A^T
+    are then its products (the same weights, summed in another order).
     """
 
-    def __init__(self, n: int, n_angles: int, n_det: int, kind: str, params=None, n_gates: int | None = None):
+    def __init__(self, n: int, n_angles: int, n_det: int, kind: str, params=None, n_gates: int | None = None,
+                 matrix=None):
         self.n, self.n_angles, self.n_det = n, n_angles, n_det
         self.kind = kind
+        if matrix is not None and matrix.shape != (n_angles * n_det, n * n):
+            raise ValueError("matrix shape does not match the geometry")
+        self.matrix = matrix
         if kind == "identity":
             self.n_gates = int(n_gates)
             self.params = None
@@ -41,9 +47,15 @@ class GatedOperators:
         return warp.warp_adjoint(b, *self.pos[i])
 
     def project(self, x):
+        if self.matrix is not None:
+            v = self.matrix @ np.asarray(x, dtype=np.float64).ravel()
+            return v.reshape(self.n_angles, self.n_det)
         return projector.forward(x, self.n_angles, self.n_det)
 
     def backproject(self, y):
+        if self.matrix is not None:
+            v = self.matrix.T @ np.asarray(y, dtype=np.float64).ravel()
+            return v.reshape(self.n, self.n)
         return projector.adjoint(y, self.n)
 
     def A(self, i, x):

@@ -20,7 +20,10 @@ discretisation. This oracle uses the Joseph rule:
   r_f = (t_j - x_c cos) / sin + (n-1)/2 and weight 1/|sin|.
 
 A^T is the scatter of exactly the same weights (np.bincount), so it is the
-exact transpose of `forward` by construction.
+exact transpose of `forward` by construction. `sparse_matrix` assembles the
+same weights, angle by angle, as a sparse matrix: the matrix of `forward`,
+whose transpose is `adjoint` (used where the full-size iterations would
+otherwise take hours).
 """
 from __future__ import annotations
 
@@ -133,3 +136,39 @@ def matrix(n: int, n_angles: int, n_det: int) -> np.ndarray:
         e[q] = 1.0
         m[:, q] = forward(e.reshape(n, n), n_angles, n_det).ravel()
     return m
+
+
+def sparse_matrix(n: int, n_angles: int, n_det: int):
+    """The matrix of `forward` (rows: rays k * n_det + j; columns: pixels
+    r * n + c) as a scipy.sparse CSR matrix, assembled from the same crossings
+    and weights: ray (k, j) holds, for every line along its stepping axis,
+    weight ds (1 - f) on the pixel at floor(c_f) and ds f on the next one,
+    where those pixels lie inside the image. A ray meets each pixel of a line
+    at most once, so no entry is written twice."""
+    import scipy.sparse as sps
+    lane = np.arange(n)[:, None]
+    counts = np.zeros(n_angles * n_det, dtype=np.int64)
+    cols, vals = [], []
+    for k in range(n_angles):
+        cf, ds, rows = _crossings(n, n_det, k, n_angles)
+        c0 = np.floor(cf).astype(np.int64)
+        f = cf - c0
+        # entries of this angle ordered by ray, then line, then tap
+        tap = np.stack([c0, c0 + 1], axis=-1)                       # [lane][ray][2]
+        w = np.stack([ds * (1.0 - f), ds * f], axis=-1)
+        pix = (lane[..., None] * n + tap) if rows else (tap * n + lane[..., None])
+        ok = (tap >= 0) & (tap < n)
+        order = (1, 0, 2)                                          # -> [ray][lane][2]
+        ok_t = ok.transpose(order)
+        cols.append(pix.transpose(order)[ok_t].astype(np.int32))
+        vals.append(w.transpose(order)[ok_t])
+        counts[k * n_det:(k + 1) * n_det] = ok_t.reshape(n_det, -1).sum(axis=1)
+    indptr = np.zeros(n_angles * n_det + 1, dtype=np.int64)
+    np.cumsum(counts, out=indptr[1:])
+    indices = np.concatenate(cols)
+    del cols
+    data = np.concatenate(vals)
+    del vals
+    if indptr[-1] < 2 ** 31:
+        indptr = indptr.astype(np.int32)
+    return sps.csr_matrix((data, indices, indptr), shape=(n_angles * n_det, n * n))

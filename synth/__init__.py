@@ -27,7 +27,7 @@ import numpy as np
 __all__ = [
     "Workload", "WORKLOADS", "ellipse_phantom", "chest_phantom", "disc_image",
     "rigid_params", "dilatation_fields", "unit_noise", "gate_sequence",
-    "random_image", "random_sinograms",
+    "random_image", "random_sinograms", "BatchSlice", "batched_slices",
 ]
 
 
@@ -228,3 +228,34 @@ WORKLOADS = {
     "chest128_field10_k70": Workload("chest128_field10_k70", 128, 120, 182, 10, "field", 0.0, phantom="chest",
                                      kappa=70.0),
 }
+
+
+@dataclasses.dataclass(frozen=True)
+class BatchSlice:
+    """One slice of the batched workload: its gate count, kind of motion and
+    the seeds of its phantom, motion, noise and gate draws."""
+    index: int
+    n_gates: int
+    motion: str            # "rigid" | "field"
+    phantom_seed: int
+    motion_seed: int
+    noise_seed: int
+    gate_seed: int
+
+    def image(self, n: int) -> np.ndarray:
+        return ellipse_phantom(n, self.phantom_seed)
+
+    def rigid(self) -> np.ndarray:
+        return rigid_params(self.n_gates, self.motion_seed, 8.0, 10.0)
+
+    def fields(self, n: int) -> np.ndarray:
+        return dilatation_fields(n, self.n_gates, self.motion_seed)
+
+
+def batched_slices(count: int = 64, seed: int = 4):
+    """The batched workload: `count` independent ellipse slices whose gate
+    counts are uniform in {4..32}; odd slices move non-rigidly (dilatation
+    fields), even ones rigidly (rotation up to 8 deg, shift up to 10 px)."""
+    ngs = np.random.default_rng(seed).integers(4, 33, size=count)
+    return [BatchSlice(s, int(ngs[s]), "field" if s % 2 else "rigid", 200 + s, 100 + s, 300 + s, 500 + s)
+            for s in range(count)]

@@ -124,3 +124,39 @@ def test_stepping_axis_integer_rule():
     th, rows = projector.angle_table(720)
     assert rows[180] and rows[540] and not rows[181] and not rows[539]
     assert rows.sum() == 361   # k = 0..180 and 540..719
+
+
+@pytest.mark.parametrize("n,na,nd", [(16, 12, 23), (17, 13, 25)])
+def test_sparse_matrix_equals_dense_matrix(n, na, nd):
+    # the sparse assembly holds exactly the weights of `forward`, column by column
+    m = projector.sparse_matrix(n, na, nd)
+    assert m.shape == (na * nd, n * n)
+    np.testing.assert_array_equal(m.toarray(), projector.matrix(n, na, nd))
+
+
+@pytest.mark.parametrize("n,na,nd", [(64, 60, 92), (63, 45, 70), (48, 72, 40)])
+def test_sparse_matrix_products_are_forward_and_adjoint(n, na, nd):
+    # its product is the transform and its transpose's product is the scatter
+    # of the same weights (including a detector narrower than the image)
+    m = projector.sparse_matrix(n, na, nd)
+    x = synth.random_image(n, 31).astype(np.float64)
+    y = synth.random_sinograms(1, na, nd, 32)[0].astype(np.float64)
+    a = (m @ x.ravel()).reshape(na, nd)
+    b = (m.T @ y.ravel()).reshape(n, n)
+    np.testing.assert_allclose(a, projector.forward(x, na, nd), rtol=0, atol=1e-12 * np.abs(a).max())
+    np.testing.assert_allclose(b, projector.adjoint(y, n), rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+def test_matrix_backed_operators_equal_plain_ones():
+    from oracle.operators import GatedOperators
+    n, na, nd = 40, 36, 58
+    params = synth.rigid_params(2, 3, 8.0, 3.0)
+    plain = GatedOperators(n, na, nd, "rigid", params)
+    fast = GatedOperators(n, na, nd, "rigid", params, matrix=projector.sparse_matrix(n, na, nd))
+    x = synth.random_image(n, 4).astype(np.float64)
+    y = synth.random_sinograms(1, na, nd, 5)[0].astype(np.float64)
+    for i in range(2):
+        np.testing.assert_allclose(fast.A(i, x), plain.A(i, x), rtol=0, atol=1e-12 * np.abs(plain.A(i, x)).max())
+        np.testing.assert_allclose(fast.At(i, y), plain.At(i, y), rtol=0, atol=1e-12 * np.abs(plain.At(i, y)).max())
+    with pytest.raises(ValueError):
+        GatedOperators(n, na, nd, "rigid", params, matrix=projector.sparse_matrix(n, na, nd + 1))
