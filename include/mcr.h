@@ -409,6 +409,24 @@ typedef enum {
 mcr_status mcr_profile_enable(mcr_handle* h, int32_t enable);
 mcr_status mcr_profile_read(mcr_handle* h, double* total_ms, int64_t* launches);
 
+/* ---------------------------------------------------------------------------
+ * For callers that cannot allocate device memory at the time of the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): A x, the Joseph projection of mcr_project, in float32, with no
+ * handle. geom: host struct, 1 <= n <= 1024, 1 <= n_angles <= 4096,
+ * 1 <= n_det <= 16384 (larger sizes: MCR_ERR_ARG, nothing queued). x: device
+ * float [n][n]; sino: device float [n_angles][n_det] (out); both caller-owned
+ * and on the current device. stream: hipStream_t (NULL = the null stream);
+ * the call is asynchronous on it. The work runs in a fixed scratch array of
+ * the library (8.4 MiB of device memory per GPU, held from the first call
+ * on that GPU until the process ends): no hipMalloc, hipFree or other
+ * allocation happens in the call. Every call on one GPU shares that array, so
+ * calls that overlap on one GPU (different streams or host threads without
+ * ordering between them) race and must not be issued. The result equals
+ * mcr_project of a float32 handle of the same geometry up to summation order
+ * (it runs the one-thread-per-ray kernel, forward variant 0).                 */
+mcr_status mcr_project_noalloc(const mcr_geometry* geom, const float* x, float* sino, void* stream);
+
 /* Message describing the last non-OK status returned on the calling thread. */
 const char* mcr_last_error(void);
 

@@ -20,7 +20,7 @@ import torch
 from . import _lib
 from ._lib import McrError  # noqa: F401
 
-__all__ = ["Handle", "BatchHandle", "ReconState", "McrError", "step_sizes", "step_sizes_blocks"]
+__all__ = ["Handle", "BatchHandle", "ReconState", "McrError", "step_sizes", "step_sizes_blocks", "project_noalloc"]
 
 _DTYPES = {torch.float32: _lib.MCR_F32, torch.float64: _lib.MCR_F64}
 
@@ -32,6 +32,25 @@ def _stream_ptr(device) -> int:
 def _dbl_array(vals):
     vals = [float(v) for v in vals]
     return (ctypes.c_double * len(vals))(*vals)
+
+
+def project_noalloc(x, n_angles: int, n_det: int, out):
+    """A x into the caller's float32 tensor `out` [n_angles][n_det] with no
+    handle and no device allocation (mcr_project_noalloc), on the current
+    stream of x's device. x: contiguous float32 [n][n] on the HIP device."""
+    n = x.shape[0] if x.dim() == 2 else -1
+    for t, shape, name in ((x, (n, n), "x"), (out, (n_angles, n_det), "out")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda):
+            raise ValueError(f"{name} must be a tensor on the HIP device")
+        if t.dtype != torch.float32 or tuple(t.shape) != shape or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float32 tensor of shape {shape}")
+    if out.device != x.device:
+        raise ValueError("x and out must be on the same device")
+    geo = _lib.Geometry(n, int(n_angles), int(n_det))
+    with torch.cuda.device(x.device):
+        _lib.check(_lib.load().mcr_project_noalloc(ctypes.byref(geo), x.data_ptr(), out.data_ptr(),
+                                                   ctypes.c_void_p(_stream_ptr(x.device))))
+    return out
 
 
 def step_sizes(algo: str, norms_sq: Sequence[float], alpha: float, n_gates: int):

@@ -78,6 +78,7 @@ SIGNATURES = {
     "mcr_autotune": [_P, _I, _PI, _PI, _PI],
     "mcr_set_variant": [_P, _I, _I, _I],
     "mcr_profile_read": [_P, _PD, ctypes.POINTER(ctypes.c_int64)],
+    "mcr_project_noalloc": [ctypes.POINTER(Geometry), _P, _P, _P],
 }
 KERNEL_CLASSES = ["warp", "project", "backproject", "twarp", "xstep", "other"]
 

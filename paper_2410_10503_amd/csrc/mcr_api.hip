@@ -2808,3 +2808,153 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Joseph projection that allocates nothing (mcr_project_noalloc).
+//
+// Its scratch (the per-angle fixed-point table, an identity motion entry and
+// the zero-bordered image with its transpose) lives in one file-scope device
+// array. Host code never passes the array's name to a kernel: the name is a
+// host-side stand-in, so each device's address is looked up once with
+// hipGetSymbolAddress (with that device current) and kept per device.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kNoallocMaxN = 1024;
+constexpr int kNoallocMaxAngles = 4096;
+constexpr int kNoallocMaxDevices = 64;
+constexpr size_t kNoallocAlign = 256;
+
+constexpr size_t align_up(size_t v) { return (v + kNoallocAlign - 1) / kNoallocAlign * kNoallocAlign; }
+constexpr size_t kNoallocAngBytes = align_up(sizeof(AngleFx) * kNoallocMaxAngles);
+constexpr size_t kNoallocMotionBytes = align_up(sizeof(GateMotion<float>));
+constexpr size_t kNoallocPlaneBytes =
+    align_up(sizeof(float) * (size_t)(kNoallocMaxN + 2 * kPad) * (kNoallocMaxN + 2 * kPad));
+constexpr size_t kNoallocScratchBytes = kNoallocAngBytes + kNoallocMotionBytes + 2 * kNoallocPlaneBytes;
+
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_noalloc_mu;
+unsigned char* g_noalloc_ptr[kNoallocMaxDevices] = {};
+
+// The fixed-point table of angle_table_fx, evaluated on the device in FP64
+// with the same formulas (contraction off, as in the host code), plus the
+// identity motion entry and the zero border of both padded planes. The border
+// has to be cleared on every call: the array keeps what earlier calls, maybe
+// with another size, wrote there.
+#pragma clang fp contract(off)
+__global__ __launch_bounds__(256) void k_noalloc_prepare(int n, int na, int nd, AngleFx* __restrict__ ang,
+                                                         GateMotion<float>* __restrict__ motion,
+                                                         float* __restrict__ wP, float* __restrict__ wTP) {
+  const long tid = (long)blockIdx.x * 256 + threadIdx.x;
+  const long stride = (long)gridDim.x * 256;
+  if (tid < na) {
+    const int k = (int)tid;
+    const double hc = (n - 1) / 2.0, jc = (nd - 1) / 2.0, one = 4294967296.0;
+    const double th = M_PI * k / na;
+    const double cs = cos(th), sn = sin(th);
+    const bool rows = (4L * k <= na) || (4L * k >= 3L * na);
+    const double a = rows ? 1.0 / cs : 1.0 / sn;
+    const double beta = rows ? -sn / cs : -cs / sn;
+    const double c0 = hc - jc * a - hc * beta;
+    const double ia = 1.0 / a;
+    AngleFx f;
+    f.C0 = llround(c0 * one);
+    f.A = llround(a * one);
+    f.B = llround(beta * one);
+    f.U0 = llround(-c0 * ia * one);
+    f.P = llround(ia * one);
+    f.Q = llround(-beta * ia * one);
+    f.a = float(a);
+    f.beta = float(beta);
+    f.absa = float(fabs(a));
+    f.oma = float(1.0 - fabs(a));
+    f.ds = float(fabs(a));
+    f.rows = rows ? 1 : 0;
+    f.na32 = float(-fabs(a) / one);
+    f.pa32 = float(fabs(a) / one);
+    ang[k] = f;
+  }
+  if (tid == 0) {
+    GateMotion<float> m;
+    m.kind = 0;
+    m.radius = 0;
+    m.cm1 = m.sn = m.tx = m.ty = 0.0f;
+    m.i00 = m.i01 = m.i10 = m.i11 = 0.0f;
+    m.bx = m.by = 0.0f;
+    *motion = m;
+  }
+  const int pitch = n + 2 * kPad;
+  const long cells = (long)pitch * pitch;
+  for (long i = tid; i < cells; i += stride) {
+    const int r = (int)(i / pitch), c = (int)(i % pitch);
+    const bool interior = r >= kPad && r < kPad + n && c >= kPad && c < kPad + n;
+    if (!interior) {
+      wP[i] = 0.0f;
+      wTP[i] = 0.0f;
+    }
+  }
+}
+#pragma clang fp contract(on)
+
+// This device's address of `scratch`, looked up on the first call made with
+// the device current.
+mcr_status noalloc_scratch(unsigned char** out) {
+  int dev = -1;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocMaxDevices)
+    return fail(MCR_ERR_STATE, "device %d is beyond the %d devices this entry point serves", dev,
+                kNoallocMaxDevices);
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(MCR_ERR_HIP, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_noalloc_ptr[dev] = (unsigned char*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return MCR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mcr_status mcr_project_noalloc(const mcr_geometry* geom, const float* x, float* sino, void* stream) {
+  if (!geom) return fail(MCR_ERR_ARG, "null geometry");
+  const int n = geom->n, na = geom->n_angles, nd = geom->n_det;
+  if (n < 1 || n > kNoallocMaxN)
+    return fail(MCR_ERR_ARG, "n = %d outside [1, %d], the largest image this entry point's scratch holds", n,
+                kNoallocMaxN);
+  if (na < 1 || na > kNoallocMaxAngles)
+    return fail(MCR_ERR_ARG, "n_angles = %d outside [1, %d], the largest angle table this entry point's scratch holds",
+                na, kNoallocMaxAngles);
+  if (nd < 1 || nd > 16384) return fail(MCR_ERR_ARG, "n_det = %d outside [1, 16384]", nd);
+  STATUS_OK(check_ptr(x, "x"));
+  STATUS_OK(check_ptr(sino, "sino"));
+  unsigned char* base = nullptr;
+  STATUS_OK(noalloc_scratch(&base));
+  AngleFx* ang = (AngleFx*)base;
+  GateMotion<float>* motion = (GateMotion<float>*)(base + kNoallocAngBytes);
+  float* wP = (float*)(base + kNoallocAngBytes + kNoallocMotionBytes);
+  float* wTP = (float*)(base + kNoallocAngBytes + kNoallocMotionBytes + kNoallocPlaneBytes);
+  hipStream_t s = (hipStream_t)stream;
+  const int pitch = n + 2 * kPad;
+  Geo<float> g{n, na, nd, pitch, float((n - 1) / 2.0), float((nd - 1) / 2.0)};
+  hipLaunchKernelGGL(k_noalloc_prepare, dim3(std::max<unsigned>(cdiv(na, 256), cdiv((long)pitch * pitch, 1024))),
+                     dim3(256), 0, s, n, na, nd, ang, motion, wP, wTP);
+  LAUNCH_OK();
+  // the identity warp copies x into both padded planes (row-major and
+  // transposed); it never reads the field argument of an identity gate
+  hipLaunchKernelGGL(k_warp_fwd<float>, dim3(cdiv(n, 32), cdiv(n, 32), 1), dim3(32, 32), 0, s, g,
+                     (const GateMotion<float>*)motion, 0, (const float*)wP, 0L, 0L, x, 0L, wP, wTP, 0L,
+                     (const SlotInfo*)nullptr, (float*)nullptr, 0L, 0L);
+  LAUNCH_OK();
+  hipLaunchKernelGGL((k_joseph_fwd_fx<0>), dim3(cdiv(nd, 256), na, 1), dim3(256), 0, s, g,
+                     (const AngleFx*)ang, (const float*)wP, (const float*)wTP, 0L, sino, 0L, 0,
+                     (const GateScalars<float>*)nullptr, (const GatePtrs<float>*)nullptr, (const SlotInfo*)nullptr, 0);
+  LAUNCH_OK();
+  return MCR_OK;
+}
+
+}  // extern "C"

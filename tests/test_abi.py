@@ -143,3 +143,18 @@ def test_register_affine_rejects_null_handle(lib):
 
 def test_register_field_rejects_null_handle(lib):
     assert lib.mcr_register_field(None, 0, None, None, None, 0.1, None, 0, 10, 1e-4, None, None) == _lib.MCR_ERR_ARG
+
+
+def test_project_noalloc_validates_before_device_work(lib):
+    # sizes beyond the fixed scratch array, a null geometry and null pointers
+    # are refused before anything touches a device (this runs without a GPU)
+    dummy = ctypes.c_void_p(0x1000)
+    for geo, msg in ((_lib.Geometry(1025, 10, 10), b"n = 1025"), (_lib.Geometry(64, 4097, 10), b"n_angles = 4097"),
+                     (_lib.Geometry(64, 10, 16385), b"n_det = 16385"), (_lib.Geometry(0, 10, 10), b"n = 0")):
+        st = lib.mcr_project_noalloc(ctypes.byref(geo), dummy, dummy, None)
+        assert st == _lib.MCR_ERR_ARG
+        assert msg in lib.mcr_last_error()
+    assert lib.mcr_project_noalloc(None, dummy, dummy, None) == _lib.MCR_ERR_ARG
+    geo = _lib.Geometry(64, 10, 10)
+    assert lib.mcr_project_noalloc(ctypes.byref(geo), None, dummy, None) == _lib.MCR_ERR_ARG
+    assert lib.mcr_project_noalloc(ctypes.byref(geo), dummy, None, None) == _lib.MCR_ERR_ARG
