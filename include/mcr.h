@@ -166,15 +166,19 @@ mcr_status mcr_pdhg_epoch(mcr_handle* h, const mcr_state* st, const void* const*
 mcr_status mcr_batch_create(const mcr_geometry* geom, int32_t n_slices, const int32_t* gates_per_slice,
                             const mcr_motion* motion, mcr_dtype dtype, void* stream, mcr_handle** out);
 /* One SPDHG epoch of every slice (Algorithm 1 with serial sampling; slice s
- * runs N_s iterations): all slices take step (i), then at every step t the
- * slices with N_s > t advance together, one launch per phase. Device arrays
+ * runs N_s iterations): all slices take step (i), then max_s N_s rounds run
+ * one launch per phase each over the round's slots; slice s takes its
+ * iteration j in round floor(j max N / N_s), so every round holds about
+ * sum N_s / max N slots and each slice's iterations keep their order (the
+ * slices are independent problems, so the rounds only decide which slots
+ * share a launch; the results are those of per-slice epochs). Device arrays
  * (handle dtype): x, z, zbar [S][n][n]; y, d [sum N_s][n_angles][n_det] in
  * global gate order. Host arrays: alpha, tau, theta [S]; sigma, p [sum N_s];
  * gate_seq [sum N_s], slice s's draws (local gate indices) at its first global
  * gate. use_graph != 0 replays the epoch as a HIP graph (captured on first use
  * and again whenever x, z or zbar move, or after mcr_set_variant,
- * mcr_autotune, mcr_set_motion or mcr_set_rigid_params) on a stream of the
- * handle, ordered after and before the handle's stream by events.             */
+ * mcr_autotune, mcr_set_motion or mcr_set_rigid_params; captured on a stream
+ * of the handle) and launched on the handle's stream.                         */
 mcr_status mcr_batch_spdhg_epoch(mcr_handle* h, void* x, void* z, void* zbar, void* y, const void* d,
                                  const double* alpha, const double* sigma, const double* tau,
                                  const double* theta, const double* p, const int32_t* gate_seq,
@@ -315,8 +319,8 @@ mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq,
 /* ---------------------------------------------------------------------------
  * Sampling over gates x angle subsets (the next step named in the
  * Conclusions: sampling over both the gates and subsets of the data).
- * The angles are cut into M contiguous subsets [k_s, k_{s+1}),
- * k_s = floor(s n_angles / M). Block b = i M + s (gate i, subset s) has the
+ * The angles are cut into M subsets: contiguous ones [k_s, k_{s+1}),
+ * k_s = floor(s n_angles / M), or paired ones (mcr_set_subset_partition). Block b = i M + s (gate i, subset s) has the
  * operator A_b = R_s A D_i (R_s keeps the rows of subset s) and the data term
  * f_b(u) = |u - d_{i,s}|^2 / N, so the objective, its minimiser and the dual
  * solution are those of the gate problem; f_b^* keeps the modulus N/2, so the
@@ -329,6 +333,15 @@ mcr_status mcr_step_sizes(int32_t algo, int32_t n_gates, const double* norms_sq,
  * crosses a subset boundary; the full-range operators are unchanged.
  * Synchronises the stream. Not available on batch handles (MCR_ERR_STATE).  */
 mcr_status mcr_set_subsets(mcr_handle* h, int32_t n_subsets);
+/* The same with a choice of partition: paired = 0 gives the contiguous
+ * subsets above; paired != 0 (n_angles even, 1 <= M <= n_angles/2) gives
+ * subset s = [h_s, h_{s+1}) and [h_s + n_angles/2, h_{s+1} + n_angles/2),
+ * h_s = floor(s (n_angles/2) / M): every angle with its partner a quarter
+ * turn away (the Conclusions leave the choice of subsets open; every
+ * partition gives the same objective and minimiser). With paired subsets
+ * the quarter-turn projector pair (forward 4, adjoint codes < 0) also runs
+ * the block launches. Synchronises the stream.                               */
+mcr_status mcr_set_subset_partition(mcr_handle* h, int32_t n_subsets, int32_t paired);
 /* |A_b|^2 for block (gate, subset) by FP64 power iteration on A_b^* A_b, as
  * mcr_power_norm_sq.                                                          */
 mcr_status mcr_block_norm_sq(mcr_handle* h, int32_t gate, int32_t subset, const double* v0,

@@ -4,8 +4,12 @@ The Conclusions name sampling over both the gates and subsets of the data
 (e.g. angles) as the next step. This module is that extension of Algorithm 1,
 written from the model of Section II-A:
 
-* the angles are cut into M contiguous subsets [k_s, k_{s+1}) with
-  k_s = floor(s n_a / M); R_s keeps the sinogram rows of subset s;
+* the angles are cut into M subsets, either contiguous ranges
+  [k_s, k_{s+1}) with k_s = floor(s n_a / M), or (n_a even) paired ranges
+  [h_s, h_{s+1}) and [h_s + n_a/2, h_{s+1} + n_a/2) with h_s = floor(s n_a / (2M)),
+  every angle together with the one a quarter turn away (the Conclusions
+  name no partition; any partition of the angles gives the same problem);
+  R_s keeps the sinogram rows of subset s;
 * a block b = (i, s) (b = i M + s) has the operator A_b = R_s A D_i and the
   data term f_b(u) = |u - d_{i,s}|^2 / N, so that sum_s f_{(i,s)}(R_s u) equals
   the gate's f_i(u): the objective O, its minimiser x* and the dual solution
@@ -38,23 +42,55 @@ def subset_bounds(n_angles: int, n_subsets: int):
     return [(s * n_angles) // n_subsets for s in range(n_subsets + 1)]
 
 
-class BlockOperators:
-    """Blocks b = i M + s of a GatedOperators `ops` and M angle subsets."""
+def contiguous_subsets(n_angles: int, n_subsets: int):
+    """Subset s = the angles [k_s, k_{s+1}) (index arrays)."""
+    kb = subset_bounds(n_angles, n_subsets)
+    return [np.arange(kb[s], kb[s + 1]) for s in range(n_subsets)]
 
-    def __init__(self, ops, n_subsets: int):
+
+def paired_subsets(n_angles: int, n_subsets: int):
+    """Subset s = the angles [h_s, h_{s+1}) and their partners a quarter turn
+    away, [h_s + n_a/2, h_{s+1} + n_a/2), h_s = floor(s (n_a/2) / M) (n_a even,
+    1 <= M <= n_a/2)."""
+    if n_angles % 2:
+        raise ValueError("paired subsets need an even number of angles")
+    half = n_angles // 2
+    hb = subset_bounds(half, n_subsets)
+    return [np.concatenate([np.arange(hb[s], hb[s + 1]), np.arange(hb[s] + half, hb[s + 1] + half)])
+            for s in range(n_subsets)]
+
+
+class BlockOperators:
+    """Blocks b = i M + s of a GatedOperators `ops` and M angle subsets.
+
+    partition: "contiguous" (default), "paired", or an explicit list of M
+    index arrays that together hold every angle exactly once."""
+
+    def __init__(self, ops, n_subsets: int, partition="contiguous"):
         self.ops = ops
         self.n_gates = ops.n_gates
         self.n_subsets = int(n_subsets)
         self.n_blocks = self.n_gates * self.n_subsets
         self.n, self.n_angles, self.n_det = ops.n, ops.n_angles, ops.n_det
-        self.bounds = subset_bounds(ops.n_angles, self.n_subsets)
+        if isinstance(partition, str):
+            make = {"contiguous": contiguous_subsets, "paired": paired_subsets}[partition]
+            parts = make(ops.n_angles, self.n_subsets)
+        else:
+            parts = [np.sort(np.asarray(p, dtype=np.int64)) for p in partition]
+        if len(parts) != self.n_subsets:
+            raise ValueError("the partition needs one index array per subset")
+        seen = np.concatenate(parts) if parts else np.zeros(0, dtype=np.int64)
+        if not np.array_equal(np.sort(seen), np.arange(ops.n_angles)):
+            raise ValueError("the subsets must hold every angle exactly once")
+        self.parts = parts
 
     def split(self, b: int):
         """(gate, subset) of block b."""
         return divmod(int(b), self.n_subsets)
 
-    def rows(self, s: int) -> slice:
-        return slice(self.bounds[s], self.bounds[s + 1])
+    def rows(self, s: int) -> np.ndarray:
+        """The sinogram rows (angles) of subset s."""
+        return self.parts[s]
 
     def mask(self, s: int, y):
         """R_s^T R_s y: the rows of subset s, zero elsewhere."""

@@ -122,6 +122,12 @@ class Handle:
         for i, m in enumerate(motion):
             arr[i] = self._motion(m, keep)
         self._kinds = [arr[i].kind for i in range(self.n_gates)]
+        # bumped by every call that changes a gate's motion; `_installed` is the
+        # whole-handle motion last installed by the differentiation path
+        # ((kind, tensor) or None when unknown), so that its backward pass can
+        # put back what it found
+        self._motion_gen = 0
+        self._installed = None
         geo = _lib.Geometry(self.n, self.n_angles, self.n_det)
         self._stream = _stream_ptr(self.device)
         _lib.check(self._lib.mcr_create(ctypes.byref(geo), self.n_gates, arr, _DTYPES[dtype],
@@ -192,9 +198,14 @@ class Handle:
         return (ctypes.c_void_p * len(vals))(*vals)
 
     # -- operators -----------------------------------------------------------
+    def _motion_changed(self):
+        self._motion_gen += 1
+        self._installed = None
+
     def set_motion(self, gate: int, motion):
         keep = []
         m = self._motion(motion, keep)
+        self._motion_changed()
         self._checked_motion_call(gate, lambda: self._lib.mcr_set_motion(self._h, int(gate), ctypes.byref(m)))
         self._kinds[int(gate)] = m.kind
 
@@ -215,6 +226,7 @@ class Handle:
         if len(vals) != 3 * self.n_gates:
             raise ValueError(f"need {self.n_gates} x 3 rigid parameters")
         self._sync_stream()
+        self._motion_changed()
         _lib.check(self._lib.mcr_set_rigid_params(self._h, _dbl_array(vals)))
 
     def warp(self, gate, x, out=None):
@@ -338,6 +350,7 @@ class Handle:
         """Rigid parameters (phi, t_x, t_y) of `gate` minimising |D ref - target|^2 / 2, from
         `params`; the gate's motion is set to them. Returns (params, energy, steps)."""
         self._sync_stream()
+        self._motion_changed()
         th = (ctypes.c_double * 3)(*[float(v) for v in params])
         E, k = ctypes.c_double(), ctypes.c_int32()
         _lib.check(self._lib.mcr_register_rigid(self._h, int(gate), self._img(ref, "ref"), self._img(target, "target"),
@@ -350,6 +363,7 @@ class Handle:
         A11, t_x, t_y), minimising |D ref - target|^2 / 2 from `params`; the gate's field is set to
         it. Returns (params, energy, steps)."""
         self._sync_stream()
+        self._motion_changed()
         th = (ctypes.c_double * 6)(*[float(v) for v in params])
         E, k = ctypes.c_double(), ctypes.c_int32()
         rp, tp = self._img(ref, "ref"), self._img(target, "target")
@@ -365,6 +379,7 @@ class Handle:
         sigmas: scale-space schedule (Gaussian widths in pixels, coarse to fine; empty: one level
         on the images themselves). Returns (field, energy, steps)."""
         self._sync_stream()
+        self._motion_changed()
         if field is None:
             field = torch.zeros((2, self.n, self.n), dtype=torch.float32, device=self.device)
         if not (isinstance(field, torch.Tensor) and field.dtype == torch.float32 and field.is_cuda
@@ -391,10 +406,12 @@ class Handle:
                                                ctypes.byref(out), ctypes.byref(it)))
         return out.value, it.value
 
-    def set_subsets(self, n_subsets: int):
-        """Cut the angles into n_subsets contiguous subsets (gates x angle-subsets sampling)."""
+    def set_subsets(self, n_subsets: int, paired: bool = False):
+        """Cut the angles into n_subsets subsets (gates x angle-subsets
+        sampling): contiguous ranges, or (paired) ranges of the first half
+        with their partners a quarter turn away."""
         self._sync_stream()
-        _lib.check(self._lib.mcr_set_subsets(self._h, int(n_subsets)))
+        _lib.check(self._lib.mcr_set_subset_partition(self._h, int(n_subsets), 1 if paired else 0))
         self.n_subsets = int(n_subsets)
 
     def block_norm_sq(self, gate: int, subset: int, v0, max_iter: int = 500, rtol: float = 1e-12):
@@ -495,6 +512,12 @@ class BatchHandle(Handle):
         for i, m in enumerate(motion):
             arr[i] = self._motion(m, keep)
         self._kinds = [arr[i].kind for i in range(self.n_gates)]
+        # bumped by every call that changes a gate's motion; `_installed` is the
+        # whole-handle motion last installed by the differentiation path
+        # ((kind, tensor) or None when unknown), so that its backward pass can
+        # put back what it found
+        self._motion_gen = 0
+        self._installed = None
         geo = _lib.Geometry(self.n, self.n_angles, self.n_det)
         ng = (ctypes.c_int32 * self.n_slices)(*self.gates_per_slice)
         self._stream = _stream_ptr(self.device)

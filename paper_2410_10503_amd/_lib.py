@@ -63,6 +63,7 @@ SIGNATURES = {
     "mcr_duality_gap": [_P, ctypes.POINTER(State), _PP, _D, _PD],
     "mcr_step_sizes": [_I, _I, _PD, _D, _PD, _PD, _PD, _PD],
     "mcr_set_subsets": [_P, _I],
+    "mcr_set_subset_partition": [_P, _I, _I],
     "mcr_block_norm_sq": [_P, _I, _I, _P, _I, _D, _PD, _PI],
     "mcr_spdhg_blocks_iterate": [_P, ctypes.POINTER(State), _PP, _D, _PD, _D, _D, _PD, _PI, _I],
     "mcr_step_sizes_blocks": [_I, _I, _PD, _D, _PD, _PD, _PD, _PD],

@@ -10,6 +10,14 @@ dual and the iteration's backprojection); the backward pass runs the
 library's reverse of each iteration (mcr_spdhg_step_backward) from its
 checkpoint. All arithmetic runs in the
 library's kernels; this module moves tensors.
+
+The handle holds one motion at a time. The forward pass installs its motion
+and keeps a copy; if the handle's motion has changed by the time backward runs
+(another unrolled forward on the same handle, a finite-difference evaluation,
+a registration), backward installs the copy for its reverse steps, so the
+gradient is that of its own operators A_i = A D_i, and then puts back the
+motion it found when that motion was installed by another unrolled forward
+(otherwise the forward's motion stays installed).
 """
 from __future__ import annotations
 
@@ -17,17 +25,23 @@ import torch
 
 
 def _apply_motion(handle, kind: str, motion: torch.Tensor):
+    """Installs the whole-handle motion and records it (with the handle's
+    motion generation after the change)."""
     if kind == "rigid":
         handle.set_rigid_params(motion.detach().to(torch.float64).cpu().tolist())
-        return
-    for i in range(handle.n_gates):
-        handle.set_motion(i, ("field", motion[i].detach().to(torch.float32).contiguous()))
+    else:
+        for i in range(handle.n_gates):
+            handle.set_motion(i, ("field", motion[i].detach().to(torch.float32).contiguous()))
+    handle._installed = (kind, motion)
+    return handle._motion_gen
 
 
 class UnrolledSPDHG(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x0, motion, handle, kind, d, alpha, sigma, tau, theta, p, gate_seq):
-        _apply_motion(handle, kind, motion)
+        saved = motion.detach().clone()
+        ctx.motion_gen = _apply_motion(handle, kind, saved)
+        ctx.motion_saved = saved
         st = handle.zero_state()
         st.x.copy_(x0.detach())
         K = len(gate_seq)
@@ -48,6 +62,10 @@ class UnrolledSPDHG(torch.autograd.Function):
         h = ctx.handle
         d, alpha, sigma, tau, theta, p, seq = ctx.args
         x1c, yc, bc = ctx.ckpt
+        restore = None
+        if h._motion_gen != ctx.motion_gen:
+            restore = h._installed
+            _apply_motion(h, ctx.kind, ctx.motion_saved)
         gx = gout.detach().to(h.dtype).contiguous().clone()
         gz = torch.zeros_like(gx)
         gzb = torch.zeros_like(gx)
@@ -62,6 +80,8 @@ class UnrolledSPDHG(torch.autograd.Function):
                 gy[g] = torch.zeros((h.n_angles, h.n_det), dtype=h.dtype, device=h.device)
             h.spdhg_step_backward(g, x1c[k], yc[k], d[g], alpha, sigma[g], tau, theta, p[g], gx, gy[g], gz, gzb,
                                   gm[g], b_ckpt=bc[k])
+        if restore is not None:
+            _apply_motion(h, *restore)
         gmot = gm.to(device=ctx.motion_device, dtype=ctx.motion_dtype).reshape(ctx.motion_shape)
         return gx, gmot, None, None, None, None, None, None, None, None, None
 

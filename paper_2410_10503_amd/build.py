@@ -16,8 +16,10 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libmcr.so")
+PROBES_LIB = os.path.join(PKG, "libmcr_probes.so")
 
 SOURCES = ["mcr_api.hip"]
+PROBE_SOURCES = ["mcr_probes.hip"]  # roofline probes (measurement only), a library of their own
 HEADERS = ["mcr_kernels.h"]
 
 FLAGS = [
@@ -40,10 +42,9 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (set HIPCC or install ROCm)")
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source into libmcr.so; returns its path. Always rebuilds."""
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + FLAGS + ["-I", INCLUDE, "-I", CSRC] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+def _compile(sources, out, verbose):
+    tmp = out + ".tmp"
+    cmd = [hipcc()] + FLAGS + ["-I", INCLUDE, "-I", CSRC] + [os.path.join(CSRC, s) for s in sources] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -52,7 +53,14 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed with status {res.returncode}")
     if verbose and res.stderr.strip():
         sys.stderr.write(res.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compile libmcr.so (the HIP kernels and the C ABI) and libmcr_probes.so
+    (roofline probes); returns the path of libmcr.so. Always rebuilds."""
+    _compile(SOURCES, LIB, verbose)
+    _compile(PROBE_SOURCES, PROBES_LIB, verbose)
     return LIB
 
 

@@ -152,9 +152,13 @@ struct mcr_handle {
   int* quad_multi = nullptr;
   int quad_npieces = 0, quad_nmulti = 0;
   long quad_part_floats = 0;
-  // angle subsets (mcr_set_subsets): subset s holds angles [sub_k[s], sub_k[s + 1])
+  // angle subsets (mcr_set_subsets, mcr_set_subset_partition): subset s holds
+  // the angles of sub[s], one range or (paired) a range and its partner range
   int M = 1;
-  std::vector<int> sub_k;
+  bool sub_paired = false;
+  std::vector<AngleRanges> sub;
+  std::vector<int2> quad_sub;        // paired subsets: (first quad piece, pieces) per subset
+  std::vector<int2> quad_sub_multi;  // paired subsets: (first multi-piece unit entry, entries) per subset
   long shear_part_floats = 0;
   float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
   // affine registration scratch (allocated on first use)
@@ -168,8 +172,10 @@ struct mcr_handle {
   struct Batch {
     int S = 0;                        // 0: not a batch handle
     std::vector<int> ng, off;         // gates per slice, first global gate of each slice
-    int tmax = 0;                     // largest gate count
-    std::vector<int> nact;            // slices still iterating at step t
+    int tmax = 0;                     // largest gate count = number of rounds
+    std::vector<int> nact;            // slots of round t
+    std::vector<int2> items;          // (slice, iteration) of every slot, round after round
+    std::vector<int> round_off;       // first item of each round
     SlotInfo* slots = nullptr;        // device [tmax][S]
     void* tc = nullptr;               // device [S][2] (tau, c_x) in the handle's dtype
     void* pin = nullptr;              // pinned staging of slots + tc
@@ -177,7 +183,6 @@ struct mcr_handle {
     hipEvent_t pin_ev = nullptr;
     bool pin_recorded = false;
     hipStream_t gstream = nullptr;    // stream the epoch graph runs on
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     const void* key[3] = {nullptr, nullptr, nullptr};  // x, z, zbar baked into the graph
@@ -485,7 +490,7 @@ bool shear_tile_bands(int n, int nd, const std::vector<AngleFx>& af, int k0, int
 // window; detector tiles of kShJD bins cover bins [0, nbins); cap: staged
 // entries per band; ppp: partial sums per piece.
 Schedule build_shear_units(int n, int nd, int nbins, const std::vector<AngleFx>& af, const std::vector<int2>& runs,
-                           const std::vector<int>& bounds, int cap, int ppp, int piece_lines) {
+                           const std::vector<int>& asub, int M, int cap, int ppp, int piece_lines) {
   Schedule S;
   const int ntiles = (nbins + kShJD - 1) / kShJD;
   for (const int2& run : runs) {
@@ -541,14 +546,11 @@ Schedule build_shear_units(int n, int nd, int nbins, const std::vector<AngleFx>&
       if (pc > 1) S.part_floats += (long)pc * ppp;
     }
   }
-  // pieces and multi-piece units come in chunk order, so each subset's are contiguous
-  const int M = (int)bounds.size() - 1;
+  // pieces and multi-piece units come in chunk order and the runs in subset
+  // order, so each subset's are contiguous
   S.sub_pieces.assign(M, make_int2(0, 0));
   S.sub_multi.assign(M, make_int2(0, 0));
-  auto subset_of = [&](int unit) {
-    const int k0 = S.chunks[S.units[unit].x].x;
-    return (int)(std::upper_bound(bounds.begin(), bounds.end(), k0) - bounds.begin()) - 1;
-  };
+  auto subset_of = [&](int unit) { return asub[S.chunks[S.units[unit].x].x]; };
   for (int q = 0; q < (int)S.pieces.size(); ++q) {
     int2& r = S.sub_pieces[subset_of(S.pieces[q].z)];
     if (r.y == 0) r.x = q;
@@ -562,35 +564,44 @@ Schedule build_shear_units(int n, int nd, int nbins, const std::vector<AngleFx>&
   return S;
 }
 
-// Line-sheared forward over all angles: runs of one stepping type, cut at
-// the subset bounds.
-Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& bounds) {
-  std::vector<int2> runs;
-  for (const int2& r : angle_chunks(af, INT_MAX)) {
+// Runs of `runs` cut where the subset changes, in subset order (stable).
+std::vector<int2> cut_runs(const std::vector<int2>& runs, const std::vector<int>& asub) {
+  std::vector<int2> out;
+  for (const int2& r : runs) {
     int k = r.x;
-    for (size_t b = 1; b < bounds.size() && k < r.x + r.y; ++b) {
-      const int e = std::min(r.x + r.y, bounds[b]);
-      if (e > k) {
-        runs.push_back(make_int2(k, e - k));
+    for (int e = r.x + 1; e <= r.x + r.y; ++e) {
+      if (e == r.x + r.y || asub[e] != asub[k]) {
+        out.push_back(make_int2(k, e - k));
         k = e;
       }
     }
   }
-  return build_shear_units(n, nd, nd, af, runs, bounds, kShCap, 2 * 256, kShPieceLines);
+  std::stable_sort(out.begin(), out.end(), [&](const int2& a, const int2& b) { return asub[a.x] < asub[b.x]; });
+  return out;
+}
+
+// Line-sheared forward over all angles: runs of one stepping type and one
+// subset (asub: the subset of every angle), in subset order.
+Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& asub, int M) {
+  return build_shear_units(n, nd, nd, af, cut_runs(angle_chunks(af, INT_MAX), asub), asub, M, kShCap, 2 * 256,
+                           kShPieceLines);
 }
 
 // Quarter-turn forward: the primary angles are the row-stepping ones
 // (4k <= n_angles or 4k >= 3 n_angles), without k = 3 n_angles / 4 (the
 // partner of k = n_angles / 4); with n_angles even each pair {k, k +- n_angles/2}
 // holds exactly one primary angle. Bins [0, ceil(n_det / 2)).
-Schedule build_quad_schedule(int n, int nd, const std::vector<AngleFx>& af) {
+// asub: the subset of every angle, the same for an angle and its partner
+// (paired subsets, or one subset); runs cut by subset, in subset order.
+Schedule build_quad_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& asub, int M) {
   const int na = (int)af.size();
   std::vector<int2> runs;
   const int a_end = na / 4 + 1;                  // k <= floor(na / 4)
   const int b_beg = (3 * na + 3) / 4 + (na % 4 == 0 ? 1 : 0);
   if (a_end > 0) runs.push_back(make_int2(0, std::min(a_end, na)));
   if (b_beg < na) runs.push_back(make_int2(b_beg, na - b_beg));
-  return build_shear_units(n, nd, (nd + 1) / 2, af, runs, {0, na}, kQuCap, 8 * 256, kQuPieceLines);
+  return build_shear_units(n, nd, (nd + 1) / 2, af, cut_runs(runs, asub), asub, M, kQuCap, 8 * 256,
+                           kQuPieceLines);
 }
 
 Schedule build_schedule(int n, int nd, const std::vector<AngleFx>& af, int ka, int jd, int wl) {
@@ -647,6 +658,17 @@ void dfree(mcr_handle* h, void* p) {
   (void)hipFree(p);
 }
 
+// The subset of every angle under the handle's partition.
+std::vector<int> angle_subsets(const mcr_handle* h) {
+  std::vector<int> asub(h->geo.n_angles, 0);
+  for (int s = 0; s < (int)h->sub.size(); ++s) {
+    const AngleRanges& r = h->sub[s];
+    for (int k = r.ka; k < r.kb; ++k) asub[k] = s;
+    for (int k = r.kc; k < r.kd; ++k) asub[k] = s;
+  }
+  return asub;
+}
+
 // (Re)builds the line-sheared forward's tables for the handle's angle subsets.
 // Synchronises the stream (the previous tables may still be in use).
 mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
@@ -660,7 +682,7 @@ mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
   h->shear_npieces = h->shear_nmulti = 0;
   h->shear_sub.clear();
   h->shear_sub_multi.clear();
-  const Schedule ss = build_shear_schedule(h->geo.n, h->geo.n_det, af, h->sub_k);
+  const Schedule ss = build_shear_schedule(h->geo.n, h->geo.n_det, af, angle_subsets(h), h->M);
   if (!ss.ok) return MCR_OK;  // variant 3 unavailable on this geometry
   const int ns = h->nslots;
   h->shear_part_floats = ss.part_floats;
@@ -690,20 +712,40 @@ mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
   return MCR_OK;
 }
 
-// Tables of the quarter-turn forward (float handles with even n and n_angles).
+// Tables of the quarter-turn forward (float handles with even n and n_angles),
+// over all angles and, with paired subsets, per subset. Rebuilding frees the
+// previous tables (synchronises the stream).
 mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
   if (h->geo.n % 2 || h->geo.n_angles % 2) return MCR_OK;
-  Schedule qs = build_quad_schedule(h->geo.n, h->geo.n_det, af);
-  if (!qs.ok || qs.pieces.empty()) return MCR_OK;  // variant 4 unavailable on this geometry
-  // consecutive workgroups go to the 8 XCDs in turn: sort the pieces by the
-  // middle image row of their lines and cut them into 8 runs of equal line
-  // counts; run x goes to positions = x (mod 8), so that each XCD's L2 holds
-  // about an eighth of the image planes; shorter runs are padded with
-  // entries of unit -1
-  {
+  HIP_OK(hipStreamSynchronize(h->stream));
+  for (void* p : {(void*)h->quad_chunks, (void*)h->quad_pieces, (void*)h->quad_units, (void*)h->quad_bands,
+                  (void*)h->quad_part, (void*)h->quad_multi})
+    dfree(h, p);
+  h->quad_chunks = h->quad_pieces = h->quad_units = h->quad_bands = nullptr;
+  h->quad_part = nullptr;
+  h->quad_multi = nullptr;
+  h->quad_npieces = h->quad_nmulti = 0;
+  h->quad_sub.clear();
+  h->quad_sub_multi.clear();
+  // the subsets the quarter-turn kernels can serve: one, or paired ones
+  const bool by_subset = h->M > 1 && h->sub_paired;
+  const std::vector<int> asub = by_subset ? angle_subsets(h) : std::vector<int>(h->geo.n_angles, 0);
+  const int M = by_subset ? h->M : 1;
+  Schedule qs = build_quad_schedule(h->geo.n, h->geo.n_det, af, asub, M);
+  if (!qs.ok || qs.pieces.empty()) return MCR_OK;  // variants 4 and 5 unavailable on this geometry
+  // consecutive workgroups go to the 8 XCDs in turn: within each subset, sort
+  // the pieces by the middle image row of their lines and cut them into 8
+  // runs of equal line counts; run x goes to positions = x (mod 8), so that
+  // each XCD's L2 holds about an eighth of the image planes; shorter runs are
+  // padded with entries of unit -1
+  std::vector<int4> ordered;
+  std::vector<int2> sub_pieces(M);
+  for (int sb = 0; sb < M; ++sb) {
+    const int2 r = qs.sub_pieces[sb];
     std::vector<std::pair<int, int4>> keyed;
     long total = 0;
-    for (const int4& pc : qs.pieces) {
+    for (int q = r.x; q < r.x + r.y; ++q) {
+      const int4& pc = qs.pieces[q];
       int lo = INT_MAX, hi = -1, lines = 0;
       for (int b = pc.x; b < pc.x + pc.y; ++b) {
         lo = std::min(lo, qs.bands[b].x);
@@ -727,10 +769,12 @@ mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
     std::vector<int4> order(8 * len, make_int4(0, 0, -1, 0));
     for (int x = 0; x < 8; ++x)
       for (size_t q = 0; q < bucket[x].size(); ++q) order[8 * q + x] = bucket[x][q];
-    qs.pieces = order;
+    sub_pieces[sb] = make_int2((int)ordered.size(), (int)order.size());
+    ordered.insert(ordered.end(), order.begin(), order.end());
   }
+  qs.pieces = ordered;
   const int ns = h->nslots;
-  STATUS_OK(dmalloc(h, (void**)&h->wf.wQ, sizeof(float) * 3 * h->padded * ns));
+  if (!h->wf.wQ) STATUS_OK(dmalloc(h, (void**)&h->wf.wQ, sizeof(float) * 3 * h->padded * ns));
   h->quad_part_floats = qs.part_floats;
   STATUS_OK(dmalloc(h, (void**)&h->quad_chunks, sizeof(int4) * qs.chunks.size()));
   STATUS_OK(dmalloc(h, (void**)&h->quad_pieces, sizeof(int4) * qs.pieces.size()));
@@ -753,6 +797,10 @@ mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
   HIP_OK(hipStreamSynchronize(h->stream));
   h->quad_npieces = (int)qs.pieces.size();
   h->quad_nmulti = (int)qs.multi.size();
+  if (by_subset) {
+    h->quad_sub = sub_pieces;
+    h->quad_sub_multi = qs.sub_multi;
+  }
   return MCR_OK;
 }
 
@@ -766,18 +814,18 @@ int quad_tiled_px(int code) { return code >= -8 ? -code : 8; }
 // The quarter-turn adjoint pairs angle k with angle k +- n_angles/2 and a
 // pixel with its quarter turns: it needs an even image size, an even number
 // of angles, and all of them in the launch.
-bool quad_ok(const mcr_handle* h, int ka, int kb) {
-  return h->geo.n % 2 == 0 && h->geo.n_angles % 2 == 0 && ka == 0 && kb == h->geo.n_angles;
+// All angles, or a subset whose angles come with their partners k +- n_a/2
+// (the paired partition).
+bool quad_ok(const mcr_handle* h, const AngleRanges& ar) {
+  const int na = h->geo.n_angles;
+  const bool all = ar.ka == 0 && ar.kb == na && ar.kd == ar.kc;
+  const bool paired = ar.kc == ar.ka + na / 2 && ar.kd == ar.kb + na / 2;
+  return h->geo.n % 2 == 0 && na % 2 == 0 && (all || paired);
 }
 
-void subset_range(const mcr_handle* h, int subset, int& ka, int& kb) {
-  if (subset < 0) {
-    ka = 0;
-    kb = h->geo.n_angles;
-  } else {
-    ka = h->sub_k[subset];
-    kb = h->sub_k[subset + 1];
-  }
+AngleRanges subset_ranges(const mcr_handle* h, int subset) {
+  if (subset < 0 || h->M == 1) return AngleRanges{0, h->geo.n_angles, 0, 0};
+  return h->sub[subset];
 }
 
 template <typename T>
@@ -878,7 +926,7 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
   // forward (angle subsets of less than all angles)
   const bool quad = std::is_same<T, float>::value && h->tune.fwd == 4 && h->quad_npieces > 0;
   T* wQ = quad ? w.wQ : nullptr;
-  T* wT = quad && h->M == 1 ? nullptr : w.wTP;
+  T* wT = quad && (h->M == 1 || (h->sub_paired && !h->quad_sub.empty())) ? nullptr : w.wTP;
   hipLaunchKernelGGL(k_warp_fwd<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate0,
                      h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, wT, h->padded, slots, wQ,
                      3 * h->padded, h->padded);
@@ -887,8 +935,8 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
 }
 
 // Angles of subset `subset` (-1: all angles).
-void subset_range(const mcr_handle* h, int subset, int& ka, int& kb);
-bool quad_ok(const mcr_handle* h, int ka, int kb);
+AngleRanges subset_ranges(const mcr_handle* h, int subset);
+bool quad_ok(const mcr_handle* h, const AngleRanges& ar);
 int quad_tiled_px(int code);
 
 template <typename T, int MODE>
@@ -896,25 +944,31 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
                           const SlotInfo* slots = nullptr, int subset = -1) {
   Work<T>& w = work<T>(h);
   Timed tm(h, MCR_KERNEL_PROJECT);
-  int ka, kb;
-  subset_range(h, subset, ka, kb);
+  const AngleRanges ar = subset_ranges(h, subset);
   const GateScalars<T>* gs = w.scalars + w.sc_base;
-  dim3 grid(cdiv(h->geo.n_det, 256), kb - ka, G), block(256);
+  const dim3 block(256);
   if constexpr (std::is_same<T, float>::value) {
-    // the chunk tables of variants 1, 2 and 4 cover all angles
-    const bool part = ka > 0 || kb < h->geo.n_angles;
-    const int fwd = (part && h->tune.fwd != 0 && h->tune.fwd != 3) ? (h->shear_npieces > 0 ? 3 : 0) : h->tune.fwd;
+    // the chunk tables of variants 1 and 2 cover all angles; those of variant
+    // 4 all angles or each paired subset
+    const bool part = subset >= 0 && h->M > 1;
+    int fwd = h->tune.fwd;
+    if (part && !(fwd == 0 || fwd == 3 || (fwd == 4 && h->sub_paired && !h->quad_sub.empty())))
+      fwd = h->shear_npieces > 0 ? 3 : 0;
     if (fwd == 4 && h->quad_npieces > 0) {
       const long qp = h->quad_part_floats;
-      hipLaunchKernelGGL((k_joseph_fwd_quad<MODE>), dim3(h->quad_npieces, 1, G), dim3(256), 0, h->stream,
-                         geo_of<T>(h), w.angfx, h->quad_chunks, h->quad_pieces, h->quad_units, h->quad_bands, w.wP,
-                         w.wQ, h->padded, 3 * h->padded, h->padded, out, out_stride, gate0, gs, w.ptrs, slots,
-                         h->quad_part, qp, 0);
-      LAUNCH_OK();
-      if (h->quad_nmulti > 0) {
-        hipLaunchKernelGGL((k_joseph_fwd_quad_finish<MODE>), dim3(h->quad_nmulti, 4, G), dim3(256), 0, h->stream,
+      const int2 pr = part ? h->quad_sub[subset] : make_int2(0, h->quad_npieces);
+      const int2 mr = part ? h->quad_sub_multi[subset] : make_int2(0, h->quad_nmulti);
+      if (pr.y > 0) {
+        hipLaunchKernelGGL((k_joseph_fwd_quad<MODE>), dim3(pr.y, 1, G), dim3(256), 0, h->stream, geo_of<T>(h),
+                           w.angfx, h->quad_chunks, h->quad_pieces, h->quad_units, h->quad_bands, w.wP, w.wQ,
+                           h->padded, 3 * h->padded, h->padded, out, out_stride, gate0, gs, w.ptrs, slots,
+                           h->quad_part, qp, pr.x);
+        LAUNCH_OK();
+      }
+      if (mr.y > 0) {
+        hipLaunchKernelGGL((k_joseph_fwd_quad_finish<MODE>), dim3(mr.y, 4, G), dim3(256), 0, h->stream,
                            geo_of<T>(h), w.angfx, h->quad_chunks, h->quad_units, h->quad_multi, h->quad_part, qp,
-                           out, out_stride, gate0, gs, w.ptrs, slots, 0);
+                           out, out_stride, gate0, gs, w.ptrs, slots, mr.x);
       }
     } else if (fwd == 3 && h->shear_npieces > 0) {
       const int2 pr = subset >= 0 ? h->shear_sub[subset] : make_int2(0, h->shear_npieces);
@@ -942,12 +996,24 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
                          geo_of<T>(h), w.angfx, h->chunks, w.wP, w.wTP, h->padded, out, out_stride, gate0, gs,
                          w.ptrs, slots);
     } else {
-      hipLaunchKernelGGL((k_joseph_fwd_fx<MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.angfx, w.wP,
-                         w.wTP, h->padded, out, out_stride, gate0, gs, w.ptrs, slots, ka);
+      for (int part_r = 0; part_r < 2; ++part_r) {  // one launch per angle range
+        const int k0 = part_r ? ar.kc : ar.ka, cnt = part_r ? ar.kd - ar.kc : ar.kb - ar.ka;
+        if (cnt <= 0) continue;
+        hipLaunchKernelGGL((k_joseph_fwd_fx<MODE>), dim3(cdiv(h->geo.n_det, 256), cnt, G), block, 0, h->stream,
+                           geo_of<T>(h), w.angfx, w.wP, w.wTP, h->padded, out, out_stride, gate0, gs, w.ptrs, slots,
+                           k0);
+        LAUNCH_OK();
+      }
     }
-  } else
-    hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), grid, block, 0, h->stream, geo_of<T>(h), w.ang, w.wP,
-                       w.wTP, h->padded, out, out_stride, gate0, gs, w.ptrs, slots, ka);
+  } else {
+    for (int part_r = 0; part_r < 2; ++part_r) {
+      const int k0 = part_r ? ar.kc : ar.ka, cnt = part_r ? ar.kd - ar.kc : ar.kb - ar.ka;
+      if (cnt <= 0) continue;
+      hipLaunchKernelGGL((k_joseph_fwd<T, MODE>), dim3(cdiv(h->geo.n_det, 256), cnt, G), block, 0, h->stream,
+                         geo_of<T>(h), w.ang, w.wP, w.wTP, h->padded, out, out_stride, gate0, gs, w.ptrs, slots, k0);
+      LAUNCH_OK();
+    }
+  }
   LAUNCH_OK();
   return MCR_OK;
 }
@@ -971,14 +1037,14 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
   Work<T>& w = work<T>(h);
   const int n = h->geo.n;
   Timed tm(h, MCR_KERNEL_BACKPROJECT);
-  int ka, kb;
-  subset_range(h, subset, ka, kb);
+  const AngleRanges ar = subset_ranges(h, subset);
   dim3 grid(cdiv(n, 16), cdiv(n, 16), G), block(16, 16);
   if constexpr (std::is_same<T, float>::value) {
     // adj_px < 0: the quarter-turn kernel where the geometry allows it (even
-    // n and n_angles, all angles), else the tiled kernel (quad_tiled_px)
+    // n and n_angles, all angles or a paired subset), else the tiled kernel
+    // (quad_tiled_px)
     const int code = h->tune.adj_px;
-    const bool quad = code < 0 && quad_ok(h, ka, kb);
+    const bool quad = code < 0 && quad_ok(h, ar);
     const int px = code < 0 ? quad_tiled_px(code) : code, S = px > 0 ? h->tune.adj_s : 1;
     if (quad) {
       const long n2 = (long)n * n;
@@ -988,7 +1054,7 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
 #define ADJQ(PX, TX, TY)                                                                                          \
   hipLaunchKernelGGL((k_joseph_adj_quad<PX, TX, TY>), dim3(cdiv(n / 2, TX * PX), cdiv(n / 2, TY), G * S),         \
                      dim3(TX * TY), 0, h->stream, geo_of<T>(h), w.angfx, sino, sino_stride, dst, dst_stride, padded, \
-                     S, part_stride)
+                     S, part_stride, ar)
       if (code == -2)
         ADJQ(2, 8, 32);
       else if (code == -4)
@@ -1013,7 +1079,7 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
       dim3 gt(cdiv(n, 8 * px), cdiv(n, 32), G * S);
 #define ADJ(PX)                                                                                           \
   hipLaunchKernelGGL(k_joseph_adj_lds<PX>, gt, dim3(256), 0, h->stream, geo_of<T>(h), w.angfx, sino, \
-                     sino_stride, dst, dst_stride, padded, S, part_stride, ka, kb)
+                     sino_stride, dst, dst_stride, padded, S, part_stride, ar)
       if (px == 1)
         ADJ(1);
       else if (px == 2)
@@ -1029,11 +1095,11 @@ mcr_status launch_backproject(mcr_handle* h, int G, const T* sino, long sino_str
       }
     } else {
       hipLaunchKernelGGL(k_joseph_adj_fx, grid, block, 0, h->stream, geo_of<T>(h), w.angfx, sino,
-                         sino_stride, out, out_stride, padded, ka, kb);
+                         sino_stride, out, out_stride, padded, ar);
     }
   } else
     hipLaunchKernelGGL(k_joseph_adj<T>, grid, block, 0, h->stream, geo_of<T>(h), w.ang, sino,
-                       sino_stride, out, out_stride, padded, ka, kb);
+                       sino_stride, out, out_stride, padded, ar);
   LAUNCH_OK();
   return MCR_OK;
 }
@@ -1796,8 +1862,8 @@ mcr_status gap_impl(mcr_handle* h, const mcr_state* st, const void* const* d, do
 namespace {
 
 // One SPDHG epoch of every slice of a batch: step (i) for all slices, then for
-// each step t the four phases over the slices still iterating (one launch
-// each, block z = slot). Kernels read gates, slices and per-slice scalars from
+// each round t the four phases over the round's slots (one launch each, block
+// z = slot; a slot is one iteration of one slice). Kernels read gates, slices and per-slice scalars from
 // device tables, so the launch sequence does not depend on the gate draws and
 // can be replayed as a graph.
 template <typename T>
@@ -1853,10 +1919,9 @@ mcr_status batch_epoch_impl(mcr_handle* h, void* x, void* z, void* zbar, void* y
   SlotInfo* hs = (SlotInfo*)B.pin;
   for (int t = 0; t < B.tmax; ++t) {
     int c = 0;
-    for (int s = 0; s < S; ++s) {
-      if (B.ng[s] <= t) continue;
-      hs[(long)t * S + c] = SlotInfo{s, B.off[s] + seq[B.off[s] + t], t + 1 < B.ng[s] ? 1 : 0, 0};
-      ++c;
+    for (int q = B.round_off[t]; q < B.round_off[t + 1]; ++q, ++c) {
+      const int s = B.items[q].x, j = B.items[q].y;
+      hs[(long)t * S + c] = SlotInfo{s, B.off[s] + seq[B.off[s] + j], j + 1 < B.ng[s] ? 1 : 0, 0};
     }
     for (; c < S; ++c) hs[(long)t * S + c] = SlotInfo{0, 0, 0, 0};
   }
@@ -1871,11 +1936,10 @@ mcr_status batch_epoch_impl(mcr_handle* h, void* x, void* z, void* zbar, void* y
   B.pin_recorded = true;
   if (!use_graph) return batch_launches<T>(h, (T*)x, (T*)z, (T*)zbar);
   // graph: captured once per (x, z, zbar) and handle configuration (variants,
-  // window radii), replayed on the batch stream after the uploads above (event
-  // ordering keeps the caller's stream semantics)
+  // window radii) on the batch stream, replayed on the handle's stream
   if (!B.exec || B.key[0] != x || B.key[1] != z || B.key[2] != zbar || B.gen != h->config_gen) {
     if (B.exec) {
-      HIP_OK(hipStreamSynchronize(B.gstream));  // the previous replay may still run
+      HIP_OK(hipStreamSynchronize(h->stream));  // the previous replay may still run
       (void)hipGraphExecDestroy(B.exec);
       B.exec = nullptr;
     }
@@ -1905,14 +1969,12 @@ mcr_status batch_epoch_impl(mcr_handle* h, void* x, void* z, void* zbar, void* y
     B.key[2] = zbar;
     B.gen = h->config_gen;
   }
-  HIP_OK(hipEventRecord(B.ev_in, h->stream));
-  HIP_OK(hipStreamWaitEvent(B.gstream, B.ev_in, 0));
+  // the replay itself goes on the handle's stream (a graph can be launched
+  // on the null stream, only captured off it), after the table uploads
   {
     Timed tm(h, MCR_KERNEL_OTHER);
-    HIP_OK(hipGraphLaunch(B.exec, B.gstream));
+    HIP_OK(hipGraphLaunch(B.exec, h->stream));
   }
-  HIP_OK(hipEventRecord(B.ev_out, B.gstream));
-  HIP_OK(hipStreamWaitEvent(h->stream, B.ev_out, 0));
   return MCR_OK;
 }
 
@@ -1991,7 +2053,7 @@ mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_moti
   h->sino = (long)geom->n_angles * geom->n_det;
   h->motion.assign(motion, motion + n_gates);
   h->radius.assign(n_gates, 1);
-  h->sub_k = {0, geom->n_angles};
+  h->sub = {AngleRanges{0, geom->n_angles, 0, 0}};
   for (auto& m : h->motion) {
     if (m.kind == MCR_MOTION_FIELD) h->any_field = true;
   }
@@ -2063,8 +2125,6 @@ mcr_status mcr_destroy(mcr_handle* h) {
   if (h->batch.graph) (void)hipGraphDestroy(h->batch.graph);
   if (h->batch.pin) (void)hipHostFree(h->batch.pin);
   if (h->batch.pin_ev) (void)hipEventDestroy(h->batch.pin_ev);
-  if (h->batch.ev_in) (void)hipEventDestroy(h->batch.ev_in);
-  if (h->batch.ev_out) (void)hipEventDestroy(h->batch.ev_out);
   if (h->batch.gstream) (void)hipStreamDestroy(h->batch.gstream);
   delete h;
   return MCR_OK;
@@ -2460,21 +2520,42 @@ mcr_status mcr_block_norm_sq(mcr_handle* h, int32_t gate, int32_t subset, const 
   return power_norm_impl(h, gate, subset, v0, max_iter, rtol, out, iters);
 }
 
-mcr_status mcr_set_subsets(mcr_handle* h, int32_t n_subsets) {
+mcr_status mcr_set_subset_partition(mcr_handle* h, int32_t n_subsets, int32_t paired) {
   STATUS_OK(check_handle(h));
-  if (n_subsets < 1 || n_subsets > h->geo.n_angles)
-    return fail(MCR_ERR_ARG, "n_subsets = %d must be in [1, %d]", n_subsets, h->geo.n_angles);
+  const int na = h->geo.n_angles;
+  if (paired && na % 2) return fail(MCR_ERR_ARG, "paired subsets need an even number of angles (n_angles = %d)", na);
+  const int cap = paired ? na / 2 : na;
+  if (n_subsets < 1 || n_subsets > cap)
+    return fail(MCR_ERR_ARG, "n_subsets = %d must be in [1, %d]", n_subsets, cap);
   if (h->nslots < h->N) return fail(MCR_ERR_STATE, "angle subsets are not available on a batch handle");
-  if (n_subsets == h->M) return MCR_OK;
+  const bool pd = paired != 0 && n_subsets > 1;
+  if (n_subsets == h->M && pd == h->sub_paired) return MCR_OK;
   HIP_OK(hipStreamSynchronize(h->stream));
   h->M = n_subsets;
-  h->sub_k.resize(n_subsets + 1);
-  for (int s = 0; s <= n_subsets; ++s) h->sub_k[s] = (int)((long)s * h->geo.n_angles / n_subsets);
+  h->sub_paired = pd;
+  h->sub.resize(n_subsets);
+  const int H = na / 2;
+  for (int s = 0; s < n_subsets; ++s) {
+    if (pd) {
+      const int a = (int)((long)s * H / n_subsets), b = (int)((long)(s + 1) * H / n_subsets);
+      h->sub[s] = AngleRanges{a, b, a + H, b + H};
+    } else {
+      h->sub[s] = AngleRanges{(int)((long)s * na / n_subsets), (int)((long)(s + 1) * na / n_subsets), 0, 0};
+    }
+  }
   STATUS_OK(ensure_scalars<float>(h));
   STATUS_OK(ensure_scalars<double>(h));
-  if (h->wf.ready)
-    STATUS_OK(upload_shear(h, angle_table_fx(h->geo.n, h->geo.n_angles, h->geo.n_det)));
+  if (h->wf.ready) {
+    const std::vector<AngleFx> af = angle_table_fx(h->geo.n, na, h->geo.n_det);
+    STATUS_OK(upload_shear(h, af));
+    STATUS_OK(upload_quad(h, af));
+  }
+  ++h->config_gen;
   return MCR_OK;
+}
+
+mcr_status mcr_set_subsets(mcr_handle* h, int32_t n_subsets) {
+  return mcr_set_subset_partition(h, n_subsets, 0);
 }
 
 mcr_status mcr_spdhg_blocks_iterate(mcr_handle* h, const mcr_state* st, const void* const* d, double alpha,
@@ -2661,13 +2742,24 @@ mcr_status mcr_batch_create(const mcr_geometry* geom, int32_t n_slices, const in
   B.ng.assign(gates_per_slice, gates_per_slice + n_slices);
   B.off.resize(n_slices);
   for (int s = 0, o = 0; s < n_slices; o += B.ng[s], ++s) B.off[s] = o;
+  // rounds: an epoch takes tmax rounds (the longest slice's iterations);
+  // slice s runs its iteration j in round floor(j tmax / N_s), so a slice's
+  // iterations keep their order and every round holds about sum N_s / tmax
+  // slots instead of all slices at the start and the longest ones alone at
+  // the end
   B.tmax = tmax;
-  B.nact.resize(tmax);
+  B.nact.assign(tmax, 0);
+  std::vector<std::vector<int2>> per_round(tmax);
+  for (int s = 0; s < n_slices; ++s)
+    for (int j = 0; j < B.ng[s]; ++j) per_round[(long)j * tmax / B.ng[s]].push_back(make_int2(s, j));
+  B.items.clear();
+  B.round_off.assign(tmax + 1, 0);
   for (int t = 0; t < tmax; ++t) {
-    int c = 0;
-    for (int s = 0; s < n_slices; ++s) c += B.ng[s] > t;
-    B.nact[t] = c;
+    B.round_off[t] = (int)B.items.size();
+    B.nact[t] = (int)per_round[t].size();
+    B.items.insert(B.items.end(), per_round[t].begin(), per_round[t].end());
   }
+  B.round_off[tmax] = (int)B.items.size();
   const size_t esz = dtype == MCR_F32 ? sizeof(float) : sizeof(double);
   const size_t slot_bytes = sizeof(SlotInfo) * (size_t)tmax * n_slices;
   mcr_status st = dmalloc(h, (void**)&B.slots, slot_bytes);
@@ -2676,8 +2768,6 @@ mcr_status mcr_batch_create(const mcr_geometry* geom, int32_t n_slices, const in
   if (st == MCR_OK && hipHostMalloc(&B.pin, B.pin_bytes, hipHostMallocDefault) != hipSuccess)
     st = fail(MCR_ERR_NOMEM, "pinned allocation failed");
   if (st == MCR_OK && (hipEventCreateWithFlags(&B.pin_ev, hipEventDisableTiming) != hipSuccess ||
-                       hipEventCreateWithFlags(&B.ev_in, hipEventDisableTiming) != hipSuccess ||
-                       hipEventCreateWithFlags(&B.ev_out, hipEventDisableTiming) != hipSuccess ||
                        hipStreamCreateWithFlags(&B.gstream, hipStreamNonBlocking) != hipSuccess))
     st = fail(MCR_ERR_HIP, "could not create the batch stream and events");
   if (st == MCR_OK && hipStreamSynchronize(h->stream) != hipSuccess) st = fail(MCR_ERR_HIP, "batch set-up failed");

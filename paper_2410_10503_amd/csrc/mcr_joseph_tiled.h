@@ -733,14 +733,14 @@ constexpr int adj_window() {
   return PX == 8 ? 80 : 64;
 }
 
-// grid (ceil(n/(8*PX)), ceil(n/32), G*S), block 256; angles [ka, kb). With S > 1 block z
+// grid (ceil(n/(8*PX)), ceil(n/32), G*S), block 256; the angles of `ar`. With S > 1 block z
 // handles angle share z % S of gate slot z / S and writes an unpadded partial
 // image to out + (z % S) * part_stride + (z / S) * out_stride (summed later).
 template <int PX>
 __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const AngleFx* __restrict__ ang,
                                                         const float* __restrict__ sino, long sino_stride,
                                                         float* __restrict__ out, long out_stride,
-                                                        int padded, int S, long part_stride, int ka, int kb) {
+                                                        int padded, int S, long part_stride, AngleRanges ar) {
   constexpr int kAdjW = adj_window<PX>();
   constexpr int kAdjUnroll = PX >= 8 ? 1 : 2;  // angles per unrolled step (registers)
   __shared__ float sy[kAdjKC * kAdjW];
@@ -759,7 +759,14 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
   const int share = L % S, rest = L / S;
   const int tiles = gridDim.x * gridDim.y, tile = rest % tiles, slot = rest / tiles;
   const int R0 = (tile / gridDim.x) * 32, C0 = (tile % gridDim.x) * (8 * PX);
-  const int kbeg = ka + (int)((long)(kb - ka) * share / S), kend = ka + (int)((long)(kb - ka) * (share + 1) / S);
+  // the share's angles: launch angles [vbeg, vend) in the order of `ar`,
+  // staged in chunks of consecutive angles that end where a range ends
+  const int V = ar.count();
+  const int vbeg = (int)((long)V * share / S), vend = (int)((long)V * (share + 1) / S);
+  auto chunk = [&](int v, int& k0, int& kcn) {
+    k0 = ar.at(v);
+    kcn = min(min(kAdjKC, vend - v), ar.run(v));
+  };
   const float* s = sino + slot * sino_stride;
   const int nd = g.nd;
   float acc[PX], blk[PX];
@@ -798,18 +805,21 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
   // flight while the current chunk is computed)
   int jb = 0;
   float ds = 0.0f;
-  window(kbeg, min(kAdjKC, kend - kbeg), jb, ds);
+  int k0 = 0, kcn = 0;
+  if (vbeg < vend) chunk(vbeg, k0, kcn);
+  window(k0, kcn, jb, ds);
   if (tid < kAdjKC) {
     s_jb[0][tid] = jb;
     s_ds[0][tid] = ds;
   }
   __syncthreads();
-  if (kbeg < kend) fetch(kbeg, min(kAdjKC, kend - kbeg), s_jb[0]);
+  if (vbeg < vend) fetch(k0, kcn, s_jb[0]);
   int cur = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += kAdjKC, cur ^= 1) {
-    const int kcn = min(kAdjKC, kend - k0);
-    const int k1 = k0 + kAdjKC;
-    const int kcn1 = min(kAdjKC, kend - k1);
+  for (int v0 = vbeg; v0 < vend; v0 += kcn, cur ^= 1) {
+    chunk(v0, k0, kcn);
+    const int v1 = v0 + kcn;
+    int k1 = 0, kcn1 = 0;
+    if (v1 < vend) chunk(v1, k1, kcn1);
     // stage the fetched bins, pre-scaled by the ray length per line
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
@@ -836,7 +846,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
         }
       }
     }
-    if (k1 < kend) {
+    if (v1 < vend) {
       window(k1, kcn1, jb, ds);
       if (tid < kAdjKC) {
         s_jb[cur ^ 1][tid] = jb;
@@ -844,7 +854,7 @@ __global__ __launch_bounds__(256) void k_joseph_adj_lds(Geo<float> g, const Angl
       }
     }
     __syncthreads();
-    if (k1 < kend) fetch(k1, kcn1, s_jb[cur ^ 1]);
+    if (v1 < vend) fetch(k1, kcn1, s_jb[cur ^ 1]);
 #pragma unroll kAdjUnroll
     for (int kc = 0; kc < kcn; ++kc) {
       const float4 wc = s_w[kc];
@@ -934,7 +944,7 @@ template <int PX, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const AngleFx* __restrict__ ang,
                                                              const float* __restrict__ sino, long sino_stride,
                                                              float* __restrict__ out, long out_stride, int padded,
-                                                             int S, long part_stride) {
+                                                             int S, long part_stride, AngleRanges ar) {
   constexpr int NT = TX * TY;
   constexpr int kW = quad_window<PX, TX, TY>();
   constexpr int KC = kQuadKC;
@@ -954,7 +964,15 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
   const int tiles = gridDim.x * gridDim.y, tile = rest % tiles, slot = rest / tiles;
   const int R0 = (tile / gridDim.x) * TY, C0 = (tile % gridDim.x) * (TX * PX);
   const int na = g.na, H = na >> 1, nd = g.nd;
-  const int kbeg = (int)((long)na * share / S), kend = (int)((long)na * (share + 1) / S);
+  // the share's angles: launch angles [vbeg, vend) in the order of `ar`
+  // (all angles, or an angle subset closed under k <-> k +- n_angles/2),
+  // staged in chunks of consecutive angles that end where a range ends
+  const int V = ar.count();
+  const int vbeg = (int)((long)V * share / S), vend = (int)((long)V * (share + 1) / S);
+  auto chunk = [&](int v, int& k0, int& kcn) {
+    k0 = ar.at(v);
+    kcn = min(min(KC, vend - v), ar.run(v));
+  };
   const float* s = sino + slot * sino_stride;
   float acc[4][PX], blk[4][PX];
 #pragma unroll
@@ -1001,18 +1019,21 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
   };
   int jb = 0;
   float ds = 0.0f;
-  window(kbeg, min(KC, kend - kbeg), jb, ds);
+  int k0 = 0, kcn = 0;
+  if (vbeg < vend) chunk(vbeg, k0, kcn);
+  window(k0, kcn, jb, ds);
   if (tid < KC) {
     s_jb[0][tid] = jb;
     s_ds[0][tid] = ds;
   }
   __syncthreads();
-  if (kbeg < kend) fetch(kbeg, min(KC, kend - kbeg), s_jb[0]);
+  if (vbeg < vend) fetch(k0, kcn, s_jb[0]);
   int cur = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += KC, cur ^= 1) {
-    const int kcn = min(KC, kend - k0);
-    const int k1 = k0 + KC;
-    const int kcn1 = min(KC, kend - k1);
+  for (int v0 = vbeg; v0 < vend; v0 += kcn, cur ^= 1) {
+    chunk(v0, k0, kcn);
+    const int v1 = v0 + kcn;
+    int k1 = 0, kcn1 = 0;
+    if (v1 < vend) chunk(v1, k1, kcn1);
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int i = tid + e * NT;
@@ -1040,7 +1061,7 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
         }
       }
     }
-    if (k1 < kend) {
+    if (v1 < vend) {
       window(k1, kcn1, jb, ds);
       if (tid < KC) {
         s_jb[cur ^ 1][tid] = jb;
@@ -1048,7 +1069,7 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
       }
     }
     __syncthreads();
-    if (k1 < kend) fetch(k1, kcn1, s_jb[cur ^ 1]);
+    if (v1 < vend) fetch(k1, kcn1, s_jb[cur ^ 1]);
 #pragma unroll 2
     for (int kc = 0; kc < kcn; ++kc) {
       const float4 wc = s_w[kc];

@@ -72,6 +72,19 @@ struct GateMotion {
   T bx, by;               // hc + t (window centres only)
 };
 
+// Angles a launch covers: [ka, kb) and [kc, kd) (the second range may be
+// empty). An angle subset of the gates x angle-subsets sampling is one or two
+// such ranges (a contiguous range, or a range and its partner range a
+// quarter turn away).
+struct AngleRanges {
+  int ka, kb, kc, kd;
+  __host__ __device__ int count() const { return (kb - ka) + (kd - kc); }
+  // the v-th angle of the launch, v in [0, count())
+  __host__ __device__ int at(int v) const { return v < kb - ka ? ka + v : kc + (v - (kb - ka)); }
+  // angles from the v-th one to the end of its range
+  __host__ __device__ int run(int v) const { return v < kb - ka ? kb - ka - v : count() - v; }
+};
+
 // Per-gate scalars of one call of Algorithm 1.
 template <typename T>
 struct GateScalars {
@@ -360,7 +373,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* __restrict__ ang,
                                                     const T* __restrict__ sino, long sino_stride,
                                                     T* __restrict__ out, long out_stride,
-                                                    int padded, int ka, int kb) {
+                                                    int padded, AngleRanges ar) {
   const int c = blockIdx.x * 16 + threadIdx.x;
   const int r = blockIdx.y * 16 + threadIdx.y;
   if (c >= g.n || r >= g.n) return;
@@ -369,7 +382,8 @@ __global__ __launch_bounds__(256) void k_joseph_adj(Geo<T> g, const AngleT<T>* _
   const T fc = T(c), fr = T(r);
   const int nd = g.nd;
   T acc = T(0), blk = T(0);
-  for (int k = ka; k < kb; ++k) {
+  for (int part = 0; part < 2; ++part)
+  for (int k = part ? ar.kc : ar.ka; k < (part ? ar.kd : ar.kb); ++k) {
     if ((k & (kLineBlock - 1)) == 0) {  // two-level sum over angles
       acc += blk;
       blk = T(0);
@@ -514,14 +528,15 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_fx(Geo<float> g, const Angle
 __global__ __launch_bounds__(256) void k_joseph_adj_fx(Geo<float> g, const AngleFx* __restrict__ ang,
                                                        const float* __restrict__ sino, long sino_stride,
                                                        float* __restrict__ out, long out_stride, int padded,
-                                                       int ka, int kb) {
+                                                       AngleRanges ar) {
   const int c = blockIdx.x * 16 + threadIdx.x;
   const int r = blockIdx.y * 16 + threadIdx.y;
   if (c >= g.n || r >= g.n) return;
   const float* s = sino + blockIdx.z * sino_stride;
   const int nd = g.nd;
   float acc = 0.0f, blk = 0.0f;
-  for (int k = ka; k < kb; ++k) {
+  for (int part = 0; part < 2; ++part)
+  for (int k = part ? ar.kc : ar.ka; k < (part ? ar.kd : ar.kb); ++k) {
     if ((k & (kLineBlock - 1)) == 0) {
       acc += blk;
       blk = 0.0f;

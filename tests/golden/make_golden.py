@@ -1,8 +1,8 @@
 """Writes tests/golden/paper_constants.json.
 
-The problem constants are the paper's (each entry cites where); the derived
-per-epoch rates are computed by the oracle's l(kappa, n) (Section II-B) and
-nothing else.  Run from the repository root: python tests/golden/make_golden.py
+The problem constants are the paper's (each entry cites where); nothing in
+the file is computed. Run from the repository root:
+python tests/golden/make_golden.py
 """
 import json
 import os
@@ -10,8 +10,6 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
-
-from oracle import spdhg  # noqa: E402
 
 
 def main():
@@ -25,12 +23,6 @@ def main():
         "norm_approximations": {"max_gate_vs_A": 0.03, "stacked_vs_N_A": 0.08,
                                 "cite": "Section II-B, after Theorem 1"},
         "comparison_epoch": {"value": 30, "cite": "Section III, Results; Figs. 2 and 3 (e), (f)"},
-        "derived_rates": {
-            "pdhg": round(spdhg.rate(kappa, 1), 6),
-            "spdhg_N20": round(spdhg.rate(kappa / 20, 20), 6),
-            "spdhg_N10": round(spdhg.rate(kappa / 10, 10), 6),
-            "how": "l(kappa, 1) and l(kappa / N, N), Section II-B with Theorem 1's approximations",
-        },
     }
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_constants.json")
     with open(path, "w") as f:

@@ -36,3 +36,20 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, cwd=ROOT, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_cpu_baseline_legs_on_a_small_workload():
+    # the oracle timed on one core (operators, one iteration) and on all
+    # cores (one iteration per worker process), on the 128^2 workload
+    r = bench.cpu_baseline("ellipses128_rigid4")
+    assert r["kind"] == "oracle" and r["cores"] == r["all_cores"]["workers"] >= 1
+    one = r["one_core"]
+    assert one["s_apply_Ai"] > 0 and one["s_apply_Ai_adjoint"] > 0 and one["s_per_iteration"] > 0
+    assert r["value"] == r["all_cores"]["epochs_per_s"] > 0
+
+
+def test_measured_roofs_reads_the_committed_probe_summary():
+    roofs = bench.measured_roofs()
+    if roofs is None:
+        pytest.skip("no probe summary committed")
+    assert roofs["lds_read_tbs"] > 0 and roofs["copy_gbs"] > 0

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import F32_OP, Problem, dev, f32, host, need_gpu, rel
+from gpu_common import F32_EPOCHS, F32_OP, Problem, dev, f32, host, need_gpu, rel, rel_max
 import synth
 from oracle import spdhg as osp
 
@@ -110,6 +110,63 @@ def test_batch_against_oracle():
     for i, P in enumerate(probs):
         assert rel(host(st["x"][i]), refs[i].x) < F32_OP * 10
         assert rel(host(st["zbar"][i]), refs[i].zbar) < F32_OP * 10
+
+
+@pytest.mark.parametrize("dtype,bar", [(torch.float32, F32_EPOCHS), (torch.float64, 1e-10)])
+def test_batch_slices_against_oracle_five_epochs(dtype, bar):
+    # four slices of the batched workload (256^2, 360 x 366; 32, 6, 12 and 20
+    # gates, field and rigid) in one batch handle, 5 epochs, after each epoch
+    # x, z-bar and sampled duals of every slice against the FP64 oracle's
+    # stored iterates (tests/golden/make_fullsize.py, case c4_batch)
+    import golden_fullsize as gf
+    from paper_2410_10503_amd import BatchHandle
+    arrays, meta = gf.load("c4_batch")
+    n, na, nd, alpha = meta["n"], meta["n_angles"], meta["n_det"], meta["alpha"]
+    want = [m["index"] for m in meta["slices"]]
+    slices = sorted((sl for sl in synth.batched_slices() if sl.index in want), key=lambda sl: want.index(sl.index))
+    motion, d_all, ngs = [], [], []
+    for sl in slices:
+        if sl.motion == "rigid":
+            motion += [("rigid", tuple(float(v) for v in r)) for r in sl.rigid()]
+        else:
+            f = torch.from_numpy(sl.fields(n)).cuda()
+            motion += [("field", f[i].contiguous()) for i in range(sl.n_gates)]
+        dd, how = gf.slice_data(sl, n, na, nd, [str(v) for v in arrays[f"s{sl.index}_d_sha256"]])
+        print(f"slice {sl.index}: data {how}", flush=True)
+        d_all += dd
+        ngs.append(sl.n_gates)
+    bh = BatchHandle(n, na, nd, ngs, motion, dtype=dtype)
+    if dtype == torch.float32:
+        bh.autotune(max(1, round(sum(ngs) / max(ngs))))
+    d = torch.stack([dev(v, dtype) for v in d_all]).contiguous()
+    sig, tau, th, p = [], [], [], []
+    for m in meta["slices"]:
+        sig += m["sigma"]
+        p += m["p"]
+        tau.append(m["tau"])
+        th.append(m["theta"])
+    st = bh.zero_batch_state()
+    for e in range(meta["epochs"]):
+        seq = [int(g) for sl in slices for g in synth.gate_sequence(sl.n_gates, sl.gate_seed, e)]
+        bh.batch_spdhg_epoch(st, d, [alpha] * len(slices), sig, tau, th, p, seq, use_graph=True)
+        torch.cuda.synchronize()
+        for i, sl in enumerate(slices):
+            key = f"s{sl.index}_e{e + 1}_"
+            o = bh.offsets[i]
+            idx = arrays[f"s{sl.index}_y_index"]
+            pix = arrays[f"s{sl.index}_pixel_index"]
+            ys = np.stack([host(st["y"][o + k]).ravel()[idx[k]] for k in range(sl.n_gates)])
+            xs, zs = host(st["x"][i]), host(st["zbar"][i])
+            if key + "x" in arrays:      # in full after the last epoch, sampled pixels before
+                pairs = (("x", xs), ("zbar", zs))
+            else:
+                pairs = (("x_sample", xs.ravel()[pix]), ("zbar_sample", zs.ravel()[pix]))
+            for name, got in pairs + (("y_sample", ys),):
+                ref = arrays[key + name]
+                a, b = rel(got, ref), rel_max(got, ref)
+                assert a < bar and b < bar, (dtype, e, sl.index, name, a, b)
+    print(f"{dtype}: batch of slices {want} within {bar:g} of the oracle after each of {meta['epochs']} epochs",
+          flush=True)
 
 
 def test_batched_workload_shape():

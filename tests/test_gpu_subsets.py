@@ -16,19 +16,19 @@ def _gpu():
     need_gpu()
 
 
-def _blocks_setup(P, M, norm=None):
-    bops = osub.BlockOperators(P.ops, M)
+def _blocks_setup(P, M, norm=None, partition="contiguous"):
+    bops = osub.BlockOperators(P.ops, M, partition)
     nb = bops.n_blocks
     norms = [norm or 2.0 * P.na * P.n / M] * nb
     sig, tau, th, _ = osub.step_sizes(norms, P.alpha, P.N)
     return bops, sig, tau, th, [1.0 / nb] * nb
 
 
-def _run_gpu(P, M, dtype, sig, tau, th, p, seqs, variant=None):
+def _run_gpu(P, M, dtype, sig, tau, th, p, seqs, variant=None, partition="contiguous"):
     h = P.handle(dtype)
     if variant is not None:
         h.set_variant(*variant)
-    h.set_subsets(M)
+    h.set_subsets(M, paired=partition == "paired")
     d = [dev(v, dtype) for v in P.d]
     st = h.zero_state()
     for sq in seqs:
@@ -43,32 +43,38 @@ def _compare(st, ref, bar):
     assert rel(yg, np.concatenate([v.ravel() for v in ref.y])) < bar
 
 
+PARTITIONS = ["contiguous", "paired"]
+
+
+@pytest.mark.parametrize("partition", PARTITIONS)
 @pytest.mark.parametrize("kind,M", [("rigid", 3), ("field", 4)])
-def test_fp64_block_iterations_match_oracle(kind, M):
+def test_fp64_block_iterations_match_oracle(kind, M, partition):
     P = Problem(64, 96, 92, 3, kind, alpha=1e-3)
-    bops, sig, tau, th, p = _blocks_setup(P, M)
+    bops, sig, tau, th, p = _blocks_setup(P, M, partition=partition)
     nb = bops.n_blocks
     seqs = [synth.gate_sequence(nb, 3, e) for e in range(2)]
     ref = osp.State.zeros(64, P.N, 96, 92)
     for sq in seqs:
         ref = osub.spdhg_blocks(bops, ref, P.d, P.alpha, sig, tau, th, p, sq)
-    st = _run_gpu(P, M, torch.float64, sig, tau, th, p, seqs)
+    st = _run_gpu(P, M, torch.float64, sig, tau, th, p, seqs, partition=partition)
     _compare(st, ref, 1e-11)
 
 
 # (forward variant, adjoint pixels per thread, angle shares)
-@pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1), (4, -4, 8), (4, -32, 16)])
-def test_fp32_block_iterations_match_oracle(variant):
+@pytest.mark.parametrize("partition", PARTITIONS)
+@pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1), (4, -4, 8), (4, -32, 16),
+                                     (4, -4, 1), (0, -8, 3), (4, 8, 6)])
+def test_fp32_block_iterations_match_oracle(variant, partition):
     P = Problem(64, 96, 92, 4, "field", alpha=1e-3)
     M = 3
-    bops, sig, tau, th, p = _blocks_setup(P, M)
+    bops, sig, tau, th, p = _blocks_setup(P, M, partition=partition)
     nb = bops.n_blocks
     seqs = [synth.gate_sequence(nb, 5, e) for e in range(4)]
     ref = osp.State.zeros(64, P.N, 96, 92)
     for sq in seqs:
         ref = osub.spdhg_blocks(bops, ref, P.d, P.alpha, sig, tau, th, p, sq)
     try:
-        st = _run_gpu(P, M, torch.float32, sig, tau, th, p, seqs, variant)
+        st = _run_gpu(P, M, torch.float32, sig, tau, th, p, seqs, variant, partition)
     except Exception as e:  # a variant whose tables do not fit this geometry
         assert "do not fit" in str(e)
         return
@@ -92,13 +98,14 @@ def test_one_subset_block_iterations_equal_gate_iterations():
             assert torch.equal(u, v)
 
 
-def test_block_norms_match_oracle():
+@pytest.mark.parametrize("partition", PARTITIONS)
+def test_block_norms_match_oracle(partition):
     P = Problem(48, 60, 70, 2, "field", alpha=1e-3)
     M = 3
-    bops = osub.BlockOperators(P.ops, M)
+    bops = osub.BlockOperators(P.ops, M, partition)
     v0 = f32(synth.random_image(48, 9))
     h = P.handle(torch.float64)
-    h.set_subsets(M)
+    h.set_subsets(M, paired=partition == "paired")
     for b in range(bops.n_blocks):
         g, s = divmod(b, M)
         lam, _ = h.block_norm_sq(g, s, dev(v0, torch.float64), max_iter=400, rtol=1e-13)
@@ -106,15 +113,18 @@ def test_block_norms_match_oracle():
         assert abs(lam - lam_o) <= 1e-9 * lam_o
 
 
+@pytest.mark.parametrize("geom", [(75, 40, 300), (64, 96, 92)])
+@pytest.mark.parametrize("partition", PARTITIONS)
 @pytest.mark.parametrize("M", [2, 5])
-def test_full_range_operators_unchanged_by_subsets(M):
+def test_full_range_operators_unchanged_by_subsets(M, partition, geom):
     # the forward's work tables are rebuilt with subset boundaries; the full
     # operators stay within the parity bar
-    P = Problem(75, 40, 300, 2, "rigid")
-    x = f32(synth.ellipse_phantom(75, 3))
-    y = f32(synth.random_sinograms(1, 40, 300, 5)[0])
+    n, na, nd = geom
+    P = Problem(n, na, nd, 2, "rigid")
+    x = f32(synth.ellipse_phantom(n, 3))
+    y = f32(synth.random_sinograms(1, na, nd, 5)[0])
     h = P.handle(torch.float32)
-    h.set_subsets(M)
+    h.set_subsets(M, paired=partition == "paired")
     assert rel(host(h.apply_Ai(1, dev(x, torch.float32))), P.ops.A(1, x)) < F32_OP
     assert rel(host(h.apply_Ai_adjoint(1, dev(y, torch.float32))), P.ops.At(1, y)) < F32_OP
 
@@ -127,6 +137,10 @@ def test_subset_arguments():
         h.set_subsets(0)
     with pytest.raises(McrError):
         h.set_subsets(21)
+    with pytest.raises(McrError):
+        h.set_subsets(11, paired=True)   # 20 angles pair into at most 10 subsets
+    with pytest.raises(McrError):
+        Problem(32, 21, 46, 2, "rigid").handle(torch.float32).set_subsets(2, paired=True)  # odd angle count
     h.set_subsets(4)
     with pytest.raises(McrError):
         h.block_norm_sq(0, 4, torch.ones(32, 32, dtype=torch.float64, device="cuda"))
@@ -138,10 +152,12 @@ def test_subset_arguments():
         h.spdhg_blocks_iterate(st, d, P.alpha, [1.0] * 2, 1.0, 1.0, [0.5] * 2, [0])
 
 
-def test_full_size_block_iteration_sampled():
+@pytest.mark.parametrize("partition", PARTITIONS)
+def test_full_size_block_iteration_sampled(partition):
     # 512^2, 720 x 730, 16 field gates, 4 angle subsets: one block iteration per
     # subset from zero; the dual rows of the block against the oracle, and the
-    # rows of the other subsets untouched (still zero)
+    # rows of the other subsets untouched (still zero); the benchmark's
+    # variants (autotuned)
     wl = synth.WORKLOADS["chest512_field16"]
     P = Problem(512, 720, 730, 16, "field", phantom="chest", alpha=wl.alpha)
     M = 4
@@ -151,8 +167,9 @@ def test_full_size_block_iteration_sampled():
     p = [1.0 / nb] * nb
     dn = 50.0 * np.abs(synth.random_sinograms(2, 720, 730, 13, dtype=np.float64))
     h = P.handle(torch.float32)
-    h.set_subsets(M)
-    bops = osub.BlockOperators(P.ops, M)
+    h.autotune(1)
+    h.set_subsets(M, paired=partition == "paired")
+    bops = osub.BlockOperators(P.ops, M, partition)
     for b in [5, 3 * M + 2]:
         g, s = divmod(b, M)
         d = [dev(f32(dn[k % 2]), torch.float32) for k in range(16)]

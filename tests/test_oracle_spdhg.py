@@ -118,14 +118,16 @@ def test_rate_closed_forms_and_paper_claim():
 
 
 def test_paper_constants_fixture():
+    # Section III's printed problems (kappa ~ 70, 20 rigid and 10 non-rigid
+    # gates) satisfy Section II-B's condition kappa >= 10, so with Theorem 1's
+    # approximations |A_i| ~ |A| and |(A_1..A_N)|^2 ~ N |A|^2 the SPDHG epoch
+    # rate l(kappa / N, N) is below PDHG's l(kappa, 1) for both
     with open(os.path.join(GOLDEN, "paper_constants.json")) as f:
         g = json.load(f)
     k = g["kappa"]["value"]
-    r = g["derived_rates"]
-    assert abs(spdhg.rate(k, 1) - r["pdhg"]) < 5e-5
-    assert abs(spdhg.rate(k / 20, 20) - r["spdhg_N20"]) < 5e-5
-    assert abs(spdhg.rate(k / 10, 10) - r["spdhg_N10"]) < 5e-5
-    assert r["spdhg_N20"] < r["pdhg"] and r["spdhg_N10"] < r["pdhg"]
+    assert k >= 10
+    for N in (g["gates"]["rigid"], g["gates"]["nonrigid"]):
+        assert spdhg.rate(k / N, N) < spdhg.rate(k, 1)
 
 
 def _iteration_matrices(mats, alpha, sigma, tau, theta, p, S_list):

@@ -15,11 +15,14 @@ from oracle.operators import GatedOperators
 import synth
 
 
-def small(n=16, na=18, nd=24, N=3, M=3, alpha=5.0, seed=0):
+PARTITIONS = ["contiguous", "paired"]
+
+
+def small(n=16, na=18, nd=24, N=3, M=3, alpha=5.0, seed=0, partition="contiguous"):
     ops = GatedOperators(n, na, nd, "rigid", synth.rigid_params(N, seed + 1, 6.0, 2.0))
     x_true = synth.ellipse_phantom(n, seed).astype(np.float64)
     d = spdhg.make_data(ops, x_true, synth.unit_noise((N, na, nd), seed + 2))
-    return ops, subsets.BlockOperators(ops, M), d, alpha
+    return ops, subsets.BlockOperators(ops, M, partition), d, alpha
 
 
 def test_subset_bounds():
@@ -28,6 +31,22 @@ def test_subset_bounds():
     assert subsets.subset_bounds(5, 1) == [0, 5]
     with pytest.raises(ValueError):
         subsets.subset_bounds(5, 6)
+
+
+def test_paired_subsets():
+    # every angle with its partner a quarter turn away, each subset two
+    # contiguous ranges, all angles exactly once
+    parts = subsets.paired_subsets(720, 4)
+    assert np.array_equal(parts[0], np.r_[0:90, 360:450])
+    assert np.array_equal(parts[3], np.r_[270:360, 630:720])
+    assert np.array_equal(np.sort(np.concatenate(parts)), np.arange(720))
+    for p in subsets.paired_subsets(18, 3):
+        assert set((p + 9) % 18) == set(p)
+    with pytest.raises(ValueError):
+        subsets.paired_subsets(17, 2)
+    ops = GatedOperators(8, 6, 12, "identity", n_gates=1)
+    with pytest.raises(ValueError):
+        subsets.BlockOperators(ops, 2, [np.array([0, 1, 2]), np.array([2, 3, 4, 5])])
 
 
 def test_one_subset_is_the_gate_algorithm():
@@ -47,8 +66,9 @@ def test_one_subset_is_the_gate_algorithm():
         np.testing.assert_allclose(v, u, rtol=0, atol=1e-13 * max(1.0, np.abs(u).max()))
 
 
-def test_blocks_partition_each_gate_operator():
-    ops, bops, _, _ = small()
+@pytest.mark.parametrize("partition", PARTITIONS)
+def test_blocks_partition_each_gate_operator(partition):
+    ops, bops, _, _ = small(partition=partition)
     x = synth.random_image(ops.n, 3).astype(np.float64)
     y = synth.random_sinograms(1, ops.n_angles, ops.n_det, 4)[0].astype(np.float64)
     for i in range(ops.n_gates):
@@ -66,8 +86,9 @@ def test_blocks_partition_each_gate_operator():
         assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1.0)
 
 
-def test_block_norms_against_svd():
-    ops, bops, _, _ = small(n=10, na=12, nd=16, N=2, M=3)
+@pytest.mark.parametrize("partition", PARTITIONS)
+def test_block_norms_against_svd(partition):
+    ops, bops, _, _ = small(n=10, na=12, nd=16, N=2, M=3, partition=partition)
     n = ops.n
     v0 = synth.random_image(n, 9).astype(np.float64)
     for i in range(ops.n_gates):
@@ -89,8 +110,9 @@ def test_block_norms_against_svd():
         assert max(b2) <= gate2 * (1 + 1e-12) and gate2 <= sum(b2) * (1 + 1e-12)
 
 
-def test_saddle_point_is_a_fixed_point_of_the_block_iteration():
-    ops, bops, d, alpha = small()
+@pytest.mark.parametrize("partition", PARTITIONS)
+def test_saddle_point_is_a_fixed_point_of_the_block_iteration(partition):
+    ops, bops, d, alpha = small(partition=partition)
     xs, ys = spdhg.saddle_point(ops, d, alpha, dense=True)
     zs = sum(ops.At(i, ys[i]) for i in range(ops.n_gates))
     np.testing.assert_allclose(zs, -2 * alpha * xs, rtol=1e-9, atol=1e-11)
@@ -106,8 +128,9 @@ def test_saddle_point_is_a_fixed_point_of_the_block_iteration():
         assert np.abs(a - b).max() <= 1e-9 * max(np.abs(b).max(), 1e-30)
 
 
-def test_invariant_z_is_sum_of_gate_adjoints():
-    ops, bops, d, alpha = small()
+@pytest.mark.parametrize("partition", PARTITIONS)
+def test_invariant_z_is_sum_of_gate_adjoints(partition):
+    ops, bops, d, alpha = small(partition=partition)
     nb = bops.n_blocks
     sig, tau, th, _ = subsets.step_sizes([4.0e2] * nb, alpha, ops.n_gates)
     st = spdhg.State.zeros(ops.n, ops.n_gates, ops.n_angles, ops.n_det)
@@ -131,20 +154,22 @@ def test_step_size_identities():
 
 
 class _MatrixBlocks:
-    """Explicit matrices A_i (rows = data entries) cut into M row ranges."""
+    """Explicit matrices A_i (rows = data entries) cut into M row subsets."""
 
-    def __init__(self, mats, M):
+    def __init__(self, mats, M, partition="contiguous"):
         self.mats = [np.asarray(m, dtype=np.float64) for m in mats]
         self.n_gates = len(mats)
         self.n_subsets = M
         self.n_blocks = self.n_gates * M
-        self.bounds = subsets.subset_bounds(self.mats[0].shape[0], M)
+        rows = self.mats[0].shape[0]
+        make = {"contiguous": subsets.contiguous_subsets, "paired": subsets.paired_subsets}[partition]
+        self.parts = make(rows, M)
 
     def split(self, b):
         return divmod(int(b), self.n_subsets)
 
     def rows(self, s):
-        return slice(self.bounds[s], self.bounds[s + 1])
+        return self.parts[s]
 
     def A(self, b, x):
         i, s = self.split(b)
@@ -159,14 +184,17 @@ class _MatrixBlocks:
         return self.mats[i].T @ yy
 
 
+@pytest.mark.parametrize("partition", PARTITIONS)
 @pytest.mark.parametrize("N,M,alpha,seed", [(1, 3, 0.2, 0), (2, 2, 0.05, 1), (3, 3, 1.0, 2), (2, 4, 0.2, 3)])
-def test_block_second_moment_within_rate(N, M, alpha, seed):
+def test_block_second_moment_within_rate(N, M, alpha, seed, partition):
+    if partition == "paired" and M > 3:
+        pytest.skip("6 data rows pair into at most 3 subsets")
     # exact mean-square contraction of the block iteration (d = 0, error form):
     # T = sum_b p_b M_b (x) M_b; its spectral radius per iteration must not
     # exceed 1 - 2p/(1 + s) of the step-size rule
     rng = np.random.default_rng(seed + 40)
     mats = [rng.standard_normal((6, 4)) for _ in range(N)]
-    bops = _MatrixBlocks(mats, M)
+    bops = _MatrixBlocks(mats, M, partition)
     norms = []
     for b in range(bops.n_blocks):
         i, s = bops.split(b)
@@ -196,7 +224,8 @@ def test_block_second_moment_within_rate(N, M, alpha, seed):
     assert sr ** nb <= subsets.epoch_rate(norms, alpha, N) * (1 + 1e-9)
 
 
-def test_observed_rate_in_paper_regime():
+@pytest.mark.parametrize("partition", PARTITIONS)
+def test_observed_rate_in_paper_regime(partition):
     # kappa = |A|^2 / alpha ~ 70 (Section III); 4 rigid gates x 3 angle subsets
     N, M, n, na, nd = 4, 3, 20, 30, 30
     ops = GatedOperators(n, na, nd, "rigid", synth.rigid_params(N, 11, 8.0, 1.5))
@@ -206,7 +235,7 @@ def test_observed_rate_in_paper_regime():
     normA, _ = spdhg.gate_norm_sq(GatedOperators(n, na, nd, "identity", n_gates=1), 0, v0)
     alpha = normA / 70.0
     xs, ys = spdhg.saddle_point(ops, d, alpha, dense=True)
-    bops = subsets.BlockOperators(ops, M)
+    bops = subsets.BlockOperators(ops, M, partition)
     nb = bops.n_blocks
     bn = [subsets.block_norm_sq(bops, b, v0)[0] for b in range(nb)]
     gn = [spdhg.gate_norm_sq(ops, i, v0)[0] for i in range(N)]
