@@ -116,6 +116,56 @@ def roofs_measurement():
     return out
 
 
+def lds_lanes_measurement():
+    """Which lanes of a wave the LDS serves in one cycle for 16-byte reads,
+    from the lane-pattern probe of libmcr_probes.so: octet i of the wave reads
+    entries 0-7, octet j entries 16-23 (the same banks, other entries), every
+    other octet entries 8-15. The read rate drops against the identity
+    pattern (lane t reads entry t) exactly when octets i and j share a cycle.
+    Then the quarter-turn projection's possible wave layouts, with the
+    entries of lane (bin b, angle slot s) at floor(1.2 b + 0.5 s) (bins about
+    1.2 entries apart, neighbouring angles half an entry)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2410_10503_amd", "libmcr_probes.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2410_10503_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.mcr_probe_lds_pattern.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double)]
+
+    def rate(pattern):
+        arr = (ctypes.c_int * 64)(*pattern)
+        vals = []
+        for _ in range(3):
+            v = ctypes.c_double()
+            rc = lib.mcr_probe_lds_pattern(arr, 2048, 5000, ctypes.byref(v))
+            if rc != 0:
+                raise RuntimeError(f"mcr_probe_lds_pattern failed with status {rc}")
+            vals.append(v.value)
+        return max(vals)
+
+    base = rate(list(range(64)))
+    pairs = {}
+    for i in range(8):
+        for j in range(i + 1, 8):
+            pat = [(t & 7) + (0 if t >> 3 == i else 16 if t >> 3 == j else 8) for t in range(64)]
+            pairs[f"{i},{j}"] = rate(pat) / base
+    layouts = {
+        "32 bins x 2 slots (bins 8k..8k+7 of slot 0, then of slot 1)":
+            [((t & 7) | (((t >> 4) & 3) << 3), (t >> 3) & 1) for t in range(64)],
+        "16 bins x 4 slots": [(t & 15, t >> 4) for t in range(64)],
+        "8 bins x 8 slots (one slot per octet)": [(t & 7, t >> 3) for t in range(64)],
+    }
+    lay = {name: rate([int(1.2 * b + 0.5 * sl) for b, sl in lanes]) / base for name, lanes in layouts.items()}
+    return {
+        "identity_lds_read_tbs": base / 1e12,
+        "octet_pairs_rate_vs_identity": pairs,
+        "octet_pairs_served_together": sorted(k for k, v in pairs.items() if v < 0.85),
+        "projection_wave_layouts_rate_vs_identity": lay,
+        "probe": "2048 blocks x 256 threads x 4 x 5000 reads of 16 B per pattern, best of three",
+    }
+
+
 def measured_roofs():
     """The roofs line of the committed probe summary (profiles/), or None."""
     if not os.path.exists(ROOFS_SUMMARY):
@@ -581,7 +631,7 @@ def dense_registration_measurement(n: int):
     return out
 
 
-def subsets_measurement(h, d, wl, gate_norms, v0, gate_eps: float, M: int = 4, epochs: int = 10):
+def subsets_measurement(h, d, wl, gate_norms, v0, gate_eps: float, variant: dict, M: int = 4, epochs: int = 10):
     """Sampling over gates x angle subsets (the next step named in the
     Conclusions) on the same handle and data, for M contiguous angle subsets
     and for M paired ones (a range of the first half of the angles with its
@@ -591,7 +641,8 @@ def subsets_measurement(h, d, wl, gate_norms, v0, gate_eps: float, M: int = 4, e
     l(kappa, N M) against the gate-only l(kappa, N) at the workload's alpha
     and in the paper's regime (kappa = |A|^2 / alpha = 70), and the
     contraction per second, epochs/s x ln(rate), against the gate epochs'
-    (gate_eps: the gate-only epochs/s of the same handle)."""
+    (gate_eps: the gate-only epochs/s of the same handle, with the projector
+    variants `variant`)."""
     import torch
     import synth
     from paper_2410_10503_amd import step_sizes_blocks
@@ -608,6 +659,7 @@ def subsets_measurement(h, d, wl, gate_norms, v0, gate_eps: float, M: int = 4, e
            "gates": {"epochs_per_s": gate_eps, "rate_per_epoch": r_g, "rate_per_epoch_kappa70": r_g70,
                      "contraction_per_s": gate_eps * math.log(r_g),
                      "contraction_per_s_kappa70": gate_eps * math.log(r_g70)}}
+    base = (variant["fwd"], variant["adj_px"], variant["adj_shares"])
     for partition in ("contiguous", "paired"):
         h.set_subsets(M, paired=partition == "paired")
         bnorms = [h.block_norm_sq(b // M, b % M, v0, max_iter=15, rtol=1e-5)[0] for b in range(nb)]
@@ -618,20 +670,29 @@ def subsets_measurement(h, d, wl, gate_norms, v0, gate_eps: float, M: int = 4, e
         def epoch(e):
             h.spdhg_blocks_iterate(st, d, wl.alpha, sig, tau, th, p, synth.gate_sequence(nb, wl.gate_seed, e))
 
-        epoch(0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for e in range(epochs):
-            epoch(1 + e)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
+        # a block launch holds 1/M of the angles: the adjoint's angle shares
+        # are chosen among a few counts for it (the gate launches keep theirs)
+        times = {}
+        for shares in sorted({base[2], max(1, base[2] // M), max(1, base[2] // 2), 2 * base[2] // M}):
+            h.set_variant(base[0], base[1], min(16, shares))
+            epoch(0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for e in range(epochs):
+                epoch(1 + e)
+            torch.cuda.synchronize()
+            times[min(16, shares)] = time.perf_counter() - t0
+        best = min(times, key=times.get)
+        el = times[best]
         eps = epochs / el
         r70 = l(max(bnorms) / (a70 * N), nb)
         out[partition] = {
-            "epochs_per_s": eps, "us_per_block_iteration": 1e6 * el / (epochs * nb),
+            "epochs_per_s": eps, "us_per_block_iteration": 1e6 * el / (epochs * nb), "adjoint_shares": best,
+            "us_per_block_iteration_by_shares": {str(k): 1e6 * v / (epochs * nb) for k, v in sorted(times.items())},
             "block_norm_sq_range": [min(bnorms), max(bnorms)],
             "rate_per_epoch": rate_b, "rate_per_epoch_kappa70": r70,
             "contraction_per_s": eps * math.log(rate_b), "contraction_per_s_kappa70": eps * math.log(r70)}
+    h.set_variant(*base)
     h.set_subsets(1)
     return out
 
@@ -802,12 +863,14 @@ def main():
     ap.add_argument("--variant", default=None,
                     help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
                          "(counter runs serialise dispatches, which would change the autotuner's choice)")
-    ap.add_argument("--experiment", choices=["paper", "batched", "autograd", "registration", "pdhg", "roofs"],
+    ap.add_argument("--experiment",
+                    choices=["paper", "batched", "autograd", "registration", "pdhg", "roofs", "lds-lanes"],
                     default=None,
                     help="paper: the Section III reproduction (rates vs Theorem 1, MC vs no-MC); batched: the "
                          "64-slice batched workload alone (--steps epochs, --variant applies), for counter "
                          "runs; autograd, registration, pdhg: that measurement of the bench alone; roofs: the "
-                         "LDS, L2 and copy probes; each instead of the bench")
+                         "LDS, L2 and copy probes; lds-lanes: the LDS lane-grouping probe; each instead of the "
+                         "bench")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also copy 256 MiB once (reference dispatch for hardware byte counters)")
     args = ap.parse_args()
@@ -819,9 +882,10 @@ def main():
     if args.experiment == "paper":
         print(json.dumps({"experiment": "section III reproduction", "results": paper_experiment()}), flush=True)
         return
-    if args.experiment in ("autograd", "registration", "pdhg", "roofs"):
+    if args.experiment in ("autograd", "registration", "pdhg", "roofs", "lds-lanes"):
         fn = {"autograd": autograd_measurement, "registration": registration_measurement,
-              "pdhg": pdhg_spdhg_measurement, "roofs": roofs_measurement}[args.experiment]
+              "pdhg": pdhg_spdhg_measurement, "roofs": roofs_measurement,
+              "lds-lanes": lds_lanes_measurement}[args.experiment]
         print(json.dumps({"experiment": args.experiment, "results": fn()}), flush=True)
         return
     if args.experiment == "batched":
@@ -1049,7 +1113,7 @@ def main():
         del a, bcopy
     if not args.no_subsets:
         log("gates x angle subsets ...")
-        out["subsets"] = subsets_measurement(h, d, wl, norms, v0, value)
+        out["subsets"] = subsets_measurement(h, d, wl, norms, v0, value, variant)
         log(f"subsets: {out['subsets']}")
     if not args.no_pdhg:
         log("PDHG vs SPDHG on the 512^2 rigid workload ...")

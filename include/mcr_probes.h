@@ -24,6 +24,14 @@ extern "C" {
  * LDS per second over the whole GPU.                                          */
 int mcr_probe_lds_read(int blocks, int iters, double* bytes_per_s);
 
+/* LDS lane grouping: `blocks` workgroups of 256 threads; lane t of every
+ * wave reads the 16-byte entry pattern[t] (64 host ints, each in [0, 64);
+ * the call copies them) of an LDS array, 4 * iters times, each time shifted
+ * by a multiple of 64 entries. bytes_per_s: bytes read from LDS per second over
+ * the whole GPU; a pattern whose lanes on the same banks at different
+ * entries are served in one cycle reads slower than a conflict-free one.    */
+int mcr_probe_lds_pattern(const int* pattern, int blocks, int iters, double* bytes_per_s);
+
 /* L2-resident global reads: `blocks` workgroups of 256 threads each walk a
  * buffer of buffer_bytes (rounded down to 16 KB; a few MiB fits every XCD's
  * L2) `passes` times with 16-byte loads. bytes_per_s: bytes loaded per

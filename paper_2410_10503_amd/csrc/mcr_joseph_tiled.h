@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 // grid (pieces, 1, G), block 256; piece piece0 + blockIdx.x. wQ holds the
 // planes P_1, P_2, P_3 (plane_stride apart) of each slot, wP is P_0.
 constexpr int kQuCap = 1024;       // staged float4 entries per band
-constexpr int kQuPieceLines = 64;  // target lines per block
+constexpr int kQuPieceLines = 48;  // target lines per block
 
 // Sinogram index of the output of plane m for the ray (k, j), or -1 where
 // it repeats plane m - 2's (the centre bin of an odd detector is its own
@@ -500,12 +500,15 @@ __device__ __forceinline__ void quad_epilogue(const float (&v)[4], int k, int j,
   }
 }
 
-// Thread -> (angle slot kk of 8, bin of 32) of k_joseph_fwd_quad: each group
-// of 16 lanes holds 8 bins of two neighbouring angles, so its 16-byte LDS
-// reads stay within about 12 consecutive entries (no bank conflicts); each
-// wave still holds two angle slots times the 32 bins.
-__device__ __forceinline__ int quad_bin(int tid) { return (tid & 7) | (((tid >> 4) & 3) << 3); }
-__device__ __forceinline__ int quad_slot(int tid) { return ((tid >> 3) & 1) | ((tid >> 6) << 1); }
+// Thread -> (angle slot kk of 8, bin of 32) of k_joseph_fwd_quad: wave w
+// holds bins 8w .. 8w + 7 of all 8 slots, one slot per octet of lanes. A
+// 16-byte LDS read is served 16 lanes per cycle; with 8 neighbouring bins of
+// close angles in every cycle, the entries read lie within a few consecutive
+// ones, and the LDS conflict counters of gfx950 show no bank conflicts for
+// this layout (layouts with 16 or 32 bins of one angle per wave have 2-3
+// conflict cycles per read).
+__device__ __forceinline__ int quad_bin(int tid) { return (tid & 7) | ((tid >> 6) << 3); }
+__device__ __forceinline__ int quad_slot(int tid) { return (tid >> 3) & 7; }
 
 template <int MODE>
 __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const AngleFx* __restrict__ ang,
@@ -612,8 +615,11 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
       lo1 = __builtin_addc(lo1, s1lo, 0u, &c1);
       hi1 = __builtin_addc(hi1, s1hi, c1, &c1);
     };
+    // tap weights times 2^32: w1 = f, w0 = 2^32 - f (one rounding, the
+    // rounding of 1 - f 2^-32 scaled by 2^32), so that every sum is 2^32
+    // times the sum of the unscaled weights, exactly; kFix undoes the scale
     auto mix = [&](const float4& x, const float4& y, float f, float (&a)[4]) {
-      const float w1 = f * kFix, w0 = fmaf(f, -kFix, 1.0f);
+      const float w1 = f, w0 = fmaf(f, -1.0f, 4294967296.0f);
       a[0] = fmaf(w1, y.x, fmaf(w0, x.x, a[0]));
       a[1] = fmaf(w1, y.y, fmaf(w0, x.y, a[1]));
       a[2] = fmaf(w1, y.z, fmaf(w0, x.z, a[2]));
@@ -650,6 +656,11 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
       acc1[m] += b1[m];
     }
     __syncthreads();
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    acc0[m] *= kFix;
+    acc1[m] *= kFix;
   }
   if (un.z > 1) {  // partial sums; k_joseph_fwd_quad_finish adds them
     float* pu = part + blockIdx.z * part_stride + un.w + pc.w * 2048;

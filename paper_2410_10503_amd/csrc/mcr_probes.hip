@@ -70,6 +70,39 @@ __global__ __launch_bounds__(256) void k_probe_l2(const uint4* __restrict__ buf,
   out[blockIdx.x * 256 + tid] = a0 ^ a1;
 }
 
+// Every lane of every wave reads the 16-byte entry pattern[lane] (< 64) of a
+// 512-entry LDS array, shifted each step by a multiple of 64 entries (which
+// keeps each entry's banks). With a pattern that puts two lanes on different
+// entries of the same banks, the read takes longer exactly when the LDS
+// serves those two lanes in the same cycle: the pattern's read rate against
+// a conflict-free one tells which lanes share a cycle.
+__global__ __launch_bounds__(256) void k_probe_lds_pattern(const int* __restrict__ pattern, int iters,
+                                                           unsigned* __restrict__ out) {
+  __shared__ uint4 buf[512];
+  const int tid = threadIdx.x;
+  buf[tid] = make_uint4(tid, blockIdx.x, 1u, 2u);
+  buf[tid + 256] = make_uint4(tid, blockIdx.x, 3u, 4u);
+  __syncthreads();
+  const int e = pattern[tid & 63];
+  unsigned a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  for (int i = 0; i < iters; ++i) {
+    // four independent reads per step, so that the LDS bounds the loop
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint4 v = buf[e + 64 * ((4 * i + k) & 7)];
+      if (k & 1) {
+        a0 = a0 ^ v.x ^ v.y;
+        a1 = a1 ^ v.z ^ v.w;
+      } else {
+        a2 = a2 ^ v.x ^ v.y;
+        a3 = a3 ^ v.z ^ v.w;
+      }
+    }
+    __asm__ volatile("" ::: "memory");
+  }
+  out[blockIdx.x * 256 + tid] = a0 ^ a1 ^ a2 ^ a3;
+}
+
 // Four 16-byte loads in flight per thread, then the four stores.
 __global__ __launch_bounds__(256) void k_probe_copy(const float4* __restrict__ a, float4* __restrict__ b, long n4) {
   const long i0 = (long)blockIdx.x * 1024 + threadIdx.x;
@@ -110,6 +143,38 @@ int mcr_probe_lds_read(int blocks, int iters, double* bytes_per_s) {
   const int err = timed(e0, e1, &ms) || hipGetLastError() != hipSuccess;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  (void)hipFree(out);
+  if (err || ms <= 0.0f) return 3;
+  *bytes_per_s = 16.0 * 4.0 * 256.0 * (double)blocks * (double)iters / (ms * 1e-3);
+  return 0;
+}
+
+int mcr_probe_lds_pattern(const int* pattern, int blocks, int iters, double* bytes_per_s) {
+  if (!pattern || blocks < 1 || iters < 1 || !bytes_per_s) return 1;
+  for (int t = 0; t < 64; ++t)
+    if (pattern[t] < 0 || pattern[t] >= 64) return 1;
+  int* pat = nullptr;
+  unsigned* out = nullptr;
+  if (hipMalloc(&pat, sizeof(int) * 64) != hipSuccess) return 2;
+  if (hipMalloc(&out, sizeof(unsigned) * 256 * (size_t)blocks) != hipSuccess) {
+    (void)hipFree(pat);
+    return 2;
+  }
+  int err = hipMemcpy(pat, pattern, sizeof(int) * 64, hipMemcpyHostToDevice) != hipSuccess;
+  hipEvent_t e0, e1;
+  (void)hipEventCreate(&e0);
+  (void)hipEventCreate(&e1);
+  float ms = 0.0f;
+  if (!err) {
+    hipLaunchKernelGGL(k_probe_lds_pattern, dim3(blocks), dim3(256), 0, nullptr, pat, iters, out);  // warm-up
+    (void)hipEventRecord(e0, nullptr);
+    hipLaunchKernelGGL(k_probe_lds_pattern, dim3(blocks), dim3(256), 0, nullptr, pat, iters, out);
+    (void)hipEventRecord(e1, nullptr);
+    err = timed(e0, e1, &ms) || hipGetLastError() != hipSuccess;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(pat);
   (void)hipFree(out);
   if (err || ms <= 0.0f) return 3;
   *bytes_per_s = 16.0 * 4.0 * 256.0 * (double)blocks * (double)iters / (ms * 1e-3);

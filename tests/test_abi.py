@@ -158,3 +158,30 @@ def test_project_noalloc_validates_before_device_work(lib):
     geo = _lib.Geometry(64, 10, 10)
     assert lib.mcr_project_noalloc(ctypes.byref(geo), None, dummy, None) == _lib.MCR_ERR_ARG
     assert lib.mcr_project_noalloc(ctypes.byref(geo), dummy, None, None) == _lib.MCR_ERR_ARG
+
+
+def test_probe_library_exports_every_declared_function():
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    header = open(os.path.join(root, "include", "mcr_probes.h")).read()
+    declared = re.findall(r"^int (mcr_probe_\w+)\(", header, flags=re.M)
+    assert len(declared) >= 4
+    path = os.path.join(root, "paper_2410_10503_amd", "libmcr_probes.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    assert not [f for f in declared if f not in exported]
+
+
+def test_probe_lds_pattern_validates_before_device_work():
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    probes = ctypes.CDLL(os.path.join(root, "paper_2410_10503_amd", "libmcr_probes.so"))
+    probes.mcr_probe_lds_pattern.argtypes = [ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                             ctypes.POINTER(ctypes.c_double)]
+    v = ctypes.c_double()
+    assert probes.mcr_probe_lds_pattern(None, 1, 1, ctypes.byref(v)) == 1
+    bad = (ctypes.c_int * 64)(*([0] * 63 + [64]))
+    assert probes.mcr_probe_lds_pattern(bad, 1, 1, ctypes.byref(v)) == 1
+    ok = (ctypes.c_int * 64)(*range(64))
+    assert probes.mcr_probe_lds_pattern(ok, 0, 1, ctypes.byref(v)) == 1
