@@ -377,8 +377,13 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           4 = the same over the row-stepping angles and half the bins, the
  *           warp also writing the image's three quarter turns: one crossing
  *           serves rays of angle k and k +- n_angles/2, bins j and
- *           n_det - 1 - j (even n and n_angles only; angle-subset launches
- *           run variant 3);
+ *           n_det - 1 - j (even n and n_angles only; launches over a paired
+ *           angle subset run it per subset, over a contiguous one variant 3),
+ *           5 = variant 4 over the angles of 0 to 45 degrees, the warp also
+ *           writing the transposed image's four quarter turns: one crossing
+ *           serves eight rays, the transpose's ray (k, j) being the image's
+ *           ray (n_angles/2 - k, j) (even n, n_angles a multiple of 4;
+ *           angle-subset launches run variant 4 or 3);
  * adjoint:  adj_px = 0 one thread per pixel, or 1, 2, 4, 8 pixels per thread with
  *           LDS-staged sinogram chunks, the angles split into adj_s (1..16)
  *           shares whose partial images are summed in a fixed order;

@@ -63,6 +63,22 @@ constexpr int kMaxBlurRadius = 96;      // int(3 kMaxBlurSigma + 0.5)
 constexpr int kMaxLevels = 16;          // scale-space levels per dense registration
 
 
+// Work tables of a quarter-turn forward (k_joseph_fwd_quad<MODE, NP>): the
+// line-sheared schedule over its primary angles, XCD-ordered pieces, and per
+// paired angle subset the ranges of pieces and multi-piece units.
+struct QuadTables {
+  int4* chunks = nullptr;
+  int4* pieces = nullptr;
+  int4* units = nullptr;
+  int4* bands = nullptr;
+  float* part = nullptr;  // [slots][part_floats]
+  int* multi = nullptr;
+  int npieces = 0, nmulti = 0;
+  long part_floats = 0;
+  std::vector<int2> sub;        // paired subsets: (first piece, pieces) per subset
+  std::vector<int2> sub_multi;  // paired subsets: (first multi-piece unit entry, entries) per subset
+};
+
 // Per-precision workspace and tables.
 template <typename T>
 struct Work {
@@ -74,7 +90,8 @@ struct Work {
   GatePtrs<T>* ptrs = nullptr;       // [N]
   T* wP = nullptr;                   // [N][padded]
   T* wTP = nullptr;                  // [N][padded]
-  T* wQ = nullptr;                   // [N][3][padded] quarter-turn planes P_1..P_3 (float, even n and n_angles)
+  T* wQ = nullptr;                   // [N][7][padded] planes P_1..P_3 (even n and n_angles), Q_0..Q_3 (and
+                                     // n_angles a multiple of 4) of the quarter-turn forwards (float)
   T* bP = nullptr;                   // [N][padded]
   T* dy = nullptr;                   // [N][sino]
   T* img = nullptr;                  // [n*n] scratch
@@ -143,22 +160,14 @@ struct mcr_handle {
   int shear_npieces = 0, shear_nmulti = 0;
   std::vector<int2> shear_sub;        // per angle subset: (first piece, pieces)
   std::vector<int2> shear_sub_multi;  // per angle subset: (first multi-piece unit entry, entries)
-  // quarter-turn forward (variant 4): the same table format over the primary angles
-  int4* quad_chunks = nullptr;
-  int4* quad_pieces = nullptr;
-  int4* quad_units = nullptr;
-  int4* quad_bands = nullptr;
-  float* quad_part = nullptr;      // [slots][quad_part_floats]
-  int* quad_multi = nullptr;
-  int quad_npieces = 0, quad_nmulti = 0;
-  long quad_part_floats = 0;
+  // quarter-turn forwards: qt[0] four planes (variant 4, also per paired
+  // angle subset), qt[1] eight planes (variant 5, all angles)
+  QuadTables qt[2];
   // angle subsets (mcr_set_subsets, mcr_set_subset_partition): subset s holds
   // the angles of sub[s], one range or (paired) a range and its partner range
   int M = 1;
   bool sub_paired = false;
   std::vector<AngleRanges> sub;
-  std::vector<int2> quad_sub;        // paired subsets: (first quad piece, pieces) per subset
-  std::vector<int2> quad_sub_multi;  // paired subsets: (first multi-piece unit entry, entries) per subset
   long shear_part_floats = 0;
   float* parts = nullptr;          // [kMaxShares][N][n*n] partial backprojections
   // affine registration scratch (allocated on first use)
@@ -593,15 +602,18 @@ Schedule build_shear_schedule(int n, int nd, const std::vector<AngleFx>& af, con
 // holds exactly one primary angle. Bins [0, ceil(n_det / 2)).
 // asub: the subset of every angle, the same for an angle and its partner
 // (paired subsets, or one subset); runs cut by subset, in subset order.
-Schedule build_quad_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& asub, int M) {
+// NP = 8 (n_angles a multiple of 4): the primary angles are k = 0 ..
+// n_angles/4, each also serving the transposed image's rays.
+Schedule build_quad_schedule(int n, int nd, const std::vector<AngleFx>& af, const std::vector<int>& asub, int M,
+                             int NP = 4) {
   const int na = (int)af.size();
   std::vector<int2> runs;
   const int a_end = na / 4 + 1;                  // k <= floor(na / 4)
   const int b_beg = (3 * na + 3) / 4 + (na % 4 == 0 ? 1 : 0);
   if (a_end > 0) runs.push_back(make_int2(0, std::min(a_end, na)));
-  if (b_beg < na) runs.push_back(make_int2(b_beg, na - b_beg));
-  return build_shear_units(n, nd, (nd + 1) / 2, af, cut_runs(runs, asub), asub, M, kQuCap, 8 * 256,
-                           kQuPieceLines);
+  if (NP == 4 && b_beg < na) runs.push_back(make_int2(b_beg, na - b_beg));
+  return build_shear_units(n, nd, (nd + 1) / 2, af, cut_runs(runs, asub), asub, M, kQuCap, 2 * NP * 256,
+                           NP == 8 ? kOcPieceLines : kQuPieceLines);
 }
 
 Schedule build_schedule(int n, int nd, const std::vector<AngleFx>& af, int ka, int jd, int wl) {
@@ -712,27 +724,25 @@ mcr_status upload_shear(mcr_handle* h, const std::vector<AngleFx>& af) {
   return MCR_OK;
 }
 
-// Tables of the quarter-turn forward (float handles with even n and n_angles),
-// over all angles and, with paired subsets, per subset. Rebuilding frees the
-// previous tables (synchronises the stream).
-mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
-  if (h->geo.n % 2 || h->geo.n_angles % 2) return MCR_OK;
-  HIP_OK(hipStreamSynchronize(h->stream));
-  for (void* p : {(void*)h->quad_chunks, (void*)h->quad_pieces, (void*)h->quad_units, (void*)h->quad_bands,
-                  (void*)h->quad_part, (void*)h->quad_multi})
+// Tables of the quarter-turn forwards (float handles with even n and
+// n_angles): four planes over all angles and, with paired subsets, per
+// subset; eight planes over all angles where n_angles is a multiple of 4.
+// Rebuilding frees the previous tables (synchronises the stream).
+mcr_status upload_quad_tables(mcr_handle* h, const std::vector<AngleFx>& af, int which) {
+  QuadTables& qt = h->qt[which];
+  const int NP = which ? 8 : 4;
+  for (void* p : {(void*)qt.chunks, (void*)qt.pieces, (void*)qt.units, (void*)qt.bands, (void*)qt.part,
+                  (void*)qt.multi})
     dfree(h, p);
-  h->quad_chunks = h->quad_pieces = h->quad_units = h->quad_bands = nullptr;
-  h->quad_part = nullptr;
-  h->quad_multi = nullptr;
-  h->quad_npieces = h->quad_nmulti = 0;
-  h->quad_sub.clear();
-  h->quad_sub_multi.clear();
-  // the subsets the quarter-turn kernels can serve: one, or paired ones
-  const bool by_subset = h->M > 1 && h->sub_paired;
+  qt = QuadTables{};
+  if (h->geo.n % 2 || h->geo.n_angles % (2 * NP / 4)) return MCR_OK;
+  // the subsets the four-plane kernels can serve: one, or paired ones; the
+  // eight-plane kernels serve launches over all angles only
+  const bool by_subset = NP == 4 && h->M > 1 && h->sub_paired;
   const std::vector<int> asub = by_subset ? angle_subsets(h) : std::vector<int>(h->geo.n_angles, 0);
   const int M = by_subset ? h->M : 1;
-  Schedule qs = build_quad_schedule(h->geo.n, h->geo.n_det, af, asub, M);
-  if (!qs.ok || qs.pieces.empty()) return MCR_OK;  // variants 4 and 5 unavailable on this geometry
+  Schedule qs = build_quad_schedule(h->geo.n, h->geo.n_det, af, asub, M, NP);
+  if (!qs.ok || qs.pieces.empty()) return MCR_OK;  // this variant is unavailable on this geometry
   // consecutive workgroups go to the 8 XCDs in turn: within each subset, sort
   // the pieces by the middle image row of their lines and cut them into 8
   // runs of equal line counts; run x goes to positions = x (mod 8), so that
@@ -774,34 +784,40 @@ mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
   }
   qs.pieces = ordered;
   const int ns = h->nslots;
-  if (!h->wf.wQ) STATUS_OK(dmalloc(h, (void**)&h->wf.wQ, sizeof(float) * 3 * h->padded * ns));
-  h->quad_part_floats = qs.part_floats;
-  STATUS_OK(dmalloc(h, (void**)&h->quad_chunks, sizeof(int4) * qs.chunks.size()));
-  STATUS_OK(dmalloc(h, (void**)&h->quad_pieces, sizeof(int4) * qs.pieces.size()));
-  STATUS_OK(dmalloc(h, (void**)&h->quad_units, sizeof(int4) * qs.units.size()));
-  STATUS_OK(dmalloc(h, (void**)&h->quad_bands, sizeof(int4) * std::max<size_t>(1, qs.bands.size())));
-  STATUS_OK(dmalloc(h, (void**)&h->quad_part, sizeof(float) * std::max<long>(1, qs.part_floats) * ns));
-  STATUS_OK(dmalloc(h, (void**)&h->quad_multi, sizeof(int) * std::max<size_t>(1, qs.multi.size())));
-  HIP_OK(hipMemcpyAsync(h->quad_chunks, qs.chunks.data(), sizeof(int4) * qs.chunks.size(), hipMemcpyHostToDevice,
+  if (!h->wf.wQ) STATUS_OK(dmalloc(h, (void**)&h->wf.wQ, sizeof(float) * 7 * h->padded * ns));
+  qt.part_floats = qs.part_floats;
+  STATUS_OK(dmalloc(h, (void**)&qt.chunks, sizeof(int4) * qs.chunks.size()));
+  STATUS_OK(dmalloc(h, (void**)&qt.pieces, sizeof(int4) * qs.pieces.size()));
+  STATUS_OK(dmalloc(h, (void**)&qt.units, sizeof(int4) * qs.units.size()));
+  STATUS_OK(dmalloc(h, (void**)&qt.bands, sizeof(int4) * std::max<size_t>(1, qs.bands.size())));
+  STATUS_OK(dmalloc(h, (void**)&qt.part, sizeof(float) * std::max<long>(1, qs.part_floats) * ns));
+  STATUS_OK(dmalloc(h, (void**)&qt.multi, sizeof(int) * std::max<size_t>(1, qs.multi.size())));
+  HIP_OK(hipMemcpyAsync(qt.chunks, qs.chunks.data(), sizeof(int4) * qs.chunks.size(), hipMemcpyHostToDevice,
                         h->stream));
-  HIP_OK(hipMemcpyAsync(h->quad_pieces, qs.pieces.data(), sizeof(int4) * qs.pieces.size(), hipMemcpyHostToDevice,
+  HIP_OK(hipMemcpyAsync(qt.pieces, qs.pieces.data(), sizeof(int4) * qs.pieces.size(), hipMemcpyHostToDevice,
                         h->stream));
-  HIP_OK(hipMemcpyAsync(h->quad_units, qs.units.data(), sizeof(int4) * qs.units.size(), hipMemcpyHostToDevice,
+  HIP_OK(hipMemcpyAsync(qt.units, qs.units.data(), sizeof(int4) * qs.units.size(), hipMemcpyHostToDevice,
                         h->stream));
   if (!qs.bands.empty())
-    HIP_OK(hipMemcpyAsync(h->quad_bands, qs.bands.data(), sizeof(int4) * qs.bands.size(), hipMemcpyHostToDevice,
+    HIP_OK(hipMemcpyAsync(qt.bands, qs.bands.data(), sizeof(int4) * qs.bands.size(), hipMemcpyHostToDevice,
                           h->stream));
   if (!qs.multi.empty())
-    HIP_OK(hipMemcpyAsync(h->quad_multi, qs.multi.data(), sizeof(int) * qs.multi.size(), hipMemcpyHostToDevice,
+    HIP_OK(hipMemcpyAsync(qt.multi, qs.multi.data(), sizeof(int) * qs.multi.size(), hipMemcpyHostToDevice,
                           h->stream));
   HIP_OK(hipStreamSynchronize(h->stream));
-  h->quad_npieces = (int)qs.pieces.size();
-  h->quad_nmulti = (int)qs.multi.size();
+  qt.npieces = (int)qs.pieces.size();
+  qt.nmulti = (int)qs.multi.size();
   if (by_subset) {
-    h->quad_sub = sub_pieces;
-    h->quad_sub_multi = qs.sub_multi;
+    qt.sub = sub_pieces;
+    qt.sub_multi = qs.sub_multi;
   }
   return MCR_OK;
+}
+
+mcr_status upload_quad(mcr_handle* h, const std::vector<AngleFx>& af) {
+  HIP_OK(hipStreamSynchronize(h->stream));
+  STATUS_OK(upload_quad_tables(h, af, 0));
+  return upload_quad_tables(h, af, 1);
 }
 
 // Quarter-turn adjoint codes (adj_px < 0): -2, -4, -8 = 2, 4, 8 pixels per
@@ -922,14 +938,19 @@ mcr_status launch_warp(mcr_handle* h, int gate0, int G, const T* x, const SlotIn
   Timed tm(h, MCR_KERNEL_WARP);
   dim3 grid(cdiv(n, 32), cdiv(n, 32), G), block(32, 32);
   // the quarter-turn planes only when the forward that reads them is
-  // selected; the transposed image only when some launch may use another
-  // forward (angle subsets of less than all angles)
-  const bool quad = std::is_same<T, float>::value && h->tune.fwd == 4 && h->quad_npieces > 0;
+  // selected (three, or seven with the transposes); the transposed image only
+  // when some launch may use another forward (angle subsets of less than all
+  // angles)
+  const int fwd = h->tune.fwd;
+  const bool quad = std::is_same<T, float>::value && ((fwd == 4 && h->qt[0].npieces > 0) ||
+                                                      (fwd == 5 && h->qt[1].npieces > 0));
+  const int nq = quad ? (fwd == 5 ? 7 : 3) : 0;
+  const bool sub_quad = h->sub_paired && !h->qt[0].sub.empty();
   T* wQ = quad ? w.wQ : nullptr;
-  T* wT = quad && (h->M == 1 || (h->sub_paired && !h->quad_sub.empty())) ? nullptr : w.wTP;
+  T* wT = quad && (h->M == 1 || sub_quad) ? nullptr : w.wTP;
   hipLaunchKernelGGL(k_warp_fwd<T>, grid, block, 0, h->stream, geo_of<T>(h), w.motion, gate0,
                      h->fieldP, 2 * h->padded, h->padded, x, x_stride, w.wP, wT, h->padded, slots, wQ,
-                     3 * h->padded, h->padded);
+                     7 * h->padded, h->padded, nq);
   LAUNCH_OK();
   return MCR_OK;
 }
@@ -949,27 +970,36 @@ mcr_status launch_project(mcr_handle* h, int gate0, int G, T* out, long out_stri
   const dim3 block(256);
   if constexpr (std::is_same<T, float>::value) {
     // the chunk tables of variants 1 and 2 cover all angles; those of variant
-    // 4 all angles or each paired subset
+    // 4 all angles or each paired subset, those of variant 5 all angles (a
+    // subset launch of variant 5 runs variant 4, whose planes the warp also
+    // wrote)
     const bool part = subset >= 0 && h->M > 1;
+    const bool sub_quad = h->sub_paired && !h->qt[0].sub.empty();
     int fwd = h->tune.fwd;
-    if (part && !(fwd == 0 || fwd == 3 || (fwd == 4 && h->sub_paired && !h->quad_sub.empty())))
-      fwd = h->shear_npieces > 0 ? 3 : 0;
-    if (fwd == 4 && h->quad_npieces > 0) {
-      const long qp = h->quad_part_floats;
-      const int2 pr = part ? h->quad_sub[subset] : make_int2(0, h->quad_npieces);
-      const int2 mr = part ? h->quad_sub_multi[subset] : make_int2(0, h->quad_nmulti);
-      if (pr.y > 0) {
-        hipLaunchKernelGGL((k_joseph_fwd_quad<MODE>), dim3(pr.y, 1, G), dim3(256), 0, h->stream, geo_of<T>(h),
-                           w.angfx, h->quad_chunks, h->quad_pieces, h->quad_units, h->quad_bands, w.wP, w.wQ,
-                           h->padded, 3 * h->padded, h->padded, out, out_stride, gate0, gs, w.ptrs, slots,
-                           h->quad_part, qp, pr.x);
-        LAUNCH_OK();
-      }
-      if (mr.y > 0) {
-        hipLaunchKernelGGL((k_joseph_fwd_quad_finish<MODE>), dim3(mr.y, 4, G), dim3(256), 0, h->stream,
-                           geo_of<T>(h), w.angfx, h->quad_chunks, h->quad_units, h->quad_multi, h->quad_part, qp,
-                           out, out_stride, gate0, gs, w.ptrs, slots, mr.x);
-      }
+    if (part && fwd == 5) fwd = 4;
+    if (part && !(fwd == 0 || fwd == 3 || (fwd == 4 && sub_quad))) fwd = h->shear_npieces > 0 ? 3 : 0;
+    if ((fwd == 4 && h->qt[0].npieces > 0) || (fwd == 5 && h->qt[1].npieces > 0)) {
+      const QuadTables& qt = h->qt[fwd == 5];
+      const int2 pr = part ? qt.sub[subset] : make_int2(0, qt.npieces);
+      const int2 mr = part ? qt.sub_multi[subset] : make_int2(0, qt.nmulti);
+#define FWDQ(NP)                                                                                                    \
+  do {                                                                                                              \
+    if (pr.y > 0) {                                                                                                 \
+      hipLaunchKernelGGL((k_joseph_fwd_quad<MODE, NP>), dim3(pr.y, 1, G), dim3(256), 0, h->stream, geo_of<T>(h),   \
+                         w.angfx, qt.chunks, qt.pieces, qt.units, qt.bands, w.wP, w.wQ, h->padded, 7 * h->padded,  \
+                         h->padded, out, out_stride, gate0, gs, w.ptrs, slots, qt.part, qt.part_floats, pr.x);      \
+      LAUNCH_OK();                                                                                                  \
+    }                                                                                                               \
+    if (mr.y > 0)                                                                                                   \
+      hipLaunchKernelGGL((k_joseph_fwd_quad_finish<MODE, NP>), dim3(mr.y, NP, G), dim3(256), 0, h->stream,          \
+                         geo_of<T>(h), w.angfx, qt.chunks, qt.units, qt.multi, qt.part, qt.part_floats, out,        \
+                         out_stride, gate0, gs, w.ptrs, slots, mr.x);                                               \
+  } while (0)
+      if (fwd == 5)
+        FWDQ(8);
+      else
+        FWDQ(4);
+#undef FWDQ
     } else if (fwd == 3 && h->shear_npieces > 0) {
       const int2 pr = subset >= 0 ? h->shear_sub[subset] : make_int2(0, h->shear_npieces);
       const int2 mr = subset >= 0 ? h->shear_sub_multi[subset] : make_int2(0, h->shear_nmulti);
@@ -2093,7 +2123,7 @@ mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_moti
   if ((s = mcr_set_motion(h, -1, nullptr)) != MCR_OK) return cleanup(s);
   // defaults before any autotuning: the quarter-turn pair where the geometry
   // has the symmetry, else the line-sheared forward and the tiled adjoint
-  h->tune.fwd = h->quad_npieces > 0 ? 4 : (h->shear_npieces > 0 ? 3 : (h->sched_ok ? 2 : 0));
+  h->tune.fwd = h->qt[0].npieces > 0 ? 4 : (h->shear_npieces > 0 ? 3 : (h->sched_ok ? 2 : 0));
   const bool even = geom->n % 2 == 0 && geom->n_angles % 2 == 0;
   h->tune.adj_px = even ? -4 : 8;
   h->tune.adj_s = even ? 12 : 6;
@@ -2613,7 +2643,7 @@ mcr_status mcr_duality_gap(mcr_handle* h, const mcr_state* st, const void* const
 namespace {
 bool fwd_variant_ok(const mcr_handle* h, int f) {
   return f == 0 || (f == 1 && h->fwd_lds_ok) || (f == 2 && h->sched_ok) || (f == 3 && h->shear_npieces > 0) ||
-         (f == 4 && h->quad_npieces > 0);
+         (f == 4 && h->qt[0].npieces > 0) || (f == 5 && h->qt[1].npieces > 0);
 }
 }  // namespace
 
@@ -2653,7 +2683,7 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
         return 0;
       };
       std::vector<int> fv;
-      for (int f = 4; f >= 0; --f)  // preferred: the newest kernel
+      for (int f = 5; f >= 0; --f)  // preferred: the newest kernel
         if (fwd_variant_ok(h, f)) fv.push_back(f);
       std::vector<float> ft(fv.size(), 1e30f);
       for (int r = 0; r < kRounds; ++r) {
@@ -2704,10 +2734,13 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
 
 mcr_status mcr_set_variant(mcr_handle* h, int32_t fwd, int32_t adj_px, int32_t adj_s) {
   STATUS_OK(check_handle(h));
-  if (fwd < 0 || fwd > 4) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1, 2, 3 or 4", fwd);
+  if (fwd < 0 || fwd > 5) return fail(MCR_ERR_ARG, "forward variant %d must be 0, 1, 2, 3, 4 or 5", fwd);
   if (h->dtype == MCR_F32 && fwd == 4 && (h->geo.n % 2 || h->geo.n_angles % 2))
     return fail(MCR_ERR_STATE, "the quarter-turn forward needs an even n and n_angles: its tables do not fit this "
                                "geometry");
+  if (h->dtype == MCR_F32 && fwd == 5 && (h->geo.n % 2 || h->geo.n_angles % 4))
+    return fail(MCR_ERR_STATE, "the eight-plane forward needs an even n and n_angles a multiple of 4: its tables "
+                               "do not fit this geometry");
   if (h->dtype == MCR_F32 && !fwd_variant_ok(h, fwd))
     return fail(MCR_ERR_STATE, "the tiled forward's band windows do not fit this geometry");
   if (adj_px != 0 && adj_px != 1 && adj_px != 2 && adj_px != 4 && adj_px != 8 && adj_px != -2 && adj_px != -4 &&
@@ -3038,7 +3071,7 @@ mcr_status mcr_project_noalloc(const mcr_geometry* geom, const float* x, float* 
   // transposed); it never reads the field argument of an identity gate
   hipLaunchKernelGGL(k_warp_fwd<float>, dim3(cdiv(n, 32), cdiv(n, 32), 1), dim3(32, 32), 0, s, g,
                      (const GateMotion<float>*)motion, 0, (const float*)wP, 0L, 0L, x, 0L, wP, wTP, 0L,
-                     (const SlotInfo*)nullptr, (float*)nullptr, 0L, 0L);
+                     (const SlotInfo*)nullptr, (float*)nullptr, 0L, 0L, 0);
   LAUNCH_OK();
   hipLaunchKernelGGL((k_joseph_fwd_fx<0>), dim3(cdiv(nd, 256), na, 1), dim3(256), 0, s, g,
                      (const AngleFx*)ang, (const float*)wP, (const float*)wTP, 0L, sino, 0L, 0,

@@ -469,16 +469,28 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 // from the i mod 8-th eighth of the image rows; entries with unit -1 are
 // padding); a tap
 // reads the entries at the crossing's column and the next one and
-// interpolates. Multi-piece units write 8 partial sums per thread (planes x
-// two rays), added by k_joseph_fwd_quad_finish.
+// interpolates. Multi-piece units write 2 NP partial sums per thread (planes
+// x two rays), added by k_joseph_fwd_quad_finish.
+//
+// NP = 8 (n_angles a multiple of 4) adds the transposed image's quarter
+// turns, Q_m[q] = x[T R^m q] with T (r, c) -> (c, r): the ray (k, j) of the
+// transposed image is the ray (n_angles/2 - k, j) of the image (the line
+// x cos t + y sin t = u through transposed points is the line at pi/2 - t),
+// for k <= n_angles/2, and (3 n_angles/2 - k, n_det - 1 - j) above. The
+// primary angles are then k = 0 .. n_angles/4 (0 to 45 degrees) and one
+// crossing serves eight rays; at k = 0 and k = n_angles/4 the transposes
+// repeat planes 0-3 and are not written. A staged entry is two float4 (the
+// second half of the LDS array holds planes 4-7).
 // grid (pieces, 1, G), block 256; piece piece0 + blockIdx.x. wQ holds the
-// planes P_1, P_2, P_3 (plane_stride apart) of each slot, wP is P_0.
-constexpr int kQuCap = 1024;       // staged float4 entries per band
+// planes P_1, P_2, P_3 (and for NP = 8 Q_0 .. Q_3) plane_stride apart for
+// each slot, wP is P_0.
+constexpr int kQuCap = 1024;       // staged entries per band
 constexpr int kQuPieceLines = 48;  // target lines per block
+constexpr int kOcPieceLines = 32;  // the same for NP = 8
 
 // Sinogram index of the output of plane m for the ray (k, j), or -1 where
-// it repeats plane m - 2's (the centre bin of an odd detector is its own
-// reversal, written once).
+// it repeats another plane's (the centre bin of an odd detector is its own
+// reversal, written once; the transposes at k = 0 and k = n_angles/4).
 __device__ __forceinline__ long quad_index(int m, int k, int j, int na, int nd) {
   const int H = na >> 1;
   const int k2 = k < H ? k + H : k - H;
@@ -490,12 +502,22 @@ __device__ __forceinline__ long quad_index(int m, int k, int j, int na, int nd) 
   return m == 2 ? (long)k * nd + jr : (long)k2 * nd + (rev ? j : jr);
 }
 
-template <int MODE>
-__device__ __forceinline__ void quad_epilogue(const float (&v)[4], int k, int j, int na, int nd, float* o, int gate,
+__device__ __forceinline__ long oct_index(int m, int k, int j, int na, int nd) {
+  if (m < 4) return quad_index(m, k, j, na, nd);
+  if (k == 0 || 4 * k == na) return -1;
+  const long t = quad_index(m - 4, k, j, na, nd);
+  if (t < 0) return -1;
+  const int kt = (int)(t / nd), jt = (int)(t - (long)kt * nd);
+  const int H = na >> 1;
+  return kt <= H ? (long)(H - kt) * nd + jt : (long)(na + H - kt) * nd + (nd - 1 - jt);
+}
+
+template <int MODE, int NP>
+__device__ __forceinline__ void quad_epilogue(const float (&v)[NP], int k, int j, int na, int nd, float* o, int gate,
                                               const GateScalars<float>* gs, const GatePtrs<float>* gp) {
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    const long idx = quad_index(m, k, j, na, nd);
+  for (int m = 0; m < NP; ++m) {
+    const long idx = oct_index(m, k, j, na, nd);
     if (idx >= 0) project_epilogue<float, MODE>(v[m], idx, o, gate, gs, gp);
   }
 }
@@ -510,7 +532,7 @@ __device__ __forceinline__ void quad_epilogue(const float (&v)[4], int k, int j,
 __device__ __forceinline__ int quad_bin(int tid) { return (tid & 7) | ((tid >> 6) << 3); }
 __device__ __forceinline__ int quad_slot(int tid) { return (tid >> 3) & 7; }
 
-template <int MODE>
+template <int MODE, int NP>
 __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const AngleFx* __restrict__ ang,
                                                          const int4* __restrict__ chunks,
                                                          const int4* __restrict__ pieces,
@@ -524,8 +546,11 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
                                                          const GatePtrs<float>* __restrict__ gp,
                                                          const SlotInfo* __restrict__ slots,
                                                          float* __restrict__ part, long part_stride, int piece0) {
+  static_assert(NP == 4 || NP == 8, "four or eight planes");
+  constexpr int kH = NP / 4;          // float4 halves per staged entry
   constexpr int kPer = kQuCap / 256;  // staged entries per thread
-  __shared__ float4 st[kQuCap];
+  constexpr int kUnroll = NP == 4 ? 2 : 1;
+  __shared__ float4 st[kQuCap * kH];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -549,26 +574,28 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
   const long long c1j = A1.C0 + (long long)jc * A1.A;
   const int n = g.n, pitch = g.pitch;
   const long origin = (long)kPad * pitch + kPad;
-  const float* p0 = wP + blockIdx.z * w_stride + origin;
-  const float* p1 = wQ + blockIdx.z * q_stride + origin;
-  const float* p2 = p1 + plane_stride;
-  const float* p3 = p2 + plane_stride;
-  float4 pre[kPer];
+  const float* pl[NP];
+  pl[0] = wP + blockIdx.z * w_stride + origin;
+#pragma unroll
+  for (int m = 1; m < NP; ++m) pl[m] = wQ + blockIdx.z * q_stride + origin + (m - 1) * plane_stride;
+  float4 pre[kPer * kH];
   // entry i = l * pitch + q of a band; a wave's 64 entries share one line
   auto fetch = [&](const int4 bd) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int ib = 256 * e + 64 * wv;
       const int l = ib >> bd.w;
-      float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+      for (int h = 0; h < kH; ++h) pre[e * kH + h] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (l < bd.y) {
         const int o = (int)(((long long)l * Bm) >> 32);
         // column clamped into the padded row [-kPad, n + kPad - 1] (zero halo)
         const int c = min(max(bd.z + o + (ib & ((1 << bd.w) - 1)) + lane, -kPad), n + kPad - 1);
         const long q = (long)(bd.x + l) * pitch + c;
-        v = make_float4(p0[q], p1[q], p2[q], p3[q]);
+#pragma unroll
+        for (int h = 0; h < kH; ++h)
+          pre[e * kH + h] = make_float4(pl[4 * h][q], pl[4 * h + 1][q], pl[4 * h + 2][q], pl[4 * h + 3][q]);
       }
-      pre[e] = v;
     }
   };
   unsigned lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
@@ -584,29 +611,39 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
     hi1 = (unsigned)(q1 >> 32);
     s_prev = bd.z;
   }
-  float acc0[4] = {0.0f, 0.0f, 0.0f, 0.0f}, acc1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  float acc0[NP], acc1[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) acc0[m] = acc1[m] = 0.0f;
   for (int b = 0; b < bb.y; ++b) {
     const int4 bd = bands[bb.x + b];
 #pragma unroll
-    for (int e = 0; e < kPer; ++e) st[256 * e + tid] = pre[e];
+    for (int e = 0; e < kPer; ++e)
+#pragma unroll
+      for (int h = 0; h < kH; ++h) st[h * kQuCap + 256 * e + tid] = pre[e * kH + h];
     __syncthreads();
     if (b + 1 < bb.y) fetch(bands[bb.x + b + 1]);
     hi0 += (unsigned)(s_prev - bd.z);
     hi1 += (unsigned)(s_prev - bd.z);
     s_prev = bd.z;
     long long om = 0;
-    float b0[4] = {0.0f, 0.0f, 0.0f, 0.0f}, b1[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    float b0[NP], b1[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) b0[m] = b1[m] = 0.0f;
     const char* base = (const char*)st;
     // the taps of both rays on line l: the entries at the crossing's column
-    // and the next one; so = 16 (l pitch - o_l) is the byte offset of line
-    // l's window (uniform)
-    auto tap = [&](int so, float4& x0, float4& y0, float& f0, float4& x1, float4& y1, float& f1) {
+    // and the next one (each half of the entry); so = 16 (l pitch - o_l) is
+    // the byte offset of line l's window (uniform)
+    auto tap = [&](int so, float4 (&x0)[kH], float4 (&y0)[kH], float& f0, float4 (&x1)[kH], float4 (&y1)[kH],
+                   float& f1) {
       const char* q0 = base + ((hi0 << 4) + (unsigned)so);
       const char* q1 = base + ((hi1 << 4) + (unsigned)so);
-      x0 = *(const float4*)q0;
-      y0 = *(const float4*)(q0 + 16);
-      x1 = *(const float4*)q1;
-      y1 = *(const float4*)(q1 + 16);
+#pragma unroll
+      for (int h = 0; h < kH; ++h) {
+        x0[h] = *(const float4*)(q0 + 16 * kQuCap * h);
+        y0[h] = *(const float4*)(q0 + 16 * kQuCap * h + 16);
+        x1[h] = *(const float4*)(q1 + 16 * kQuCap * h);
+        y1[h] = *(const float4*)(q1 + 16 * kQuCap * h + 16);
+      }
       f0 = float(lo0);
       f1 = float(lo1);
       unsigned c0, c1;
@@ -618,31 +655,34 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
     // tap weights times 2^32: w1 = f, w0 = 2^32 - f (one rounding, the
     // rounding of 1 - f 2^-32 scaled by 2^32), so that every sum is 2^32
     // times the sum of the unscaled weights, exactly; kFix undoes the scale
-    auto mix = [&](const float4& x, const float4& y, float f, float (&a)[4]) {
+    auto mix = [&](const float4 (&x)[kH], const float4 (&y)[kH], float f, float (&a)[NP]) {
       const float w1 = f, w0 = fmaf(f, -1.0f, 4294967296.0f);
-      a[0] = fmaf(w1, y.x, fmaf(w0, x.x, a[0]));
-      a[1] = fmaf(w1, y.y, fmaf(w0, x.y, a[1]));
-      a[2] = fmaf(w1, y.z, fmaf(w0, x.z, a[2]));
-      a[3] = fmaf(w1, y.w, fmaf(w0, x.w, a[3]));
+#pragma unroll
+      for (int h = 0; h < kH; ++h) {
+        a[4 * h + 0] = fmaf(w1, y[h].x, fmaf(w0, x[h].x, a[4 * h + 0]));
+        a[4 * h + 1] = fmaf(w1, y[h].y, fmaf(w0, x[h].y, a[4 * h + 1]));
+        a[4 * h + 2] = fmaf(w1, y[h].z, fmaf(w0, x[h].z, a[4 * h + 2]));
+        a[4 * h + 3] = fmaf(w1, y[h].w, fmaf(w0, x[h].w, a[4 * h + 3]));
+      }
     };
     int l = 0;
-    for (; l + 2 <= bd.y; l += 2) {
-      float4 x0[2], y0[2], x1[2], y1[2];
-      float f0[2], f1[2];
+    for (; l + kUnroll <= bd.y; l += kUnroll) {
+      float4 x0[kUnroll][kH], y0[kUnroll][kH], x1[kUnroll][kH], y1[kUnroll][kH];
+      float f0[kUnroll], f1[kUnroll];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < kUnroll; ++t) {
         const int so = 16 * (((l + t) << bd.w) - (int)(om >> 32));
         om += Bm;
         tap(so, x0[t], y0[t], f0[t], x1[t], y1[t], f1[t]);
       }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < kUnroll; ++t) {
         mix(x0[t], y0[t], f0[t], b0);
         mix(x1[t], y1[t], f1[t], b1);
       }
     }
-    if (l < bd.y) {
-      float4 x0, y0, x1, y1;
+    if (kUnroll > 1 && l < bd.y) {
+      float4 x0[kH], y0[kH], x1[kH], y1[kH];
       float f0, f1;
       const int so = 16 * ((l << bd.w) - (int)(om >> 32));
       om += Bm;
@@ -651,21 +691,21 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
       mix(x1, y1, f1, b1);
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < NP; ++m) {
       acc0[m] += b0[m];
       acc1[m] += b1[m];
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
+  for (int m = 0; m < NP; ++m) {
     acc0[m] *= kFix;
     acc1[m] *= kFix;
   }
   if (un.z > 1) {  // partial sums; k_joseph_fwd_quad_finish adds them
-    float* pu = part + blockIdx.z * part_stride + un.w + pc.w * 2048;
+    float* pu = part + blockIdx.z * part_stride + un.w + pc.w * (NP * 512);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < NP; ++m) {
       pu[m * 512 + tid] = acc0[m];
       pu[m * 512 + 256 + tid] = acc1[m];
     }
@@ -675,19 +715,23 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
   const int gate = slot_gate(slots, gate0);
   float* o = out + blockIdx.z * out_stride;
   if (kk < ch.y) {
-    const float v[4] = {A0.ds * acc0[0], A0.ds * acc0[1], A0.ds * acc0[2], A0.ds * acc0[3]};
-    quad_epilogue<MODE>(v, ch.x + kk, j, g.na, g.nd, o, gate, gs, gp);
+    float v[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) v[m] = A0.ds * acc0[m];
+    quad_epilogue<MODE, NP>(v, ch.x + kk, j, g.na, g.nd, o, gate, gs, gp);
   }
   if (kk + 8 < ch.y) {
-    const float v[4] = {A1.ds * acc1[0], A1.ds * acc1[1], A1.ds * acc1[2], A1.ds * acc1[3]};
-    quad_epilogue<MODE>(v, ch.x + kk + 8, j, g.na, g.nd, o, gate, gs, gp);
+    float v[NP];
+#pragma unroll
+    for (int m = 0; m < NP; ++m) v[m] = A1.ds * acc1[m];
+    quad_epilogue<MODE, NP>(v, ch.x + kk + 8, j, g.na, g.nd, o, gate, gs, gp);
   }
 }
 
 // Sum of the partial sums of the multi-piece units of k_joseph_fwd_quad in
-// piece order, then the outputs; block y handles plane y (four times the
-// blocks of one launch per unit, for latency). grid (count, 4, G), block 256.
-template <int MODE>
+// piece order, then the outputs; block y handles plane y (NP times the
+// blocks of one launch per unit, for latency). grid (count, NP, G), block 256.
+template <int MODE, int NP>
 __global__ __launch_bounds__(256) void k_joseph_fwd_quad_finish(Geo<float> g, const AngleFx* __restrict__ ang,
                                                                 const int4* __restrict__ chunks,
                                                                 const int4* __restrict__ units,
@@ -713,8 +757,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad_finish(Geo<float> g, co
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const bool in = q0 + q < un.z;
-      va[q] = in ? pu[(q0 + q) * 2048 + tid] : 0.0f;
-      vb[q] = in ? pu[(q0 + q) * 2048 + 256 + tid] : 0.0f;
+      va[q] = in ? pu[(q0 + q) * (NP * 512) + tid] : 0.0f;
+      vb[q] = in ? pu[(q0 + q) * (NP * 512) + 256 + tid] : 0.0f;
     }
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -725,11 +769,11 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad_finish(Geo<float> g, co
   const int gate = slot_gate(slots, gate0);
   float* o = out + blockIdx.z * out_stride;
   if (kk < ch.y) {
-    const long idx = quad_index(m, ch.x + kk, j, g.na, g.nd);
+    const long idx = oct_index(m, ch.x + kk, j, g.na, g.nd);
     if (idx >= 0) project_epilogue<float, MODE>(ang[ch.x + kk].ds * a0, idx, o, gate, gs, gp);
   }
   if (kk + 8 < ch.y) {
-    const long idx = quad_index(m, ch.x + kk + 8, j, g.na, g.nd);
+    const long idx = oct_index(m, ch.x + kk + 8, j, g.na, g.nd);
     if (idx >= 0) project_epilogue<float, MODE>(ang[ch.x + kk + 8].ds * a1, idx, o, gate, gs, gp);
   }
 }

@@ -211,7 +211,10 @@ __device__ __forceinline__ void project_epilogue(T s, long idx, T* __restrict__ 
 // One thread per output pixel, 32x32 tiles (1024 threads, so that a 512^2
 // image fills every SIMD with 4 waves); the tile is also written transposed
 // (through LDS) so that the projector reads column-stepping angles with unit
-// stride.
+// stride. With wQ, nq = 3 extra planes P_m[q] = w[R^m q] (m = 1..3,
+// R (r, c) -> (c, n - 1 - r)) or nq = 7, adding Q_m[q] = w[T R^m q]
+// (m = 0..3, T (r, c) -> (c, r)), q_plane apart: pixel s of w goes to
+// R^-m s and R^-m T s.
 // grid (ceil(n/32), ceil(n/32), G), block (32, 32)
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
                                                   const T* __restrict__ x, long x_stride,
                                                   T* __restrict__ wP, T* __restrict__ wTP,
                                                   long w_stride, const SlotInfo* __restrict__ slots,
-                                                  T* __restrict__ wQ, long q_stride, long q_plane) {
+                                                  T* __restrict__ wQ, long q_stride, long q_plane, int nq) {
   __shared__ T tile[32][33];
   const int gate = slot_gate(slots, gate0);
   const int slice = slots ? slots[blockIdx.z].slice : (int)blockIdx.z;
@@ -262,8 +265,16 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
       }
       dst[(long)r * pitch + c] = v;
       // quarter-turn planes P_m[q] = w[R^m q], R (r, c) -> (c, n - 1 - r):
-      // P_2 takes w(r, c) at (n - 1 - r, n - 1 - c)
-      if (wQ) wQ[blockIdx.z * q_stride + origin + q_plane + (long)(n - 1 - r) * pitch + (n - 1 - c)] = v;
+      // P_2 takes w(r, c) at (n - 1 - r, n - 1 - c); Q_1 at (n - 1 - r, c),
+      // Q_3 at (r, n - 1 - c)
+      if (wQ) {
+        T* q = wQ + blockIdx.z * q_stride + origin;
+        q[q_plane + (long)(n - 1 - r) * pitch + (n - 1 - c)] = v;
+        if (nq == 7) {
+          q[4 * q_plane + (long)(n - 1 - r) * pitch + c] = v;
+          q[6 * q_plane + (long)r * pitch + (n - 1 - c)] = v;
+        }
+      }
     }
     tile[threadIdx.y][threadIdx.x] = v;
   }
@@ -278,6 +289,10 @@ __global__ __launch_bounds__(1024) void k_warp_fwd(Geo<T> g, const GateMotion<T>
       T* q = wQ + blockIdx.z * q_stride + origin;
       q[(long)(n - 1 - cc) * pitch + rr] = v;
       q[2 * q_plane + (long)cc * pitch + (n - 1 - rr)] = v;
+      if (nq == 7) {  // Q_0 at (cc, rr), Q_2 at (n - 1 - cc, n - 1 - rr)
+        q[3 * q_plane + (long)cc * pitch + rr] = v;
+        q[5 * q_plane + (long)(n - 1 - cc) * pitch + (n - 1 - rr)] = v;
+      }
     }
   }
 }

@@ -41,7 +41,9 @@ VARIANTS = [(0, 0, 1), (1, 0, 1), (1, 1, 1), (1, 2, 2), (1, 4, 1), (1, 4, 4), (0
             # quarter-turn adjoint (falls back to the tiled one on odd sizes)
             (3, -4, 6), (3, -2, 1), (3, -8, 8), (0, -4, 3), (2, -2, 5),
             # quarter-turn forward (unavailable on odd sizes)
-            (4, -4, 8), (4, 4, 4), (4, 8, 6), (4, -2, 16), (4, -16, 8), (4, -32, 16), (3, -32, 3)]
+            (4, -4, 8), (4, 4, 4), (4, 8, 6), (4, -2, 16), (4, -16, 8), (4, -32, 16), (3, -32, 3),
+            # eight-plane forward (n even, n_angles a multiple of 4)
+            (5, -4, 8), (5, 4, 4), (5, 8, 6), (5, -2, 16)]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -69,7 +71,7 @@ def test_autotune_keeps_parity():
     P = Problem(128, 120, 182, 3, "field")
     h = P.handle(torch.float32)
     choice = h.autotune(1)
-    assert choice["fwd"] in (0, 1, 2, 3, 4) and choice["adj_px"] in (0, 1, 2, 4, 8, -2, -4, -8, -16, -32)
+    assert choice["fwd"] in (0, 1, 2, 3, 4, 5) and choice["adj_px"] in (0, 1, 2, 4, 8, -2, -4, -8, -16, -32)
     assert 1 <= choice["adj_shares"] <= 16
     assert h.autotune(3) is not None
     x = f32(synth.ellipse_phantom(128, 1))
@@ -164,13 +166,17 @@ def test_determinism():
     assert torch.equal(a1, a2) and torch.equal(b1, b2)
 
 
-def test_full_size_field_gate():
+@pytest.mark.parametrize("variant", ["autotune", (4, -4, 12), (5, -4, 12)])
+def test_full_size_field_gate(variant):
     # 512^2, 720 angles x 730 bins, the headline chest phantom and one
     # non-rigid gate, in the configuration the benchmark times (the variants
-    # the autotuner keeps)
+    # the autotuner keeps) and with each quarter-turn forward
     P = Problem(512, 720, 730, 16, "field", phantom="chest")
     h = P.handle(torch.float32)
-    h.autotune(1)
+    if variant == "autotune":
+        h.autotune(1)
+    else:
+        h.set_variant(*variant)
     i = 11
     x = P.x_true
     s = host(h.apply_Ai(i, dev(x, torch.float32)))
@@ -247,7 +253,7 @@ def test_large_and_odd_geometries_sampled(geom):
         b = host(h.backproject(dev(y, torch.float32)))
         for (r, c), ref in zip(pix, prefs):
             assert abs(b[r, c] - ref) <= 1e-5 * np.abs(b).max(), (adj, r, c, b[r, c], ref)
-    for fwd in (0, 1, 2, 3, 4):
+    for fwd in (0, 1, 2, 3, 4, 5):
         try:
             h.set_variant(fwd, 8, 6)
         except McrError as e:
@@ -273,7 +279,8 @@ def test_degenerate_geometries(geom):
         h = P.handle(dtype)
         variants = [None] if dtype == torch.float64 else [(0, 0, 1), (1, 1, 1), (2, 2, 2), (3, 4, 1), (3, 8, 3),
                                                           (3, -4, 1), (3, -2, 3), (3, -8, 8), (4, -4, 1),
-                                                          (4, 8, 2), (4, -16, 1), (4, -32, 5)]
+                                                          (4, 8, 2), (4, -16, 1), (4, -32, 5), (5, -4, 1),
+                                                          (5, 8, 2)]
         for v in variants:
             if v is not None:
                 try:

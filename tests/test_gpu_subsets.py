@@ -63,7 +63,7 @@ def test_fp64_block_iterations_match_oracle(kind, M, partition):
 # (forward variant, adjoint pixels per thread, angle shares)
 @pytest.mark.parametrize("partition", PARTITIONS)
 @pytest.mark.parametrize("variant", [None, (3, 8, 6), (3, 4, 4), (0, 0, 1), (2, 2, 2), (1, 4, 1), (4, -4, 8), (4, -32, 16),
-                                     (4, -4, 1), (0, -8, 3), (4, 8, 6)])
+                                     (4, -4, 1), (0, -8, 3), (4, 8, 6), (5, -4, 8)])
 def test_fp32_block_iterations_match_oracle(variant, partition):
     P = Problem(64, 96, 92, 4, "field", alpha=1e-3)
     M = 3
@@ -86,7 +86,8 @@ def test_one_subset_block_iterations_equal_gate_iterations():
     sig, tau, th, _ = osp.step_sizes_spdhg([2.0 * 96 * 64] * 3, P.alpha, 3)
     p = [1.0 / 3] * 3
     seq = [int(g) for g in synth.gate_sequence(3, 1, 0, length=7)]
-    for dtype, variant in ((torch.float32, (3, 4, 4)), (torch.float32, (4, -4, 8)), (torch.float64, None)):
+    for dtype, variant in ((torch.float32, (3, 4, 4)), (torch.float32, (4, -4, 8)), (torch.float32, (5, -4, 8)),
+                           (torch.float64, None)):
         h = P.handle(dtype)
         if variant is not None:  # with (4, -4, 8) one subset holds all angles: the quarter-turn kernels run
             h.set_variant(*variant)
