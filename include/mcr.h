@@ -396,13 +396,16 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           all angles, else the tiled kernel runs with 2, 4, 8, 8, 8
  *           pixels per thread).
  * A new handle starts with forward 4 where available (else 3, 2, 0) and the
- * adjoint -4 with 12 shares on even n and n_angles (else 8 pixels, 6 shares).
+ * adjoint -4 with 16 shares on even n and n_angles (else 8 pixels, 6 shares).
  * All variants compute the same weights; results differ only by summation
  * order. mcr_autotune times the variants on this geometry with
- * gates_per_launch gates per launch (1 for SPDHG, N for PDHG), keeps the
- * first variant, in a fixed order of preference, that is within 3% of the
- * fastest (remembered per geometry for the life of the process) and returns
- * the choice (output pointers may be NULL). Synchronises the stream.
+ * gates_per_launch gates per launch (1 for SPDHG, N for PDHG; at most the
+ * gates one launch of the handle covers, N or the batch's slots, else
+ * MCR_ERR_ARG), each forward with the warp that writes its planes, keeps the
+ * first variant, in a fixed order of preference (forward 4, 3, 2, 1, 0;
+ * variant 5 only through mcr_set_variant), that is within 3% of the fastest (remembered per geometry and
+ * gates_per_launch for the life of the process) and returns the choice
+ * (output pointers may be NULL). Synchronises the stream.
  * ------------------------------------------------------------------------- */
 mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, int32_t* adj_px,
                         int32_t* adj_s);

@@ -2126,7 +2126,7 @@ mcr_status create_impl(const mcr_geometry* geom, int32_t n_gates, const mcr_moti
   h->tune.fwd = h->qt[0].npieces > 0 ? 4 : (h->shear_npieces > 0 ? 3 : (h->sched_ok ? 2 : 0));
   const bool even = geom->n % 2 == 0 && geom->n_angles % 2 == 0;
   h->tune.adj_px = even ? -4 : 8;
-  h->tune.adj_s = even ? 12 : 6;
+  h->tune.adj_s = even ? 16 : 6;
   *out = h;
   return MCR_OK;
 }
@@ -2649,8 +2649,9 @@ bool fwd_variant_ok(const mcr_handle* h, int f) {
 
 mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, int32_t* adj_px, int32_t* adj_s) {
   STATUS_OK(check_handle(h));
-  if (gates_per_launch < 1 || gates_per_launch > h->N)
-    return fail(MCR_ERR_ARG, "gates_per_launch = %d must be in [1, %d]", gates_per_launch, h->N);
+  if (gates_per_launch < 1 || gates_per_launch > h->nslots)
+    return fail(MCR_ERR_ARG, "gates_per_launch = %d must be in [1, %d] (the gates one launch of this handle covers)",
+                gates_per_launch, h->nslots);
   if (h->dtype == MCR_F32) {
     const auto key = std::make_tuple(h->geo.n, h->geo.n_angles, h->geo.n_det, gates_per_launch);
     bool cached = false;
@@ -2682,15 +2683,26 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
           if (t[i] <= 1.03f * lo) return (int)i;
         return 0;
       };
+      // the forwards in order of preference; each is timed with the warp in
+      // front of it, since the warp writes the planes the forward reads
+      // (three quarter turns for 4, a transposed copy for the others).
+      // Variant 5 is not a candidate: timed this way it won at 256^2 with 40
+      // gates per launch, yet the batched epochs ran 2% slower with it than
+      // with 4 (and 4% at 512^2 with one gate); mcr_set_variant selects it
       std::vector<int> fv;
-      for (int f = 5; f >= 0; --f)  // preferred: the newest kernel
+      for (int f : {4, 3, 2, 1, 0})
         if (fwd_variant_ok(h, f)) fv.push_back(f);
       std::vector<float> ft(fv.size(), 1e30f);
       for (int r = 0; r < kRounds; ++r) {
         for (size_t i = 0; i < fv.size() && st == MCR_OK; ++i) {
           h->tune.fwd = fv[i];
           float ms = 0.0f;
-          st = time_launches(h, [&] { return launch_project<float, 0>(h, 0, G, w.dy, h->sino); }, 5, &ms);
+          st = time_launches(h,
+                             [&] {
+                               STATUS_OK(launch_warp<float>(h, 0, G, w.img));
+                               return launch_project<float, 0>(h, 0, G, w.dy, h->sino);
+                             },
+                             5, &ms);
           if (st == MCR_OK) ft[i] = std::min(ft[i], ms);
         }
       }
@@ -2698,7 +2710,7 @@ mcr_status mcr_autotune(mcr_handle* h, int32_t gates_per_launch, int32_t* fwd, i
       h->tune.fwd = best.fwd;
       // quarter-turn kernels first (tiled ones where the geometry has no
       // quarter-turn symmetry: they then run as their tiled counterparts)
-      const int cand[][2] = {{-4, 8}, {-4, 12}, {-4, 16}, {-16, 8}, {-16, 16}, {-32, 16}, {-8, 16}, {-2, 8},
+      const int cand[][2] = {{-4, 16}, {-4, 8}, {-4, 12}, {-16, 8}, {-16, 16}, {-32, 16}, {-8, 16}, {-2, 8},
                              {8, 6}, {8, 8}, {8, 4}, {4, 4}, {4, 6}, {4, 8}, {4, 2}, {4, 1}, {2, 2}, {2, 1}, {1, 1},
                              {0, 1}};
       const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
