@@ -53,6 +53,34 @@ def test_spdhg_fp64_128_rigid4_20_epochs():
     _compare(gst, ost, 1e-11)
 
 
+def test_spdhg_fp32_strong_magnification_field():
+    # gate 1's field magnifies the image three times about its centre (the
+    # transposed warp's gather window at radius 2-3, window centres three
+    # pixels apart per output pixel); gate 0 is a zero field. 10 SPDHG
+    # epochs in float32 against the oracle.
+    from oracle.operators import GatedOperators
+    n, na, nd = 64, 48, 92
+    P = Problem(n, na, nd, 2, "field", alpha=1e-3)
+    hc = (n - 1) / 2.0
+    yy, xx = np.mgrid[0:n, 0:n].astype(np.float64)
+    f = np.zeros((2, 2, n, n), dtype=np.float32)
+    f[1, 0] = (-(2.0 / 3.0) * (xx - hc)).astype(np.float32)
+    f[1, 1] = (-(2.0 / 3.0) * (yy - hc)).astype(np.float32)
+    P.params = f
+    P.ops = GatedOperators(n, na, nd, "field", f.astype(np.float64), n_gates=2)
+    h = P.handle(torch.float32)
+    assert 2 <= h.info()["window_radius"] <= 3
+    d32 = [dev(v, torch.float32) for v in P.d]
+    sig, tau, th, p = _steps(P)
+    ost = osp.State.zeros(P.n, P.N, P.na, P.nd)
+    gst = h.zero_state()
+    for e in range(10):
+        seq = synth.gate_sequence(P.N, 7, e)
+        ost = osp.spdhg(P.ops, ost, P.d, P.alpha, sig, tau, th, p, seq)
+        h.spdhg_epoch(gst, d32, P.alpha, sig, tau, th, p, seq)
+    _compare(gst, ost, F32_EPOCHS)
+
+
 # (forward, adjoint pixels per thread, angle shares): the handle's default
 # (the quarter-turn pair) and the line-sheared forward with the tiled adjoint
 @pytest.mark.parametrize("variant", [None, (3, 4, 4)])
