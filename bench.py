@@ -858,6 +858,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 64 x 256^2 measurement")
     ap.add_argument("--no-autograd", action="store_true", help="skip the differentiation measurement")
     ap.add_argument("--no-subsets", action="store_true", help="skip the gates x angle-subsets measurement")
+    ap.add_argument("--subsets-m", default="4",
+                    help="comma-separated subset counts M of the subsets measurement (the first is reported "
+                         "as 'subsets', the others as 'subsets_m<M>')")
     ap.add_argument("--no-registration", action="store_true", help="skip the rigid-registration measurement")
     ap.add_argument("--no-pdhg", action="store_true", help="skip the PDHG vs SPDHG measurement")
     ap.add_argument("--variant", default=None,
@@ -1112,9 +1115,11 @@ def main():
         out["copy_probe_bytes"] = a.numel() * 4
         del a, bcopy
     if not args.no_subsets:
-        log("gates x angle subsets ...")
-        out["subsets"] = subsets_measurement(h, d, wl, norms, v0, value, variant)
-        log(f"subsets: {out['subsets']}")
+        for i, M in enumerate(int(m) for m in args.subsets_m.split(",")):
+            key = "subsets" if i == 0 else f"subsets_m{M}"
+            log(f"gates x {M} angle subsets ...")
+            out[key] = subsets_measurement(h, d, wl, norms, v0, value, variant, M=M)
+            log(f"{key}: {out[key]}")
     if not args.no_pdhg:
         log("PDHG vs SPDHG on the 512^2 rigid workload ...")
         out["pdhg_vs_spdhg"] = pdhg_spdhg_measurement()
