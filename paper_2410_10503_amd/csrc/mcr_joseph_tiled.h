@@ -484,6 +484,22 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 // grid (pieces, 1, G), block 256; piece piece0 + blockIdx.x. wQ holds the
 // planes P_1, P_2, P_3 (and for NP = 8 Q_0 .. Q_3) plane_stride apart for
 // each slot, wP is P_0.
+// Byte offset 16 col + so of a staged entry, as one v_lshl_add_u32: written
+// out because the compiler otherwise folds the high word of a 64-bit
+// position and the shift into an align-bit and a mask (two instructions).
+__device__ __forceinline__ unsigned lds_col_offset(unsigned col, int so) {
+  unsigned r;
+  asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(r) : "v"(col), "s"(so));
+  return r;
+}
+
+// 64-bit add as one v_lshl_add_u64: written out so that the compiler keeps
+// one position per ray instead of splitting it into several induction
+// variables of the unrolled line loop.
+__device__ __forceinline__ void add_u64(unsigned long long& a, unsigned long long b) {
+  asm("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(a) : "v"(b));
+}
+
 constexpr int kQuCap = 1024;       // staged entries per band
 constexpr int kQuPieceLines = 48;  // target lines per block
 constexpr int kOcPieceLines = 32;  // the same for NP = 8
@@ -568,8 +584,6 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
   const AngleFx& A1 = ang[ch.x + min(kk + 8, ch.y - 1)];
   const unsigned long long S0 = (unsigned long long)A0.B;
   const unsigned long long S1 = (unsigned long long)A1.B;
-  const unsigned s0lo = (unsigned)S0, s0hi = (unsigned)(S0 >> 32);
-  const unsigned s1lo = (unsigned)S1, s1hi = (unsigned)(S1 >> 32);
   const long long c0j = A0.C0 + (long long)jc * A0.A;
   const long long c1j = A1.C0 + (long long)jc * A1.A;
   const int n = g.n, pitch = g.pitch;
@@ -598,17 +612,16 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
       }
     }
   };
-  unsigned lo0 = 0, hi0 = 0, lo1 = 0, hi1 = 0;
+  // the two rays' 32.32 crossings relative to the band's window start: one
+  // 64-bit add per line (v_lshl_add_u64), the high word the window column,
+  // the low word the fraction
+  unsigned long long p0 = 0, p1 = 0;
   int s_prev = 0;
   if (bb.y > 0) {
     const int4 bd = bands[bb.x];
     fetch(bd);
-    const unsigned long long q0 = (unsigned long long)(c0j + (long long)bd.x * A0.B - ((long long)bd.z << 32));
-    const unsigned long long q1 = (unsigned long long)(c1j + (long long)bd.x * A1.B - ((long long)bd.z << 32));
-    lo0 = (unsigned)q0;
-    hi0 = (unsigned)(q0 >> 32);
-    lo1 = (unsigned)q1;
-    hi1 = (unsigned)(q1 >> 32);
+    p0 = (unsigned long long)(c0j + (long long)bd.x * A0.B - ((long long)bd.z << 32));
+    p1 = (unsigned long long)(c1j + (long long)bd.x * A1.B - ((long long)bd.z << 32));
     s_prev = bd.z;
   }
   float acc0[NP], acc1[NP];
@@ -622,8 +635,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
       for (int h = 0; h < kH; ++h) st[h * kQuCap + 256 * e + tid] = pre[e * kH + h];
     __syncthreads();
     if (b + 1 < bb.y) fetch(bands[bb.x + b + 1]);
-    hi0 += (unsigned)(s_prev - bd.z);
-    hi1 += (unsigned)(s_prev - bd.z);
+    p0 += (unsigned long long)(long long)(s_prev - bd.z) << 32;
+    p1 += (unsigned long long)(long long)(s_prev - bd.z) << 32;
     s_prev = bd.z;
     long long om = 0;
     float b0[NP], b1[NP];
@@ -635,8 +648,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
     // the byte offset of line l's window (uniform)
     auto tap = [&](int so, float4 (&x0)[kH], float4 (&y0)[kH], float& f0, float4 (&x1)[kH], float4 (&y1)[kH],
                    float& f1) {
-      const char* q0 = base + ((hi0 << 4) + (unsigned)so);
-      const char* q1 = base + ((hi1 << 4) + (unsigned)so);
+      const char* q0 = base + lds_col_offset((unsigned)(p0 >> 32), so);
+      const char* q1 = base + lds_col_offset((unsigned)(p1 >> 32), so);
 #pragma unroll
       for (int h = 0; h < kH; ++h) {
         x0[h] = *(const float4*)(q0 + 16 * kQuCap * h);
@@ -644,13 +657,10 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
         x1[h] = *(const float4*)(q1 + 16 * kQuCap * h);
         y1[h] = *(const float4*)(q1 + 16 * kQuCap * h + 16);
       }
-      f0 = float(lo0);
-      f1 = float(lo1);
-      unsigned c0, c1;
-      lo0 = __builtin_addc(lo0, s0lo, 0u, &c0);
-      hi0 = __builtin_addc(hi0, s0hi, c0, &c0);
-      lo1 = __builtin_addc(lo1, s1lo, 0u, &c1);
-      hi1 = __builtin_addc(hi1, s1hi, c1, &c1);
+      f0 = float((unsigned)p0);
+      f1 = float((unsigned)p1);
+      add_u64(p0, S0);
+      add_u64(p1, S1);
     };
     // tap weights times 2^32: w1 = f, w0 = 2^32 - f (one rounding, the
     // rounding of 1 - f 2^-32 scaled by 2^32), so that every sum is 2^32
