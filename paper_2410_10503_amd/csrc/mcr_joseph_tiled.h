@@ -1006,7 +1006,7 @@ constexpr int quad_window() {
 }
 
 template <int PX, int TX, int TY>
-__global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const AngleFx* __restrict__ ang,
+__global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4 ? 4 : 1))) void k_joseph_adj_quad(Geo<float> g, const AngleFx* __restrict__ ang,
                                                              const float* __restrict__ sino, long sino_stride,
                                                              float* __restrict__ out, long out_stride, int padded,
                                                              int S, long part_stride, AngleRanges ar) {
@@ -1018,10 +1018,14 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
   __shared__ float4 sy[KC * kW];
   __shared__ long long s_row[KC][TY];
   __shared__ long long s_col[KC][TX];
-  __shared__ long long s_step[KC];
-  __shared__ float4 s_w[KC];
+  // per angle of a chunk (double-buffered: the next chunk's are written
+  // while the current chunk is computed): bin window start, ray length per
+  // line, the tile corner's window coordinate, its steps along a column and
+  // a row, TX row steps, hat weight constants
   __shared__ int s_jb[2][KC];
   __shared__ float s_ds[2][KC];
+  __shared__ long long s_base[2][KC], s_sr[2][KC], s_sc[2][KC], s_step[2][KC];
+  __shared__ float4 s_w[2][KC];
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const int L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
@@ -1044,7 +1048,8 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int p = 0; p < PX; ++p) acc[m][p] = blk[m][p] = 0.0f;
-  auto window = [&](int k0, int kcn, int& jb, float& ds) {
+  // one thread per angle of the chunk: the window and the table constants
+  auto window = [&](int k0, int kcn, int buf) {
     if (tid < kcn) {
       const AngleFx A = ang[k0 + tid];
       const int pmin = A.rows ? C0 : R0, lmin = A.rows ? R0 : C0;
@@ -1052,8 +1057,18 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
       const long long u00 = A.U0 + (long long)pmin * A.P + (long long)lmin * A.Q;
       const long long up = (long long)pext * A.P, ul = (long long)lext * A.Q;
       const long long umin = min(min(u00, u00 + up), min(u00 + ul, u00 + up + ul));
-      jb = (int)(umin >> 32) - 1;
-      ds = A.ds;
+      const int jb = (int)(umin >> 32) - 1;
+      const long long sc = A.rows ? A.P : A.Q;  // along a row (column step)
+      const long long sr = A.rows ? A.Q : A.P;  // along a column (row step)
+      s_jb[buf][tid] = jb;
+      s_ds[buf][tid] = A.ds;
+      // the tile corner's coordinate in the chunk's staged window (angle
+      // tid's bins start at entry tid kW)
+      s_base[buf][tid] = u00 - ((long long)jb << 32) + ((long long)(tid * kW) << 32);
+      s_sr[buf][tid] = sr;
+      s_sc[buf][tid] = sc;
+      s_step[buf][tid] = TX * sc;
+      s_w[buf][tid] = make_float4(A.na32, A.pa32, A.oma, 0.0f);
     }
   };
   // the four rows of a chunk's entries: angle k forwards and backwards, angle
@@ -1082,15 +1097,9 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
       pre[e] = v;
     }
   };
-  int jb = 0;
-  float ds = 0.0f;
   int k0 = 0, kcn = 0;
   if (vbeg < vend) chunk(vbeg, k0, kcn);
-  window(k0, kcn, jb, ds);
-  if (tid < KC) {
-    s_jb[0][tid] = jb;
-    s_ds[0][tid] = ds;
-  }
+  window(k0, kcn, 0);
   __syncthreads();
   if (vbeg < vend) fetch(k0, kcn, s_jb[0]);
   int cur = 0;
@@ -1110,36 +1119,19 @@ __global__ __launch_bounds__(TX * TY) void k_joseph_adj_quad(Geo<float> g, const
     }
     for (int i = tid; i < kcn * kTab; i += NT) {
       const int kc = i / kTab, e = i % kTab;
-      const AngleFx A = ang[k0 + kc];
-      const long long sc = A.rows ? A.P : A.Q;  // along a row (column step)
-      const long long sr = A.rows ? A.Q : A.P;  // along a column (row step)
-      if (e < TY) {
-        const int pmin = A.rows ? C0 : R0, lmin = A.rows ? R0 : C0;
-        const long long base = A.U0 + (long long)pmin * A.P + (long long)lmin * A.Q -
-                               ((long long)s_jb[cur][kc] << 32) + ((long long)(kc * kW) << 32);
-        s_row[kc][e] = base + (long long)e * sr;
-      } else {
-        s_col[kc][e - TY] = (long long)(e - TY) * sc;
-        if (e == TY) {
-          s_step[kc] = TX * sc;
-          s_w[kc] = make_float4(A.na32, A.pa32, A.oma, 0.0f);
-        }
-      }
+      if (e < TY)
+        s_row[kc][e] = s_base[cur][kc] + (long long)e * s_sr[cur][kc];
+      else
+        s_col[kc][e - TY] = (long long)(e - TY) * s_sc[cur][kc];
     }
-    if (v1 < vend) {
-      window(k1, kcn1, jb, ds);
-      if (tid < KC) {
-        s_jb[cur ^ 1][tid] = jb;
-        s_ds[cur ^ 1][tid] = ds;
-      }
-    }
+    if (v1 < vend) window(k1, kcn1, cur ^ 1);
     __syncthreads();
     if (v1 < vend) fetch(k1, kcn1, s_jb[cur ^ 1]);
 #pragma unroll 2
     for (int kc = 0; kc < kcn; ++kc) {
-      const float4 wc = s_w[kc];
+      const float4 wc = s_w[cur][kc];
       const float na32 = wc.x, pa32 = wc.y, oma = wc.z;
-      const long long st = s_step[kc];
+      const long long st = s_step[cur][kc];
       long long u = s_row[kc][ty] + s_col[kc][tx];
       float4 y0[PX], y1[PX];
       float fl[PX];
