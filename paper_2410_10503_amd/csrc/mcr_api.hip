@@ -829,14 +829,15 @@ int quad_tiled_px(int code) { return code >= -8 ? -code : 8; }
 
 // The quarter-turn adjoint pairs angle k with angle k +- n_angles/2 and a
 // pixel with its quarter turns: it needs an even image size, an even number
-// of angles, and all of them in the launch.
-// All angles, or a subset whose angles come with their partners k +- n_a/2
-// (the paired partition).
+// of angles, and all of them in the launch (all angles, or a subset whose
+// angles come with their partners k +- n_a/2: the paired partition). Its
+// sinogram loads take 32-bit byte offsets within one slot: 4 n_a n_d < 2^31.
 bool quad_ok(const mcr_handle* h, const AngleRanges& ar) {
   const int na = h->geo.n_angles;
   const bool all = ar.ka == 0 && ar.kb == na && ar.kd == ar.kc;
   const bool paired = ar.kc == ar.ka + na / 2 && ar.kd == ar.kb + na / 2;
-  return h->geo.n % 2 == 0 && na % 2 == 0 && (all || paired);
+  const bool fits = 4L * na * h->geo.n_det < (1L << 31);
+  return h->geo.n % 2 == 0 && na % 2 == 0 && fits && (all || paired);
 }
 
 AngleRanges subset_ranges(const mcr_handle* h, int subset) {

@@ -1026,11 +1026,19 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
   __shared__ float s_ds[2][KC];
   __shared__ long long s_base[2][KC], s_sr[2][KC], s_sc[2][KC], s_step[2][KC];
   __shared__ float4 s_w[2][KC];
+  // byte offsets in the slot's sinogram of the four staged rows at the
+  // window's first bin (rows k and k' = k +- na/2, forwards and backwards;
+  // entry q of the window is at offset + q times the row's step) and the
+  // step of row k' (+4 forwards, -4 backwards)
+  __shared__ int4 s_fo[2][KC];
+  __shared__ int s_fs[2][KC];
   const int tid = threadIdx.x;
   const int tx = tid % TX, ty = tid / TX;
   const int L = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-  const int share = L % S, rest = L / S;
-  const int tiles = gridDim.x * gridDim.y, tile = rest % tiles, slot = rest / tiles;
+  // workgroup-uniform (held in scalar registers)
+  const int share = __builtin_amdgcn_readfirstlane(L % S), rest = __builtin_amdgcn_readfirstlane(L / S);
+  const int tiles = gridDim.x * gridDim.y;
+  const int tile = __builtin_amdgcn_readfirstlane(rest % tiles), slot = __builtin_amdgcn_readfirstlane(rest / tiles);
   const int R0 = (tile / gridDim.x) * TY, C0 = (tile % gridDim.x) * (TX * PX);
   const int na = g.na, H = na >> 1, nd = g.nd;
   // the share's angles: launch angles [vbeg, vend) in the order of `ar`
@@ -1069,30 +1077,37 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
       s_sc[buf][tid] = sc;
       s_step[buf][tid] = TX * sc;
       s_w[buf][tid] = make_float4(A.na32, A.pa32, A.oma, 0.0f);
+      // x: k forwards, z: k backwards (bin nd - 1 - j), and for k < na/2
+      // y: k' forwards, w: k' backwards, else the other way round
+      const int k = k0 + tid, k2 = k < H ? k + H : k - H;
+      const int fa = 4 * (k * nd + jb), ra = 4 * (k * nd + nd - 1 - jb);
+      const int fb = 4 * (k2 * nd + jb), rb = 4 * (k2 * nd + nd - 1 - jb);
+      s_fo[buf][tid] = k < H ? make_int4(fa, ra, fb, rb) : make_int4(fa, ra, rb, fb);
+      s_fs[buf][tid] = k < H ? 4 : -4;
     }
   };
   // the four rows of a chunk's entries: angle k forwards and backwards, angle
-  // k +- na/2 forwards and backwards (zero off the detector)
+  // k +- na/2 forwards and backwards (zero off the detector); the offsets
+  // are 32-bit (the host keeps 4 n_angles n_det below 2^31) from the slot's
+  // base, so each load takes one multiply-add
   float4 pre[kPer];
-  auto fetch = [&](int k0, int kcn, const int* jbs) {
+  const char* sb = (const char*)s;
+  auto ld = [&](int off) { return *(const float*)(sb + (unsigned)off); };
+  auto fetch = [&](int kcn, int buf) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int i = tid + e * NT;
       const int kc = i / kW, q = i % kW;
       float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (kc < kcn) {
-        const int k = k0 + kc;
-        const int k2 = k < H ? k + H : k - H;
-        const int ju = jbs[kc] + q, jr = nd - 1 - ju;
-        if ((unsigned)ju < (unsigned)nd) {
-          const float* r1 = s + (long)k * nd;
-          const float* r2 = s + (long)k2 * nd;
-          const float f2 = r2[ju], b2 = r2[jr];
-          v.x = r1[ju];
-          v.z = r1[jr];
-          v.y = k < H ? f2 : b2;
-          v.w = k < H ? b2 : f2;
-        }
+      // kc < KC always: the window start is read for every entry
+      const bool in = (kc < kcn) & ((unsigned)(s_jb[buf][kc] + q) < (unsigned)nd);
+      if (in) {
+        const int4 o = s_fo[buf][kc];
+        const int sq = __mul24(s_fs[buf][kc], q);
+        v.x = ld(o.x + 4 * q);
+        v.z = ld(o.y - 4 * q);
+        v.y = ld(o.z + sq);
+        v.w = ld(o.w - sq);
       }
       pre[e] = v;
     }
@@ -1101,7 +1116,7 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
   if (vbeg < vend) chunk(vbeg, k0, kcn);
   window(k0, kcn, 0);
   __syncthreads();
-  if (vbeg < vend) fetch(k0, kcn, s_jb[0]);
+  if (vbeg < vend) fetch(kcn, 0);
   int cur = 0;
   for (int v0 = vbeg; v0 < vend; v0 += kcn, cur ^= 1) {
     chunk(v0, k0, kcn);
@@ -1117,16 +1132,25 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
         sy[i] = make_float4(pre[e].x * sc, pre[e].y * sc, pre[e].z * sc, pre[e].w * sc);
       }
     }
-    for (int i = tid; i < kcn * kTab; i += NT) {
+    // table entry i = kc kTab + e (a fixed set per thread; the thread index
+    // is made opaque so that the entries' (kc, e) are recomputed per chunk
+    // rather than held in registers across the loop)
+    int tq = tid;
+    asm volatile("" : "+v"(tq));
+#pragma unroll
+    for (int it = 0; it < (KC * kTab + NT - 1) / NT; ++it) {
+      const int i = tq + it * NT;
       const int kc = i / kTab, e = i % kTab;
-      if (e < TY)
-        s_row[kc][e] = s_base[cur][kc] + (long long)e * s_sr[cur][kc];
-      else
-        s_col[kc][e - TY] = (long long)(e - TY) * s_sc[cur][kc];
+      if (kc < kcn) {
+        if (e < TY)
+          s_row[kc][e] = s_base[cur][kc] + s_sr[cur][kc] * e;
+        else
+          s_col[kc][e - TY] = s_sc[cur][kc] * (e - TY);
+      }
     }
     if (v1 < vend) window(k1, kcn1, cur ^ 1);
     __syncthreads();
-    if (v1 < vend) fetch(k1, kcn1, s_jb[cur ^ 1]);
+    if (v1 < vend) fetch(kcn1, cur ^ 1);
 #pragma unroll 2
     for (int kc = 0; kc < kcn; ++kc) {
       const float4 wc = s_w[cur][kc];
