@@ -345,6 +345,7 @@ std::vector<AngleFx> angle_table_fx(int n, int na, int nd) {
     f.U0 = std::llround(-c0 * ia * one);
     f.P = std::llround(ia * one);
     f.Q = std::llround(-beta * ia * one);
+    f.RS = rows ? f.P : f.Q;
     f.a = float(a);
     f.beta = float(beta);
     f.absa = float(std::fabs(a));
@@ -3001,6 +3002,7 @@ __global__ __launch_bounds__(256) void k_noalloc_prepare(int n, int na, int nd, 
     f.U0 = llround(-c0 * ia * one);
     f.P = llround(ia * one);
     f.Q = llround(-beta * ia * one);
+    f.RS = rows ? f.P : f.Q;
     f.a = float(a);
     f.beta = float(beta);
     f.absa = float(fabs(a));

@@ -1021,11 +1021,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
   // per angle of a chunk (double-buffered: the next chunk's are written
   // while the current chunk is computed): bin window start, ray length per
   // line, the tile corner's window coordinate, its steps along a column and
-  // a row, TX row steps, hat weight constants
+  // a row
   __shared__ int s_jb[2][KC];
   __shared__ float s_ds[2][KC];
-  __shared__ long long s_base[2][KC], s_sr[2][KC], s_sc[2][KC], s_step[2][KC];
-  __shared__ float4 s_w[2][KC];
+  __shared__ long long s_base[2][KC], s_sr[2][KC], s_sc[2][KC];
   // byte offsets in the slot's sinogram of the four staged rows at the
   // window's first bin (rows k and k' = k +- na/2, forwards and backwards;
   // entry q of the window is at offset + q times the row's step) and the
@@ -1075,8 +1074,6 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
       s_base[buf][tid] = u00 - ((long long)jb << 32) + ((long long)(tid * kW) << 32);
       s_sr[buf][tid] = sr;
       s_sc[buf][tid] = sc;
-      s_step[buf][tid] = TX * sc;
-      s_w[buf][tid] = make_float4(A.na32, A.pa32, A.oma, 0.0f);
       // x: k forwards, z: k backwards (bin nd - 1 - j), and for k < na/2
       // y: k' forwards, w: k' backwards, else the other way round
       const int k = k0 + tid, k2 = k < H ? k + H : k - H;
@@ -1153,9 +1150,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
     if (v1 < vend) fetch(kcn1, cur ^ 1);
 #pragma unroll 2
     for (int kc = 0; kc < kcn; ++kc) {
-      const float4 wc = s_w[cur][kc];
-      const float na32 = wc.x, pa32 = wc.y, oma = wc.z;
-      const long long st = s_step[cur][kc];
+      // the angle's constants through scalar loads (uniform address)
+      const AngleFx& A = ang[k0 + kc];
+      const float na32 = A.na32, pa32 = A.pa32, oma = A.oma;
+      const long long st = TX * A.RS;
       long long u = s_row[kc][ty] + s_col[kc][tx];
       float4 y0[PX], y1[PX];
       float fl[PX];

@@ -47,6 +47,7 @@ struct AngleT {
 struct AngleFx {
   long long C0, A, B;
   long long U0, P, Q;
+  long long RS;   // U step to the next column of an image row: P when lines are rows, else Q
   float a, beta;  // float copies for the loop bounds
   float absa;     // |a|
   float oma;      // 1 - |a|
