@@ -737,6 +737,8 @@ mcr_status upload_quad_tables(mcr_handle* h, const std::vector<AngleFx>& af, int
     dfree(h, p);
   qt = QuadTables{};
   if (h->geo.n % 2 || h->geo.n_angles % (2 * NP / 4)) return MCR_OK;
+  // the kernels address a padded plane with 32-bit byte offsets
+  if (4L * h->padded >= (1L << 31)) return MCR_OK;
   // the subsets the four-plane kernels can serve: one, or paired ones; the
   // eight-plane kernels serve launches over all angles only
   const bool by_subset = NP == 4 && h->M > 1 && h->sub_paired;

@@ -587,28 +587,32 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_quad(Geo<float> g, const Ang
   const long long c0j = A0.C0 + (long long)jc * A0.A;
   const long long c1j = A1.C0 + (long long)jc * A1.A;
   const int n = g.n, pitch = g.pitch;
-  const long origin = (long)kPad * pitch + kPad;
-  const float* pl[NP];
-  pl[0] = wP + blockIdx.z * w_stride + origin;
+  // plane bases (uniform) and 32-bit byte offsets from them (the host keeps
+  // a padded plane under 2^31 bytes)
+  const char* pl[NP];
+  pl[0] = (const char*)(wP + blockIdx.z * w_stride);
 #pragma unroll
-  for (int m = 1; m < NP; ++m) pl[m] = wQ + blockIdx.z * q_stride + origin + (m - 1) * plane_stride;
+  for (int m = 1; m < NP; ++m) pl[m] = (const char*)(wQ + blockIdx.z * q_stride + (m - 1) * plane_stride);
+  auto ld = [&](int m, unsigned off) { return *(const float*)(pl[m] + off); };
+  // staged entries of lines beyond a band's last are never read: they keep
+  // whatever an earlier band left (zero at first)
   float4 pre[kPer * kH];
+#pragma unroll
+  for (int e = 0; e < kPer * kH; ++e) pre[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
   // entry i = l * pitch + q of a band; a wave's 64 entries share one line
   auto fetch = [&](const int4 bd) {
 #pragma unroll
     for (int e = 0; e < kPer; ++e) {
       const int ib = 256 * e + 64 * wv;
       const int l = ib >> bd.w;
-#pragma unroll
-      for (int h = 0; h < kH; ++h) pre[e * kH + h] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
       if (l < bd.y) {
         const int o = (int)(((long long)l * Bm) >> 32);
         // column clamped into the padded row [-kPad, n + kPad - 1] (zero halo)
         const int c = min(max(bd.z + o + (ib & ((1 << bd.w) - 1)) + lane, -kPad), n + kPad - 1);
-        const long q = (long)(bd.x + l) * pitch + c;
+        const unsigned off = 4u * (unsigned)((bd.x + l + kPad) * pitch + c + kPad);
 #pragma unroll
         for (int h = 0; h < kH; ++h)
-          pre[e * kH + h] = make_float4(pl[4 * h][q], pl[4 * h + 1][q], pl[4 * h + 2][q], pl[4 * h + 3][q]);
+          pre[e * kH + h] = make_float4(ld(4 * h, off), ld(4 * h + 1, off), ld(4 * h + 2, off), ld(4 * h + 3, off));
       }
     }
   };
@@ -1014,7 +1018,6 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
   constexpr int kW = quad_window<PX, TX, TY>();
   constexpr int KC = kQuadKC;
   constexpr int kPer = (KC * kW + NT - 1) / NT;  // staged entries per thread
-  constexpr int kTab = TY + TX;                  // table entries per angle
   __shared__ float4 sy[KC * kW];
   __shared__ long long s_row[KC][TY];
   __shared__ long long s_col[KC][TX];
@@ -1129,21 +1132,23 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
         sy[i] = make_float4(pre[e].x * sc, pre[e].y * sc, pre[e].z * sc, pre[e].w * sc);
       }
     }
-    // table entry i = kc kTab + e (a fixed set per thread; the thread index
-    // is made opaque so that the entries' (kc, e) are recomputed per chunk
-    // rather than held in registers across the loop)
+    // the row table (entry i = kc TY + e) and the column table (i = kc TX
+    // + e), each a fixed set of entries per thread; the thread index is made
+    // opaque so that the entries' (kc, e) are recomputed per chunk rather
+    // than held in registers across the loop
     int tq = tid;
     asm volatile("" : "+v"(tq));
 #pragma unroll
-    for (int it = 0; it < (KC * kTab + NT - 1) / NT; ++it) {
+    for (int it = 0; it < (KC * TY + NT - 1) / NT; ++it) {
       const int i = tq + it * NT;
-      const int kc = i / kTab, e = i % kTab;
-      if (kc < kcn) {
-        if (e < TY)
-          s_row[kc][e] = s_base[cur][kc] + s_sr[cur][kc] * e;
-        else
-          s_col[kc][e - TY] = s_sc[cur][kc] * (e - TY);
-      }
+      const int kc = i / TY, e = i % TY;
+      if (kc < kcn) s_row[kc][e] = s_base[cur][kc] + s_sr[cur][kc] * e;
+    }
+#pragma unroll
+    for (int it = 0; it < (KC * TX + NT - 1) / NT; ++it) {
+      const int i = tq + it * NT;
+      const int kc = i / TX, e = i % TX;
+      if (kc < kcn) s_col[kc][e] = s_sc[cur][kc] * e;
     }
     if (v1 < vend) window(k1, kcn1, cur ^ 1);
     __syncthreads();
