@@ -377,8 +377,9 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           4 = the same over the row-stepping angles and half the bins, the
  *           warp also writing the image's three quarter turns: one crossing
  *           serves rays of angle k and k +- n_angles/2, bins j and
- *           n_det - 1 - j (even n and n_angles only; launches over a paired
- *           angle subset run it per subset, over a contiguous one variant 3),
+ *           n_det - 1 - j (even n and n_angles, and a padded image of under
+ *           2^29 pixels, only; launches over a paired angle subset run it
+ *           per subset, over a contiguous one variant 3),
  *           5 = variant 4 over the angles of 0 to 45 degrees, the warp also
  *           writing the transposed image's four quarter turns: one crossing
  *           serves eight rays, the transpose's ray (k, j) being the image's
@@ -392,8 +393,9 @@ mcr_status mcr_step_sizes_blocks(int32_t n_gates, int32_t n_subsets, const doubl
  *           per thread on 32 x 64 tiles, -32: 4 pixels per thread on 64 x 64
  *           tiles (one detector coordinate serves a pixel of the top-left
  *           quadrant at angle k and its three quarter turns at angles k and
- *           k +- n_angles/2; needs an even n and n_angles and a launch over
- *           all angles, else the tiled kernel runs with 2, 4, 8, 8, 8
+ *           k +- n_angles/2; needs an even n and n_angles,
+ *           4 n_angles n_det < 2^31 and a launch over all angles or a paired
+ *           angle subset, else the tiled kernel runs with 2, 4, 8, 8, 8
  *           pixels per thread).
  * A new handle starts with forward 4 where available (else 3, 2, 0) and the
  * adjoint -4 with 16 shares on even n and n_angles (else 8 pixels, 6 shares).
