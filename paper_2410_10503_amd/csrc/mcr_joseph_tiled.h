@@ -454,6 +454,22 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
     project_epilogue<float, MODE>(ang[ch.x + kk + 8].ds * acc1, (long)(ch.x + kk + 8) * g.nd + j, o, gate, gs, gp);
 }
 
+// Byte offset 16 col + so of a staged entry, as one v_lshl_add_u32: written
+// out because the compiler otherwise folds the high word of a 64-bit
+// position and the shift into an align-bit and a mask (two instructions).
+__device__ __forceinline__ unsigned lds_col_offset(unsigned col, int so) {
+  unsigned r;
+  asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(r) : "v"(col), "s"(so));
+  return r;
+}
+
+// 64-bit add as one v_lshl_add_u64: written out so that the compiler keeps
+// one position per ray instead of splitting it into several induction
+// variables of the unrolled line loop.
+__device__ __forceinline__ void add_u64(unsigned long long& a, unsigned long long b) {
+  asm("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(a) : "v"(b));
+}
+
 // Quarter-turn forward. For a row-stepping (primary) angle k, with k2 = k +
 // n_angles/2 (k < n_angles/2) or k - n_angles/2 (then reversed), the Joseph
 // rays of angle k through the quarter turns of the image give the other
@@ -484,22 +500,6 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 // grid (pieces, 1, G), block 256; piece piece0 + blockIdx.x. wQ holds the
 // planes P_1, P_2, P_3 (and for NP = 8 Q_0 .. Q_3) plane_stride apart for
 // each slot, wP is P_0.
-// Byte offset 16 col + so of a staged entry, as one v_lshl_add_u32: written
-// out because the compiler otherwise folds the high word of a 64-bit
-// position and the shift into an align-bit and a mask (two instructions).
-__device__ __forceinline__ unsigned lds_col_offset(unsigned col, int so) {
-  unsigned r;
-  asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(r) : "v"(col), "s"(so));
-  return r;
-}
-
-// 64-bit add as one v_lshl_add_u64: written out so that the compiler keeps
-// one position per ray instead of splitting it into several induction
-// variables of the unrolled line loop.
-__device__ __forceinline__ void add_u64(unsigned long long& a, unsigned long long b) {
-  asm("v_lshl_add_u64 %0, %0, 0, %1" : "+v"(a) : "v"(b));
-}
-
 constexpr int kQuCap = 1024;       // staged entries per band
 constexpr int kQuPieceLines = 48;  // target lines per block
 constexpr int kOcPieceLines = 32;  // the same for NP = 8
