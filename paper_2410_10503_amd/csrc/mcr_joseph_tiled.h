@@ -1099,8 +1099,10 @@ __global__ __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(PX <= 4
       const int i = tid + e * NT;
       const int kc = i / kW, q = i % kW;
       float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      // kc < KC always: the window start is read for every entry
-      const bool in = (kc < kcn) & ((unsigned)(s_jb[buf][kc] + q) < (unsigned)nd);
+      // the window start is read for every entry (kc < KC unless KC kW is
+      // not a multiple of NT: then clamped into the array)
+      const int kcr = KC * kW % NT == 0 ? kc : min(kc, KC - 1);
+      const bool in = (kc < kcn) & ((unsigned)(s_jb[buf][kcr] + q) < (unsigned)nd);
       if (in) {
         const int4 o = s_fo[buf][kc];
         const int sq = __mul24(s_fs[buf][kc], q);
