@@ -457,6 +457,8 @@ __global__ __launch_bounds__(256) void k_joseph_fwd_shear_finish(Geo<float> g, c
 // Byte offset 16 col + so of a staged entry, as one v_lshl_add_u32: written
 // out because the compiler otherwise folds the high word of a 64-bit
 // position and the shift into an align-bit and a mask (two instructions).
+// so is a scalar operand: the same for the whole wave (the line's offset in
+// the band, which depends on the band and the line counter only).
 __device__ __forceinline__ unsigned lds_col_offset(unsigned col, int so) {
   unsigned r;
   asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(r) : "v"(col), "s"(so));
