@@ -673,7 +673,8 @@ def subsets_measurement(h, d, wl, gate_norms, v0, gate_eps: float, variant: dict
         # a block launch holds 1/M of the angles: the adjoint's angle shares
         # are chosen among a few counts for it (the gate launches keep theirs)
         times = {}
-        for shares in sorted({base[2], max(1, base[2] // M), max(1, base[2] // 2), 2 * base[2] // M}):
+        for shares in sorted({base[2], max(1, base[2] // M), max(1, base[2] // 2), 2 * base[2] // M,
+                              max(1, 3 * base[2] // 4)}):
             h.set_variant(base[0], base[1], min(16, shares))
             epoch(0)
             torch.cuda.synchronize()
