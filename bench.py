@@ -51,13 +51,13 @@ def joseph_nnz(n: int, na: int, nd: int) -> int:
     return total
 
 
-def measured_traffic(dominant: str, variant: dict):
-    """HBM bytes per launch of the dominant kernel class from the committed
-    counter summary (profiles/), or None when that summary holds no line for
-    this class and variant, or the kernel sources have changed since the
-    counters were taken."""
+def summary_fields(name: str, prefix: str, dominant: str, variant: dict):
+    """The key=value fields of the line of a committed counter summary
+    (profiles/<name>) that starts with `prefix` and names this kernel class
+    and projector variant, or None when there is no such line or the kernel
+    sources have changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_joseph_pair_chest512_field16.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     want = {"class": dominant, "fwd": str(variant.get("fwd")),
@@ -67,14 +67,29 @@ def measured_traffic(dominant: str, variant: dict):
         with open(os.path.join(ROOT, "paper_2410_10503_amd", "csrc", src), "rb") as f:
             h.update(f.read())
     for line in open(path):
-        if not line.startswith("traffic: "):
+        if not line.startswith(prefix):
             continue
         fields = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
         if all(fields.get(k) == v for k, v in want.items()):
             if fields.get("sources_sha256_16") != h.hexdigest()[:16]:
                 return None
-            return float(fields["fetch_bytes"]) + float(fields["write_bytes"])
+            return fields
     return None
+
+
+def measured_traffic(dominant: str, variant: dict):
+    """HBM bytes per launch of the dominant kernel class from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE), or None (see summary_fields)."""
+    f = summary_fields("traffic_joseph_pair_chest512_field16.md", "traffic: ", dominant, variant)
+    return None if f is None else float(f["fetch_bytes"]) + float(f["write_bytes"])
+
+
+def measured_valu_issue(dominant: str, variant: dict):
+    """(fraction of the SIMD cycles on which the class's main kernel issued a
+    VALU instruction, its wave-level VALU instructions per launch) from the
+    committed SQ counter summary, or None (see summary_fields)."""
+    f = summary_fields("sq_joseph_pair_chest512_field16.md", "sq: ", dominant, variant)
+    return None if f is None else (float(f["valu_issue"]), float(f["valu_insts"]), f["kernel"])
 
 
 ROOFS_SUMMARY = os.path.join(ROOT, "profiles", "roofs_mi355x.md")
@@ -1056,6 +1071,12 @@ def main():
         roof["frac_without_packed_fp32"] = roof["achieved"] / (PEAK_FP32_TFLOPS / 2)
     roof["traffic"] = measured_traffic(dom, variant)
     roof["kernel"] = dom
+    if roof["bound"] == "alu":
+        # what binds the class's main kernel: the fraction of the SIMD cycles
+        # that issue a VALU instruction (SQ counters of the committed summary)
+        vi = measured_valu_issue(dom, variant)
+        if vi is not None:
+            roof["valu_issue_frac"], roof["valu_insts_per_launch"], roof["valu_kernel"] = vi
     roof["avg_launch_us"] = avg_s * 1e6
     roof["hbm_gbs_algorithmic"] = bytes_ / avg_s / 1e9
     roof["nnz_per_launch"] = nnz

@@ -32,6 +32,15 @@ def test_measured_traffic_follows_the_committed_summary():
     assert t > 0
 
 
+def test_measured_valu_issue_follows_the_committed_summary():
+    assert bench.measured_valu_issue("project", {"fwd": 3, "adj_px": 8, "adj_shares": 6}) is None
+    v = bench.measured_valu_issue("backproject", {"fwd": 4, "adj_px": -4, "adj_shares": 16})
+    if v is None:
+        pytest.skip("the kernel sources changed since the counter summary was taken")
+    frac, insts, kernel = v
+    assert 0.0 < frac <= 1.0 and insts > 0 and "adj_quad" in kernel
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, cwd=ROOT, timeout=120)
