@@ -441,7 +441,7 @@ mcr_status mcr_profile_read(mcr_handle* h, double* total_ms, int64_t* launches);
  * float [n][n]; sino: device float [n_angles][n_det] (out); both caller-owned
  * and on the current device. stream: hipStream_t (NULL = the null stream);
  * the call is asynchronous on it. The work runs in a fixed scratch array of
- * the library (8.4 MiB of device memory per GPU, held from the first call
+ * the library (8.5 MiB of device memory per GPU, held from the first call
  * on that GPU until the process ends): no hipMalloc, hipFree or other
  * allocation happens in the call. Every call on one GPU shares that array, so
  * calls that overlap on one GPU (different streams or host threads without
