@@ -713,6 +713,52 @@ def subsets_measurement(h, d, wl, gate_norms, v0, gate_eps: float, variant: dict
     return out
 
 
+def subsets_block_measurement(M: int, epochs: int, variant=None):
+    """The block iterations of M paired angle subsets alone, on the headline
+    workload (for kernel traces of the subset launches, which the bench's
+    subsets measurement mixes with the gate epochs): block norms by power
+    iteration, step sizes, one untimed epoch of N M block iterations, then
+    `epochs` timed ones, with the projector variants given (else autotuned
+    for one gate per launch)."""
+    import torch
+    import synth
+    from paper_2410_10503_amd import Handle, step_sizes_blocks
+    wl = synth.WORKLOADS["chest512_field16"]
+    dev = torch.device("cuda:0")
+    n, na, nd, N = wl.n, wl.n_angles, wl.n_det, wl.n_gates
+    fields = wl.fields()
+    h = Handle(n, na, nd, [("field", torch.from_numpy(fields[i]).to(dev)) for i in range(N)],
+               dtype=torch.float32, device=dev)
+    xg = torch.from_numpy(wl.image()).to(dev)
+    d = [h.apply_Ai(i, xg) for i in range(N)]
+    if variant:
+        h.set_variant(variant["fwd"], variant["adj_px"], variant["adj_shares"])
+    else:
+        variant = h.autotune(1)
+    h.set_subsets(M, paired=True)
+    nb = N * M
+    v0 = torch.from_numpy(synth.random_image(n, 17).astype(np.float64)).to(dev)
+    bnorms = [h.block_norm_sq(b // M, b % M, v0, max_iter=15, rtol=1e-5)[0] for b in range(nb)]
+    sig, tau, th, rate = step_sizes_blocks(bnorms, wl.alpha, N, M)
+    p = [1.0 / nb] * nb
+    st = h.zero_state()
+
+    def epoch(e):
+        h.spdhg_blocks_iterate(st, d, wl.alpha, sig, tau, th, p, synth.gate_sequence(nb, wl.gate_seed, e))
+
+    epoch(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e in range(epochs):
+        epoch(1 + e)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    h.close()
+    return {"workload": f"{wl.name}, {M} paired angle subsets ({nb} blocks), epoch = {nb} block iterations",
+            "projector_variant": variant, "epochs": epochs, "epochs_per_s": epochs / el,
+            "us_per_block_iteration": 1e6 * el / (epochs * nb), "rate_per_epoch": rate}
+
+
 def paper_experiment(epochs: int = 30, seeds: int = 8, reference=None):
     """Section III on the GPU in FP64: l2^2-distance to the saddle point per
     epoch for PDHG and SPDHG (mean over seeds) against Theorem 1's rates, in
@@ -883,11 +929,13 @@ def main():
                     help="fwd,adj_px,adj_shares: use these projector variants instead of autotuning "
                          "(counter runs serialise dispatches, which would change the autotuner's choice)")
     ap.add_argument("--experiment",
-                    choices=["paper", "batched", "autograd", "registration", "pdhg", "roofs", "lds-lanes"],
+                    choices=["paper", "batched", "subsets", "autograd", "registration", "pdhg", "roofs",
+                             "lds-lanes"],
                     default=None,
                     help="paper: the Section III reproduction (rates vs Theorem 1, MC vs no-MC); batched: the "
                          "64-slice batched workload alone (--steps epochs, --variant applies), for counter "
-                         "runs; autograd, registration, pdhg: that measurement of the bench alone; roofs: the "
+                         "runs; subsets: the block iterations of the first --subsets-m paired subsets alone "
+                         "(--steps epochs, --variant applies), for kernel traces; autograd, registration, pdhg: that measurement of the bench alone; roofs: the "
                          "LDS, L2 and copy probes; lds-lanes: the LDS lane-grouping probe; each instead of the "
                          "bench")
     ap.add_argument("--copy-probe", action="store_true",
@@ -906,6 +954,14 @@ def main():
               "pdhg": pdhg_spdhg_measurement, "roofs": roofs_measurement,
               "lds-lanes": lds_lanes_measurement}[args.experiment]
         print(json.dumps({"experiment": args.experiment, "results": fn()}), flush=True)
+        return
+    if args.experiment == "subsets":
+        v = None
+        if args.variant:
+            f, px, sh = (int(t) for t in args.variant.split(","))
+            v = {"fwd": f, "adj_px": px, "adj_shares": sh}
+        res = subsets_block_measurement(int(args.subsets_m.split(",")[0]), args.steps, variant=v)
+        print(json.dumps({"experiment": "subsets", "results": res}), flush=True)
         return
     if args.experiment == "batched":
         v = None
